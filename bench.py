@@ -1,0 +1,212 @@
+#!/usr/bin/env python3
+"""Benchmark of the MRG32k3a stream library on one MI355X.
+
+Headline workload (plain bulk fill): 2^20 streams spaced 2^127 apart from a
+64-bit master seed, 4096 uint32 outputs per stream per step, stream-major
+(a [2^20, 4096] array, 16 GiB), the stream states resident on the device and
+advanced by every step.  One step = one pass of the generation path over the
+whole batch.  The output buffer is allocated before timing.
+
+Printed: ONE JSON line with the headline value plus
+  roofline      -- HBM-write roofline of the fill kernel (bytes it must write
+                   per launch / its average duration measured with HIP events
+                   on the launch stream), and the counter-measured traffic;
+  cpu_baseline  -- the CPU oracle (plain single-threaded C) timed on a bounded
+                   sample of the same workload;
+  extra         -- FP32 and interleaved fills, jump and create timings.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--engine 0|1]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
+METRIC = "uint32 Gsamples/s (% HBM write roofline), batched vs plain; p50/p99 latency"
+# HBM bytes per launch read by rocprofv3 (FETCH_SIZE + WRITE_SIZE, scaled by a
+# copy-kernel calibration); None until measured for the current kernel.
+COUNTER_TRAFFIC = None
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--engine", type=int, default=None, help="0 integer, 1 binary64")
+    ap.add_argument("--tile-bytes", type=int, default=None)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--quick", action="store_true", help="headline only (for profiling)")
+    return ap.parse_args()
+
+
+def timed(fn, steps, warmup, stream):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    t0 = time.perf_counter()
+    ev[0].record(stream)
+    for i in range(steps):
+        fn()
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    per = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    return per, wall
+
+
+def cpu_baseline(streams: int, n: int):
+    import numpy as np
+    import oracle
+    from paper_1412_8266_amd import workloads as wl
+    base = oracle.seed_from_master(wl.MASTER_SEED)
+    st = oracle.streams(base, 0, streams)
+    t0 = time.perf_counter()
+    out, _ = oracle.fill(st, n, oracle.U32)
+    dt = time.perf_counter() - t0
+    del out
+    return {
+        "value": streams * n / dt / 1e9,
+        "unit": "Gsamples/s",
+        "cores": 1,
+        "kind": "oracle",
+        "sample": "first %d of the 2^20 streams x %d uint32 outputs (%d samples), stream-major; "
+                  "single-threaded C oracle, fill only (start states precomputed)"
+                  % (streams, n, streams * n),
+        "seconds": dt,
+        "cpu": platform.processor() or platform.machine(),
+        "host_cpus": os.cpu_count(),
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: the stream library has no multi-GPU path "
+              "(streams shard by index with no exchange; see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1412_8266_amd as mg
+    from paper_1412_8266_amd import workloads as wl
+
+    if args.engine is not None:
+        mg.mrg_config_set("engine", args.engine)
+    if args.tile_bytes is not None:
+        mg.mrg_config_set("tile_bytes", args.tile_bytes)
+    engine = mg.mrg_config_get("engine")
+    tile = mg.mrg_config_get("tile_bytes")
+    stream = torch.cuda.current_stream()
+
+    S, n = wl.C2_STREAMS, wl.C2_N
+    samples = S * n
+    print("[bench] creating %d streams" % S, file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    ss = mg.StreamSet(S, master_seed=wl.MASTER_SEED)
+    torch.cuda.synchronize()
+    create_s = time.perf_counter() - t0
+    out = torch.empty((S, n), dtype=torch.uint32, device="cuda")
+    ptr = out.data_ptr()
+
+    def step_u32():
+        ss.fill_ptr(n, mg.U32, mg.STREAM_MAJOR, ptr)
+
+    print("[bench] timing u32 fill: %d warmup + %d steps" % (args.warmup, args.steps),
+          file=sys.stderr, flush=True)
+    per, wall = timed(step_u32, args.steps, args.warmup, stream)
+    ms = sum(per) / len(per)
+    value = samples / (ms * 1e-3) / 1e9
+    alg_bytes = samples * 4 + S * 24 * 2  # outputs + state read and write-back
+    achieved = alg_bytes / (ms * 1e-3) / 1e9
+
+    res = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "Gsamples/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {
+            "workload": "plain bulk fill: 2^20 MRG32k3a streams x 4096 uint32 outputs, "
+                        "stream-major, streams spaced 2^127 from a 64-bit master seed",
+            "streams": S,
+            "n_per_stream": n,
+            "layout": "stream_major",
+            "master_seed": hex(wl.MASTER_SEED),
+            "engine": "binary64" if engine == 1 else "int32",
+            "tile_bytes": tile,
+        },
+        "roofline": {
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": COUNTER_TRAFFIC,
+            "kernel": "fill_sm_kernel<u32>",
+            "alg_bytes_per_launch": alg_bytes,
+            "avg_launch_ms": round(ms, 4),
+        },
+        "wall_s_timed": round(wall, 3),
+    }
+
+    extra = {"create_streams_ms": round(create_s * 1e3, 2)}
+    if not args.quick:
+        # FP32 fill (same launch, 4-byte floats)
+        outf = out.view(torch.float32)
+        per_f, _ = timed(lambda: ss.fill_ptr(n, mg.F32, mg.STREAM_MAJOR, outf.data_ptr()),
+                         args.steps, 1, stream)
+        msf = sum(per_f) / len(per_f)
+        extra["f32_fill"] = {"Gsamples_s": round(samples / msf / 1e6, 2), "ms": round(msf, 4),
+                             "hbm_frac": round((samples * 4 + S * 48) / msf / 1e6 / HBM_PEAK_GBS, 4)}
+        per_i, _ = timed(lambda: ss.fill_ptr(n, mg.U32, mg.INTERLEAVED, ptr), args.steps, 1, stream)
+        msi = sum(per_i) / len(per_i)
+        extra["u32_interleaved"] = {"Gsamples_s": round(samples / msi / 1e6, 2),
+                                    "ms": round(msi, 4)}
+        del outf
+        del out
+        # FP64 fill: half the streams so the output stays at 16 GiB
+        outd = torch.empty((S // 2, n), dtype=torch.float64, device="cuda")
+        per_d, _ = timed(lambda: ss.fill_ptr(n, mg.F64, mg.STREAM_MAJOR, outd.data_ptr(),
+                                             count=S // 2), args.steps, 1, stream)
+        msd = sum(per_d) / len(per_d)
+        extra["f64_fill_half_streams"] = {"Gsamples_s": round(samples / 2 / msd / 1e6, 2),
+                                          "ms": round(msd, 4),
+                                          "hbm_frac": round(samples * 4 / msd / 1e6 / HBM_PEAK_GBS, 4)}
+        del outd
+        # jump: 2^16 streams by random 64-bit offsets + 2^76 (per-stream tables)
+        import numpy as np
+        ss3 = mg.StreamSet(wl.C3_STREAMS, master_seed=wl.MASTER_SEED)
+        ex = torch.from_numpy(wl.c3_exponents(wl.c3_offsets()).view(np.int64)).cuda()
+        per_j, _ = timed(lambda: ss3.jump(ex), 10, 1, stream)
+        extra["jump_2^16_streams_ms"] = round(sum(per_j) / len(per_j), 4)
+        ss3.close()
+    res["extra"] = extra
+    ss.close()
+    torch.cuda.synchronize()
+
+    if not args.no_cpu and not args.quick:
+        print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline(1 << 16, n)
+    else:
+        res["cpu_baseline"] = None
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,196 @@
+/*
+ * mrg32k3a_gpu.h -- C ABI of the MI355X (gfx950) MRG32k3a stream library.
+ *
+ * The library generates uniform random numbers in bulk from many independent,
+ * reproducible streams of L'Ecuyer's combined multiple-recursive generator
+ * MRG32k3a, placed by jump-ahead as in Passerat-Palmbach & Hill, HPCS 2012:
+ *   sec. 4.1  MRG32k3a keeps 6 integers of state; its sequence is split into
+ *             2^64 adjacent streams of 2^127 numbers, each divided into
+ *             substreams of 2^76 numbers, one stream or substream per thread;
+ *   sec. 2.3  sequence splitting needs a jump ahead; random spacing seeds the
+ *             generator from different random states;
+ *   sec. 5.1  a host-side initialisation allocates the device structures and
+ *             prepares every thread's starting state before any kernel runs;
+ *   sec. 5.2  on the device each thread draws the next number of its own
+ *             stream (Listing 1 stores one float per thread).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Return value: MRG_OK (0) or a negative mrg_status.  A validation error
+ *   returns before anything is enqueued; the text of the last error of the
+ *   calling thread is available from mrg_last_error().
+ * - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *   Every call that touches device memory is enqueued on it and is
+ *   asynchronous unless stated otherwise.  Kernel faults surface as MRG_EHIP
+ *   on a later call or at synchronisation.
+ * - Device pointers (d_*) are device memory of the current HIP device, owned
+ *   by the caller.  Host pointers (h_*) are ordinary host memory.
+ * - A stream set and everything it owns live on the device that was current
+ *   when it was created; calls on it must be made with that device current.
+ * - States are 6 uint32 words per stream, oldest first in each component:
+ *   (x1[n-3], x1[n-2], x1[n-1], x2[n-3], x2[n-2], x2[n-1]), with x1 words in
+ *   [0, m1), x2 words in [0, m2), m1 = 2^32-209, m2 = 2^32-22853, and
+ *   neither triple all zero.
+ * - Output number k of a stream (k = 0, 1, ...) is the combined value after
+ *   k+1 steps of its recurrence: z = (x1 - x2) mod m1, reported as m1 when 0,
+ *   so uint32 outputs lie in [1, m1] (values above m1 never occur).
+ *   FP64: z * NORM with NORM the double nearest 1/(m1+1) (one rounding).
+ *   FP32: (2*((z-1) >> 9) + 1) * 2^-24 (exact).  Both lie in (0, 1) and are
+ *   derived from the same integers, so all three dtypes carry one sequence.
+ * - This library is not thread-safe per stream set: concurrent calls on one
+ *   stream set must be ordered by the caller (e.g. by using one HIP stream).
+ */
+#ifndef MRG32K3A_GPU_H
+#define MRG32K3A_GPU_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t mrg_status;
+#define MRG_OK      0
+#define MRG_EINVAL (-1)  /* bad argument: null pointer, invalid seed/state, bad dtype */
+#define MRG_ENOMEM (-2)  /* device or host allocation failed */
+#define MRG_EHIP   (-3)  /* a HIP runtime call failed (see mrg_last_error) */
+#define MRG_ERANGE (-4)  /* stream range or size outside the stream set / limits */
+#define MRG_ENODEV (-5)  /* no usable HIP device */
+
+typedef enum { MRG_U32 = 0, MRG_F32 = 1, MRG_F64 = 2 } mrg_dtype;
+typedef enum { MRG_STREAM_MAJOR = 0, MRG_INTERLEAVED = 1 } mrg_layout;
+
+/* Opaque stream set: `n_streams` consecutive streams of one generator,
+ * global stream indices [first_stream, first_stream + n_streams), with their
+ * current states held on the device (6 planes of n_streams uint32). */
+typedef struct mrg_streamset_s *mrg_streamset;
+
+/* ---------------------------------------------------------------------- */
+/* Stream sets (sec. 5.1 host initialisation; sec. 4.1 streams)            */
+/* ---------------------------------------------------------------------- */
+
+/* Create a stream set whose stream g (global index) starts at
+ * A^(g * 2^127) * seed6, i.e. stream 0 is seed6 itself and streams are 2^127
+ * outputs apart (sec. 4.1).  seed6 (host, 6 words) must be a valid state.
+ * n_streams >= 1; first_stream + n_streams must not exceed 2^64.
+ * Enqueues the start-state computation on `stream`; the set is usable on
+ * that stream immediately.  *out receives the handle (caller owns it; free
+ * with mrg_streamset_destroy).  Errors: MRG_EINVAL (null, invalid seed),
+ * MRG_ERANGE (n_streams == 0 or index overflow), MRG_ENOMEM, MRG_EHIP. */
+mrg_status mrg_streamset_create(mrg_streamset *out, uint64_t n_streams,
+                                uint64_t first_stream, const uint32_t seed6[6],
+                                void *stream);
+
+/* As mrg_streamset_create, with the base state expanded from a 64-bit
+ * master seed (random spacing, sec. 2.3) by mrg_seed_from_master. */
+mrg_status mrg_streamset_create_seed64(mrg_streamset *out, uint64_t n_streams,
+                                       uint64_t first_stream, uint64_t master_seed,
+                                       void *stream);
+
+/* Release the stream set and its device memory (sec. 5.1 release()).
+ * Synchronises the device work the library enqueued on the set first.
+ * NULL is accepted and ignored. */
+mrg_status mrg_streamset_destroy(mrg_streamset ss);
+
+/* Host-side metadata of a stream set: size, first global index, base state.
+ * Any output pointer may be NULL. */
+mrg_status mrg_streamset_info(mrg_streamset ss, uint64_t *n_streams,
+                              uint64_t *first_stream, uint32_t seed6[6]);
+
+/* Device pointer of the 6 state planes ([6][n_streams] uint32, plane c holds
+ * word c of every stream).  Owned by the stream set; valid until destroy. */
+mrg_status mrg_streamset_states_ptr(mrg_streamset ss, void **d_states);
+
+/* ---------------------------------------------------------------------- */
+/* Jump ahead (sec. 2.3 sequence splitting; sec. 4.1 substreams of 2^76)   */
+/* Streams [first, first+count) of the set (indices relative to the set).  */
+/* ---------------------------------------------------------------------- */
+
+/* Advance every stream in the range by its own exponent: stream first+i is
+ * moved e_i outputs ahead, e_i given as 3 little-endian uint64 words at
+ * d_exp[3*i .. 3*i+2] (device memory, e_i < 2^192).  Uses 4-bit windowed
+ * tables of A^(d * 16^w) mod m staged in LDS.  count == 0 is a no-op.
+ * Errors: MRG_EINVAL (null), MRG_ERANGE (range outside the set). */
+mrg_status mrg_jump(mrg_streamset ss, uint64_t first, uint64_t count,
+                    const uint64_t *d_exp, void *stream);
+
+/* Advance every stream in the range by the same exponent e (3 host words,
+ * little-endian).  The matrix A^e is formed on the host; one matrix-vector
+ * product per component per stream on the device. */
+mrg_status mrg_jump_uniform(mrg_streamset ss, uint64_t first, uint64_t count,
+                            const uint64_t h_exp[3], void *stream);
+
+/* Advance every stream in the range by k substreams, i.e. k * 2^76 outputs
+ * (sec. 4.1).  k < 2^115. */
+mrg_status mrg_jump_substreams(mrg_streamset ss, uint64_t first, uint64_t count,
+                               uint64_t k, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Bulk generation (sec. 5.2 next(); Listing 1 pattern)                    */
+/* ---------------------------------------------------------------------- */
+
+/* Write n_per_stream outputs of each stream first .. first+count-1 to d_out
+ * and advance each of those streams by n_per_stream.
+ *   layout MRG_STREAM_MAJOR: d_out[s * n_per_stream + k] (a [count, n] array)
+ *   layout MRG_INTERLEAVED : d_out[k * count + s]        (a [n, count] array)
+ * d_out must hold count * n_per_stream elements of the dtype (4 bytes for
+ * MRG_U32/MRG_F32, 8 for MRG_F64) and be aligned to the element size; 16-byte
+ * alignment enables the vector store path.  n_per_stream == 0 or count == 0
+ * is a no-op.  Errors: MRG_EINVAL (null d_out, bad dtype/layout,
+ * misaligned), MRG_ERANGE (range outside the set). */
+mrg_status mrg_fill(mrg_streamset ss, uint64_t first, uint64_t count,
+                    uint64_t n_per_stream, mrg_dtype dtype, mrg_layout layout,
+                    void *d_out, void *stream);
+
+/* Copy the states of streams [first, first+count) to host memory h_out
+ * ([count][6] uint32).  Synchronous with respect to `stream` (waits for it). */
+mrg_status mrg_get_states(mrg_streamset ss, uint64_t first, uint64_t count,
+                          uint32_t *h_out, void *stream);
+
+/* Overwrite the states of streams [first, first+count) from host memory
+ * h_in ([count][6] uint32, each a valid state; checked on the host, else
+ * MRG_EINVAL and nothing is written).  Synchronous with respect to `stream`. */
+mrg_status mrg_set_states(mrg_streamset ss, uint64_t first, uint64_t count,
+                          const uint32_t *h_in, void *stream);
+
+/* ---------------------------------------------------------------------- */
+/* Host-only helpers (no device work; usable without a GPU)               */
+/* ---------------------------------------------------------------------- */
+
+/* Expand a 64-bit master seed into a valid 6-word state (random spacing,
+ * sec. 2.3): successive SplitMix64 outputs (Steele, Lea & Flood 2014) taken
+ * mod m1 for words 0-2 and mod m2 for words 3-5; an all-zero triple is
+ * drawn again. */
+mrg_status mrg_seed_from_master(uint64_t master_seed, uint32_t out6[6]);
+
+/* A_c^e mod m_c (row-major 3x3) for component c in {0, 1} and a 192-bit
+ * exponent e (3 little-endian words); A_c is the companion matrix acting on
+ * the column (x[n-3], x[n-2], x[n-1]) (sec. 2.3 jump ahead). */
+mrg_status mrg_jump_matrix(int component, const uint64_t h_exp[3], uint32_t out9[9]);
+
+/* Check a host state: MRG_OK if valid, else MRG_EINVAL. */
+mrg_status mrg_state_check(const uint32_t state6[6]);
+
+/* Process-wide tuning of the generation kernels (no effect on results):
+ *   "engine"     0 = 32-bit integer arithmetic with lazy residues,
+ *                1 = binary64 arithmetic with centred residues (default);
+ *   "tile_bytes" bytes per stream per LDS tile of the stream-major fill,
+ *                128 (default) or 256.
+ * Unknown keys or values: MRG_EINVAL.  Takes effect for later launches. */
+mrg_status mrg_config_set(const char *key, int64_t value);
+mrg_status mrg_config_get(const char *key, int64_t *value);
+
+/* Static text of a status code. */
+const char *mrg_status_string(mrg_status s);
+
+/* Text of the last error raised on the calling thread ("" if none). */
+const char *mrg_last_error(void);
+
+/* Library version as an integer (major*10000 + minor*100 + patch). */
+int32_t mrg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MRG32K3A_GPU_H */

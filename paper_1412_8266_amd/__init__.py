@@ -1,0 +1,159 @@
+"""MI355X-native MRG32k3a stream library (HIP kernels for gfx950).
+
+Bulk uniform random generation from many independent, reproducible streams
+of MRG32k3a placed by jump ahead (Passerat-Palmbach & Hill, HPCS 2012:
+sec. 4.1 streams of 2^127 and substreams of 2^76; sec. 2.3 sequence
+splitting; sec. 5 host initialisation and per-thread ``next()``).
+
+Every step runs in the HIP library ``libmrg32k3a_gpu.so``; this package only
+marshals arguments.  PyTorch provides device memory and HIP streams.
+"""
+from __future__ import annotations
+
+from typing import Optional
+
+import numpy as np
+
+from . import _abi
+from ._abi import (MRGError, MRG_F32, MRG_F64, MRG_INTERLEAVED, MRG_STREAM_MAJOR, MRG_U32,
+                   mrg_config_get, mrg_config_set, mrg_jump_matrix, mrg_seed_from_master,
+                   mrg_state_check, mrg_version)
+
+U32, F32, F64 = MRG_U32, MRG_F32, MRG_F64
+STREAM_MAJOR, INTERLEAVED = MRG_STREAM_MAJOR, MRG_INTERLEAVED
+M1 = 4294967087
+M2 = 4294944443
+
+_ESIZE = {U32: 4, F32: 4, F64: 8}
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def torch_dtype(dtype: int):
+    torch = _torch()
+    return {U32: torch.uint32, F32: torch.float32, F64: torch.float64}[dtype]
+
+
+def _stream_handle(stream) -> int:
+    torch = _torch()
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+class StreamSet:
+    """``n_streams`` consecutive MRG32k3a streams resident on the current GPU.
+
+    Global stream g starts at A^(g * 2^127) * base; the stream set holds
+    streams [first_stream, first_stream + n_streams).  The base state is
+    ``seed`` (6 words) or is expanded from ``master_seed`` (64 bits).
+    """
+
+    def __init__(self, n_streams: int, seed=None, master_seed: Optional[int] = None,
+                 first_stream: int = 0, stream=None):
+        if (seed is None) == (master_seed is None):
+            raise ValueError("give exactly one of seed (6 words) or master_seed")
+        h = _stream_handle(stream)
+        if seed is not None:
+            self._h = _abi.mrg_streamset_create(n_streams, first_stream, seed, h)
+        else:
+            self._h = _abi.mrg_streamset_create_seed64(n_streams, first_stream, master_seed, h)
+        self.n_streams = int(n_streams)
+        self.first_stream = int(first_stream)
+
+    # -- lifetime -----------------------------------------------------------
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _abi.mrg_streamset_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def handle(self) -> int:
+        return self._h
+
+    @property
+    def base_state(self):
+        return _abi.mrg_streamset_info(self._h)[2]
+
+    def _range(self, first, count):
+        if count is None:
+            count = self.n_streams - first
+        return int(first), int(count)
+
+    # -- generation -----------------------------------------------------------
+    def fill(self, n: int, dtype: int = U32, layout: int = STREAM_MAJOR, out=None,
+             first: int = 0, count: Optional[int] = None, stream=None):
+        """n outputs of each stream in [first, first+count); advances them by n.
+        Returns a [count, n] (stream-major) or [n, count] (interleaved) tensor."""
+        torch = _torch()
+        first, count = self._range(first, count)
+        shape = (count, n) if layout == STREAM_MAJOR else (n, count)
+        if out is None:
+            out = torch.empty(shape, dtype=torch_dtype(dtype), device="cuda")
+        else:
+            if out.numel() < count * n or out.element_size() != _ESIZE[dtype]:
+                raise ValueError("output tensor too small or of the wrong element size")
+            if not out.is_contiguous():
+                raise ValueError("output tensor must be contiguous")
+        _abi.mrg_fill(self._h, first, count, n, dtype, layout,
+                      out.data_ptr() if out.numel() else 0, _stream_handle(stream))
+        return out
+
+    def fill_ptr(self, n: int, dtype: int, layout: int, d_out: int, first: int = 0,
+                 count: Optional[int] = None, stream=None) -> None:
+        first, count = self._range(first, count)
+        _abi.mrg_fill(self._h, first, count, n, dtype, layout, d_out, _stream_handle(stream))
+
+    # -- jumps ------------------------------------------------------------------
+    def jump(self, exps, first: int = 0, count: Optional[int] = None, stream=None) -> None:
+        """Jump stream first+i by exps[i]; ``exps`` is a device uint64 tensor
+        [count, 3] (little-endian words of each exponent)."""
+        first, count = self._range(first, count)
+        if exps.numel() < 3 * count or not exps.is_cuda or exps.element_size() != 8:
+            raise ValueError("exps must be a CUDA tensor of >= 3*count 64-bit words")
+        _abi.mrg_jump(self._h, first, count, exps.data_ptr(), _stream_handle(stream))
+
+    def jump_uniform(self, e: int, first: int = 0, count: Optional[int] = None,
+                     stream=None) -> None:
+        first, count = self._range(first, count)
+        _abi.mrg_jump_uniform(self._h, first, count, e, _stream_handle(stream))
+
+    def jump_substreams(self, k: int, first: int = 0, count: Optional[int] = None,
+                        stream=None) -> None:
+        first, count = self._range(first, count)
+        _abi.mrg_jump_substreams(self._h, first, count, k, _stream_handle(stream))
+
+    # -- states -----------------------------------------------------------------
+    def get_states(self, first: int = 0, count: Optional[int] = None, stream=None) -> np.ndarray:
+        first, count = self._range(first, count)
+        w = _abi.mrg_get_states(self._h, first, count, _stream_handle(stream))
+        return np.array(w, dtype=np.uint32).reshape(count, 6)
+
+    def set_states(self, states, first: int = 0, stream=None) -> None:
+        st = np.asarray(states, dtype=np.uint32).reshape(-1, 6)
+        _abi.mrg_set_states(self._h, first, st.shape[0], st.reshape(-1).tolist(),
+                            _stream_handle(stream))
+
+
+__all__ = [
+    "StreamSet", "MRGError", "U32", "F32", "F64", "STREAM_MAJOR", "INTERLEAVED", "M1", "M2",
+    "mrg_seed_from_master", "mrg_jump_matrix", "mrg_state_check", "mrg_config_set",
+    "mrg_config_get", "mrg_version", "torch_dtype",
+]

@@ -1,0 +1,190 @@
+"""ctypes binding of ``libmrg32k3a_gpu.so`` (declared in include/mrg32k3a_gpu.h).
+
+Argument marshalling only: every function here forwards to the C entry point
+of the same name.  Device pointers and HIP streams are passed as integers
+(``tensor.data_ptr()``, ``torch.cuda.Stream.cuda_stream``).  There is no CPU
+path: if the library is not built, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmrg32k3a_gpu.so")
+
+MRG_OK, MRG_EINVAL, MRG_ENOMEM, MRG_EHIP, MRG_ERANGE, MRG_ENODEV = 0, -1, -2, -3, -4, -5
+MRG_U32, MRG_F32, MRG_F64 = 0, 1, 2
+MRG_STREAM_MAJOR, MRG_INTERLEAVED = 0, 1
+
+
+class MRGError(RuntimeError):
+    def __init__(self, status: int, func: str, detail: str):
+        super().__init__("%s failed with %d: %s" % (func, status, detail))
+        self.status = status
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            "libmrg32k3a_gpu.so is not built (expected at %s); build it with "
+            "`python -m paper_1412_8266_amd.build`" % LIB_PATH)
+    return ctypes.CDLL(LIB_PATH)
+
+
+lib = _load()
+
+_P = ctypes.c_void_p
+_U64 = ctypes.c_uint64
+_I32 = ctypes.c_int32
+_I64 = ctypes.c_int64
+_PU32 = ctypes.POINTER(ctypes.c_uint32)
+_PU64 = ctypes.POINTER(ctypes.c_uint64)
+
+_SIGS = {
+    "mrg_streamset_create": [ctypes.POINTER(_P), _U64, _U64, _PU32, _P],
+    "mrg_streamset_create_seed64": [ctypes.POINTER(_P), _U64, _U64, _U64, _P],
+    "mrg_streamset_destroy": [_P],
+    "mrg_streamset_info": [_P, _PU64, _PU64, _PU32],
+    "mrg_streamset_states_ptr": [_P, ctypes.POINTER(_P)],
+    "mrg_jump": [_P, _U64, _U64, _P, _P],
+    "mrg_jump_uniform": [_P, _U64, _U64, _PU64, _P],
+    "mrg_jump_substreams": [_P, _U64, _U64, _U64, _P],
+    "mrg_fill": [_P, _U64, _U64, _U64, _I32, _I32, _P, _P],
+    "mrg_get_states": [_P, _U64, _U64, _PU32, _P],
+    "mrg_set_states": [_P, _U64, _U64, _PU32, _P],
+    "mrg_seed_from_master": [_U64, _PU32],
+    "mrg_jump_matrix": [_I32, _PU64, _PU32],
+    "mrg_state_check": [_PU32],
+    "mrg_config_set": [ctypes.c_char_p, _I64],
+    "mrg_config_get": [ctypes.c_char_p, ctypes.POINTER(_I64)],
+}
+for _name, _args in _SIGS.items():
+    _f = getattr(lib, _name)
+    _f.argtypes = _args
+    _f.restype = _I32
+lib.mrg_status_string.argtypes = [_I32]
+lib.mrg_status_string.restype = ctypes.c_char_p
+lib.mrg_last_error.argtypes = []
+lib.mrg_last_error.restype = ctypes.c_char_p
+lib.mrg_version.argtypes = []
+lib.mrg_version.restype = _I32
+
+
+def check(status: int, func: str) -> None:
+    if status != MRG_OK:
+        raise MRGError(status, func, lib.mrg_last_error().decode(errors="replace"))
+
+
+def _call(name, *args):
+    check(getattr(lib, name)(*args), name)
+
+
+def _u32(words, n):
+    arr = (ctypes.c_uint32 * n)(*[int(w) for w in words])
+    return arr
+
+
+def _u64x3(e: int):
+    if not (0 <= int(e) < 1 << 192):
+        raise ValueError("exponent must be in [0, 2^192)")
+    e = int(e)
+    return (ctypes.c_uint64 * 3)(*[(e >> (64 * i)) & ((1 << 64) - 1) for i in range(3)])
+
+
+# ---- same-named wrappers ------------------------------------------------------
+def mrg_streamset_create(n_streams: int, first_stream: int, seed6, stream: int = 0) -> int:
+    h = _P()
+    _call("mrg_streamset_create", ctypes.byref(h), n_streams, first_stream, _u32(seed6, 6), stream)
+    return h.value
+
+
+def mrg_streamset_create_seed64(n_streams: int, first_stream: int, master_seed: int,
+                                stream: int = 0) -> int:
+    h = _P()
+    _call("mrg_streamset_create_seed64", ctypes.byref(h), n_streams, first_stream,
+          master_seed & ((1 << 64) - 1), stream)
+    return h.value
+
+
+def mrg_streamset_destroy(ss: int) -> None:
+    _call("mrg_streamset_destroy", ss)
+
+
+def mrg_streamset_info(ss: int):
+    n, first = _U64(), _U64()
+    seed = (ctypes.c_uint32 * 6)()
+    _call("mrg_streamset_info", ss, ctypes.byref(n), ctypes.byref(first), seed)
+    return n.value, first.value, list(seed)
+
+
+def mrg_streamset_states_ptr(ss: int) -> int:
+    p = _P()
+    _call("mrg_streamset_states_ptr", ss, ctypes.byref(p))
+    return p.value
+
+
+def mrg_jump(ss: int, first: int, count: int, d_exp: int, stream: int = 0) -> None:
+    _call("mrg_jump", ss, first, count, d_exp, stream)
+
+
+def mrg_jump_uniform(ss: int, first: int, count: int, e: int, stream: int = 0) -> None:
+    _call("mrg_jump_uniform", ss, first, count, _u64x3(e), stream)
+
+
+def mrg_jump_substreams(ss: int, first: int, count: int, k: int, stream: int = 0) -> None:
+    _call("mrg_jump_substreams", ss, first, count, k, stream)
+
+
+def mrg_fill(ss: int, first: int, count: int, n_per_stream: int, dtype: int, layout: int,
+             d_out: int, stream: int = 0) -> None:
+    _call("mrg_fill", ss, first, count, n_per_stream, dtype, layout, d_out, stream)
+
+
+def mrg_get_states(ss: int, first: int, count: int, stream: int = 0):
+    buf = (ctypes.c_uint32 * (6 * count))()
+    _call("mrg_get_states", ss, first, count, buf, stream)
+    return list(buf)
+
+
+def mrg_set_states(ss: int, first: int, count: int, words, stream: int = 0) -> None:
+    buf = _u32(words, 6 * count)
+    _call("mrg_set_states", ss, first, count, buf, stream)
+
+
+def mrg_seed_from_master(master_seed: int):
+    out = (ctypes.c_uint32 * 6)()
+    _call("mrg_seed_from_master", master_seed & ((1 << 64) - 1), out)
+    return list(out)
+
+
+def mrg_jump_matrix(component: int, e: int):
+    out = (ctypes.c_uint32 * 9)()
+    _call("mrg_jump_matrix", component, _u64x3(e), out)
+    return [list(out[0:3]), list(out[3:6]), list(out[6:9])]
+
+
+def mrg_state_check(state6) -> int:
+    return int(lib.mrg_state_check(_u32(state6, 6)))
+
+
+def mrg_config_set(key: str, value: int) -> None:
+    _call("mrg_config_set", key.encode(), value)
+
+
+def mrg_config_get(key: str) -> int:
+    v = _I64()
+    _call("mrg_config_get", key.encode(), ctypes.byref(v))
+    return v.value
+
+
+def mrg_status_string(status: int) -> str:
+    return lib.mrg_status_string(status).decode()
+
+
+def mrg_last_error() -> str:
+    return lib.mrg_last_error().decode(errors="replace")
+
+
+def mrg_version() -> int:
+    return int(lib.mrg_version())

@@ -1,0 +1,493 @@
+// C ABI of the MRG32k3a stream library: argument validation, host-side jump
+// matrices and tables, device memory of stream sets, kernel launches.
+//
+// Host initialisation before any kernel (sec. 5.1): creating a stream set
+// allocates its device state and computes every stream's starting state on
+// the device; release frees it.  Streams and substreams follow sec. 4.1 and
+// the jump ahead of sec. 2.3 (matrix powers mod m).
+#include <hip/hip_runtime.h>
+
+#include <array>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "mrg32k3a_gpu.h"
+#include "kernels.h"
+#include "mrg_arith.hpp"
+
+struct mrg_streamset_s {
+    int device = -1;
+    uint64_t n = 0;         // streams in the set
+    uint64_t first = 0;     // global index of stream 0 of the set
+    uint32_t seed[6] = {};  // base state (global stream 0)
+    uint32_t *d_planes = nullptr;  // [6][n]
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+mrg_status fail(mrg_status s, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return s;
+}
+
+mrg_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(MRG_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// ---- host jump matrices (sec. 2.3) ---------------------------------------
+using Mat = std::array<uint32_t, 9>;
+
+Mat identity() { return {1, 0, 0, 0, 1, 0, 0, 0, 1}; }
+
+uint64_t modulus(int c) { return c == 0 ? mrg::M1 : mrg::M2; }
+
+// Companion matrix of component c on the column (x[n-3], x[n-2], x[n-1]).
+Mat companion(int c)
+{
+    Mat A = {0, 1, 0, 0, 0, 1, 0, 0, 0};
+    if (c == 0) {
+        A[6] = mrg::M1 - mrg::A13N;
+        A[7] = mrg::A12;
+    } else {
+        A[6] = mrg::M2 - mrg::A23N;
+        A[8] = mrg::A21;
+    }
+    return A;
+}
+
+Mat mul(const Mat &X, const Mat &Y, uint64_t m)
+{
+    Mat R;
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+            unsigned __int128 acc = 0;
+            for (int k = 0; k < 3; ++k) acc += (unsigned __int128)X[3 * i + k] * Y[3 * k + j];
+            R[3 * i + j] = (uint32_t)(acc % m);
+        }
+    return R;
+}
+
+Mat power(int c, const uint64_t e[3])
+{
+    const uint64_t m = modulus(c);
+    Mat R = identity(), B = companion(c);
+    int top = 191;
+    while (top >= 0 && !((e[top / 64] >> (top % 64)) & 1u)) --top;
+    for (int b = 0; b <= top; ++b) {
+        if ((e[b / 64] >> (b % 64)) & 1u) R = mul(R, B, m);
+        if (b < top) B = mul(B, B, m);
+    }
+    return R;
+}
+
+// T[c][w][d] = A_c^(d * 16^w), d = 0 the identity.
+std::vector<uint32_t> build_tables()
+{
+    std::vector<uint32_t> t(mrg::kTableWords);
+    for (int c = 0; c < 2; ++c) {
+        const uint64_t m = modulus(c);
+        Mat base = companion(c);  // A^(16^w)
+        for (int w = 0; w < mrg::kTableWindows; ++w) {
+            Mat cur = identity();
+            for (int d = 0; d < 16; ++d) {
+                std::memcpy(&t[((c * mrg::kTableWindows + w) * 16 + d) * 9], cur.data(), 36);
+                cur = mul(cur, base, m);
+            }
+            // cur = base^16 = A^(16^(w+1))
+            base = cur;
+        }
+    }
+    return t;
+}
+
+const std::vector<uint32_t> &host_tables()
+{
+    static const std::vector<uint32_t> t = build_tables();
+    return t;
+}
+
+// ---- per-device context ----------------------------------------------------
+struct DevCtx {
+    uint32_t *d_table = nullptr;
+};
+
+std::mutex g_mu;
+std::map<int, DevCtx> g_dev;
+mrg::FillTuning g_tune;  // process-wide kernel tuning (guarded by g_mu)
+
+mrg::FillTuning tuning()
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    return g_tune;
+}
+
+mrg_status current_device(int *dev)
+{
+    int count = 0;
+    hipError_t e = hipGetDeviceCount(&count);
+    if (e != hipSuccess || count <= 0) return fail(MRG_ENODEV, "no HIP device available");
+    e = hipGetDevice(dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    return MRG_OK;
+}
+
+mrg_status device_ctx(int dev, DevCtx **out)
+{
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_dev.find(dev);
+    if (it != g_dev.end()) {
+        *out = &it->second;
+        return MRG_OK;
+    }
+    const std::vector<uint32_t> &t = host_tables();
+    DevCtx ctx;
+    hipError_t e = hipMalloc(&ctx.d_table, t.size() * sizeof(uint32_t));
+    if (e != hipSuccess) return fail(MRG_ENOMEM, "hipMalloc(jump tables): %s", hipGetErrorString(e));
+    e = hipMemcpy(ctx.d_table, t.data(), t.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(ctx.d_table);
+        return hip_fail(e, "hipMemcpy(jump tables)");
+    }
+    auto res = g_dev.emplace(dev, ctx);
+    *out = &res.first->second;
+    return MRG_OK;
+}
+
+bool state_ok(const uint32_t *s)
+{
+    if (s[0] >= mrg::M1 || s[1] >= mrg::M1 || s[2] >= mrg::M1) return false;
+    if (s[3] >= mrg::M2 || s[4] >= mrg::M2 || s[5] >= mrg::M2) return false;
+    if ((s[0] | s[1] | s[2]) == 0u || (s[3] | s[4] | s[5]) == 0u) return false;
+    return true;
+}
+
+mrg_status check_set(mrg_streamset ss)
+{
+    if (!ss || !ss->d_planes) return fail(MRG_EINVAL, "null stream set");
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != ss->device)
+        return fail(MRG_EINVAL, "stream set lives on device %d, current device is %d", ss->device, dev);
+    return MRG_OK;
+}
+
+mrg_status check_range(mrg_streamset ss, uint64_t first, uint64_t count)
+{
+    if (first > ss->n || count > ss->n - first)
+        return fail(MRG_ERANGE, "streams [%llu, %llu+%llu) outside the set of %llu",
+                    (unsigned long long)first, (unsigned long long)first,
+                    (unsigned long long)count, (unsigned long long)ss->n);
+    // one lane per stream, gridDim.x < 2^31 blocks of 64
+    if (count > ((uint64_t)1 << 36))
+        return fail(MRG_ERANGE, "count %llu above the per-call limit 2^36", (unsigned long long)count);
+    return MRG_OK;
+}
+
+uint64_t splitmix64_next(uint64_t &x)
+{
+    x += 0x9e3779b97f4a7c15ULL;
+    uint64_t z = x;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+    return z ^ (z >> 31);
+}
+
+int bit_length(uint64_t v)
+{
+    int b = 0;
+    while (v) { ++b; v >>= 1; }
+    return b;
+}
+
+}  // namespace
+
+extern "C" {
+
+mrg_status mrg_seed_from_master(uint64_t master_seed, uint32_t out6[6])
+{
+    if (!out6) return fail(MRG_EINVAL, "null output");
+    uint64_t x = master_seed;
+    for (int c = 0; c < 2; ++c) {
+        const uint64_t m = modulus(c);
+        for (;;) {
+            uint32_t t[3];
+            for (int i = 0; i < 3; ++i) t[i] = (uint32_t)(splitmix64_next(x) % m);
+            if (t[0] | t[1] | t[2]) {
+                std::memcpy(out6 + 3 * c, t, sizeof t);
+                break;
+            }
+        }
+    }
+    return MRG_OK;
+}
+
+mrg_status mrg_jump_matrix(int component, const uint64_t h_exp[3], uint32_t out9[9])
+{
+    if (!h_exp || !out9) return fail(MRG_EINVAL, "null argument");
+    if (component != 0 && component != 1) return fail(MRG_EINVAL, "component must be 0 or 1");
+    const Mat R = power(component, h_exp);
+    std::memcpy(out9, R.data(), 36);
+    return MRG_OK;
+}
+
+mrg_status mrg_state_check(const uint32_t state6[6])
+{
+    if (!state6) return fail(MRG_EINVAL, "null state");
+    if (!state_ok(state6)) return fail(MRG_EINVAL, "invalid MRG32k3a state");
+    return MRG_OK;
+}
+
+mrg_status mrg_streamset_create(mrg_streamset *out, uint64_t n_streams, uint64_t first_stream,
+                                const uint32_t seed6[6], void *stream)
+{
+    if (!out || !seed6) return fail(MRG_EINVAL, "null argument");
+    *out = nullptr;
+    if (!state_ok(seed6)) return fail(MRG_EINVAL, "invalid seed state");
+    if (n_streams == 0) return fail(MRG_ERANGE, "n_streams must be >= 1");
+    if (n_streams - 1 > UINT64_MAX - first_stream)
+        return fail(MRG_ERANGE, "first_stream + n_streams exceeds 2^64");
+    if (n_streams > ((uint64_t)1 << 36))
+        return fail(MRG_ERANGE, "n_streams above the limit 2^36");
+    int dev;
+    mrg_status st = current_device(&dev);
+    if (st) return st;
+    DevCtx *ctx;
+    if ((st = device_ctx(dev, &ctx))) return st;
+
+    auto *ss = new (std::nothrow) mrg_streamset_s;
+    if (!ss) return fail(MRG_ENOMEM, "host allocation");
+    ss->device = dev;
+    ss->n = n_streams;
+    ss->first = first_stream;
+    std::memcpy(ss->seed, seed6, sizeof ss->seed);
+    hipError_t e = hipMalloc(&ss->d_planes, 6 * n_streams * sizeof(uint32_t));
+    if (e != hipSuccess) {
+        delete ss;
+        return fail(MRG_ENOMEM, "hipMalloc(%llu states): %s", (unsigned long long)n_streams,
+                    hipGetErrorString(e));
+    }
+    // exponent g * 2^127 uses bits 127 .. 126 + bit_length(g): windows 31 ..
+    const uint64_t g_max = first_stream + (n_streams - 1);
+    const int top_bit = 126 + bit_length(g_max);  // highest set bit of g_max * 2^127
+    const int w_lo = 31, w_hi = g_max ? top_bit / 4 + 1 : 31;
+    mrg::InitSeed sd;
+    std::memcpy(sd.w, seed6, sizeof sd.w);
+    e = mrg::launch_init(ss->d_planes, n_streams, n_streams, first_stream, sd, ctx->d_table,
+                         w_lo, w_hi, (hipStream_t)stream);
+    if (e != hipSuccess) {
+        (void)hipFree(ss->d_planes);
+        delete ss;
+        return hip_fail(e, "init kernel launch");
+    }
+    *out = ss;
+    return MRG_OK;
+}
+
+mrg_status mrg_streamset_create_seed64(mrg_streamset *out, uint64_t n_streams,
+                                       uint64_t first_stream, uint64_t master_seed, void *stream)
+{
+    uint32_t s[6];
+    mrg_status st = mrg_seed_from_master(master_seed, s);
+    if (st) return st;
+    return mrg_streamset_create(out, n_streams, first_stream, s, stream);
+}
+
+mrg_status mrg_streamset_destroy(mrg_streamset ss)
+{
+    if (!ss) return MRG_OK;
+    mrg_status st = MRG_OK;
+    if (ss->d_planes) {
+        int prev = -1;
+        (void)hipGetDevice(&prev);
+        if (prev != ss->device) (void)hipSetDevice(ss->device);
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) st = hip_fail(e, "hipDeviceSynchronize before free");
+        e = hipFree(ss->d_planes);
+        if (e != hipSuccess && st == MRG_OK) st = hip_fail(e, "hipFree(states)");
+        if (prev != ss->device && prev >= 0) (void)hipSetDevice(prev);
+    }
+    delete ss;
+    return st;
+}
+
+mrg_status mrg_streamset_info(mrg_streamset ss, uint64_t *n_streams, uint64_t *first_stream,
+                              uint32_t seed6[6])
+{
+    if (!ss) return fail(MRG_EINVAL, "null stream set");
+    if (n_streams) *n_streams = ss->n;
+    if (first_stream) *first_stream = ss->first;
+    if (seed6) std::memcpy(seed6, ss->seed, sizeof ss->seed);
+    return MRG_OK;
+}
+
+mrg_status mrg_streamset_states_ptr(mrg_streamset ss, void **d_states)
+{
+    if (!ss || !d_states) return fail(MRG_EINVAL, "null argument");
+    *d_states = ss->d_planes;
+    return MRG_OK;
+}
+
+mrg_status mrg_jump(mrg_streamset ss, uint64_t first, uint64_t count, const uint64_t *d_exp,
+                    void *stream)
+{
+    mrg_status st = check_set(ss);
+    if (st) return st;
+    if ((st = check_range(ss, first, count))) return st;
+    if (count == 0) return MRG_OK;
+    if (!d_exp) return fail(MRG_EINVAL, "null exponent array");
+    DevCtx *ctx;
+    if ((st = device_ctx(ss->device, &ctx))) return st;
+    hipError_t e = mrg::launch_jump(ss->d_planes, ss->n, first, count, d_exp, ctx->d_table,
+                                    (hipStream_t)stream);
+    return e == hipSuccess ? MRG_OK : hip_fail(e, "jump kernel launch");
+}
+
+mrg_status mrg_jump_uniform(mrg_streamset ss, uint64_t first, uint64_t count,
+                            const uint64_t h_exp[3], void *stream)
+{
+    mrg_status st = check_set(ss);
+    if (st) return st;
+    if ((st = check_range(ss, first, count))) return st;
+    if (!h_exp) return fail(MRG_EINVAL, "null exponent");
+    if (count == 0) return MRG_OK;
+    mrg::JumpMatrices J;
+    const Mat P1 = power(0, h_exp), P2 = power(1, h_exp);
+    std::memcpy(J.m, P1.data(), 36);
+    std::memcpy(J.m + 9, P2.data(), 36);
+    hipError_t e = mrg::launch_jump_uniform(ss->d_planes, ss->n, first, count, J,
+                                            (hipStream_t)stream);
+    return e == hipSuccess ? MRG_OK : hip_fail(e, "jump kernel launch");
+}
+
+mrg_status mrg_jump_substreams(mrg_streamset ss, uint64_t first, uint64_t count, uint64_t k,
+                               void *stream)
+{
+    // k * 2^76 = (k << 12) * 2^64 + (k >> 52) * 2^128
+    const uint64_t e[3] = {0, k << 12, k >> 52};
+    return mrg_jump_uniform(ss, first, count, e, stream);
+}
+
+mrg_status mrg_fill(mrg_streamset ss, uint64_t first, uint64_t count, uint64_t n_per_stream,
+                    mrg_dtype dtype, mrg_layout layout, void *d_out, void *stream)
+{
+    mrg_status st = check_set(ss);
+    if (st) return st;
+    if ((st = check_range(ss, first, count))) return st;
+    if (dtype != MRG_U32 && dtype != MRG_F32 && dtype != MRG_F64)
+        return fail(MRG_EINVAL, "unknown dtype %d", (int)dtype);
+    if (layout != MRG_STREAM_MAJOR && layout != MRG_INTERLEAVED)
+        return fail(MRG_EINVAL, "unknown layout %d", (int)layout);
+    if (count == 0 || n_per_stream == 0) return MRG_OK;
+    if (!d_out) return fail(MRG_EINVAL, "null output");
+    const uint64_t es = dtype == MRG_F64 ? 8 : 4;
+    if ((uintptr_t)d_out % es) return fail(MRG_EINVAL, "output not aligned to its element size");
+    if (n_per_stream > UINT64_MAX / es / count)
+        return fail(MRG_ERANGE, "output size overflows 64 bits");
+    const int vec_ok = ((uintptr_t)d_out % 16 == 0) && ((n_per_stream * es) % 16 == 0);
+    hipError_t e = mrg::launch_fill(ss->d_planes, ss->n, first, count, n_per_stream, (int)dtype,
+                                    (int)layout, d_out, vec_ok, tuning(), (hipStream_t)stream);
+    return e == hipSuccess ? MRG_OK : hip_fail(e, "fill kernel launch");
+}
+
+mrg_status mrg_get_states(mrg_streamset ss, uint64_t first, uint64_t count, uint32_t *h_out,
+                          void *stream)
+{
+    mrg_status st = check_set(ss);
+    if (st) return st;
+    if ((st = check_range(ss, first, count))) return st;
+    if (count == 0) return MRG_OK;
+    if (!h_out) return fail(MRG_EINVAL, "null output");
+    std::vector<uint32_t> tmp(6 * count);
+    for (int c = 0; c < 6; ++c) {
+        hipError_t e = hipMemcpyAsync(tmp.data() + c * count, ss->d_planes + c * ss->n + first,
+                                      count * 4, hipMemcpyDeviceToHost, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(states)");
+    }
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    for (uint64_t i = 0; i < count; ++i)
+        for (int c = 0; c < 6; ++c) h_out[6 * i + c] = tmp[c * count + i];
+    return MRG_OK;
+}
+
+mrg_status mrg_set_states(mrg_streamset ss, uint64_t first, uint64_t count, const uint32_t *h_in,
+                          void *stream)
+{
+    mrg_status st = check_set(ss);
+    if (st) return st;
+    if ((st = check_range(ss, first, count))) return st;
+    if (count == 0) return MRG_OK;
+    if (!h_in) return fail(MRG_EINVAL, "null input");
+    for (uint64_t i = 0; i < count; ++i)
+        if (!state_ok(h_in + 6 * i))
+            return fail(MRG_EINVAL, "state %llu is not a valid MRG32k3a state",
+                        (unsigned long long)i);
+    std::vector<uint32_t> tmp(6 * count);
+    for (uint64_t i = 0; i < count; ++i)
+        for (int c = 0; c < 6; ++c) tmp[c * count + i] = h_in[6 * i + c];
+    for (int c = 0; c < 6; ++c) {
+        hipError_t e = hipMemcpyAsync(ss->d_planes + c * ss->n + first, tmp.data() + c * count,
+                                      count * 4, hipMemcpyHostToDevice, (hipStream_t)stream);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(states)");
+    }
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    return e == hipSuccess ? MRG_OK : hip_fail(e, "hipStreamSynchronize");
+}
+
+mrg_status mrg_config_set(const char *key, int64_t value)
+{
+    if (!key) return fail(MRG_EINVAL, "null key");
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!std::strcmp(key, "engine")) {
+        if (value != 0 && value != 1) return fail(MRG_EINVAL, "engine must be 0 or 1");
+        g_tune.engine = (int)value;
+    } else if (!std::strcmp(key, "tile_bytes")) {
+        if (value != 128 && value != 256) return fail(MRG_EINVAL, "tile_bytes must be 128 or 256");
+        g_tune.tile_bytes = (int)value;
+    } else {
+        return fail(MRG_EINVAL, "unknown key '%s'", key);
+    }
+    return MRG_OK;
+}
+
+mrg_status mrg_config_get(const char *key, int64_t *value)
+{
+    if (!key || !value) return fail(MRG_EINVAL, "null argument");
+    std::lock_guard<std::mutex> lk(g_mu);
+    if (!std::strcmp(key, "engine")) *value = g_tune.engine;
+    else if (!std::strcmp(key, "tile_bytes")) *value = g_tune.tile_bytes;
+    else return fail(MRG_EINVAL, "unknown key '%s'", key);
+    return MRG_OK;
+}
+
+const char *mrg_status_string(mrg_status s)
+{
+    switch (s) {
+    case MRG_OK: return "MRG_OK";
+    case MRG_EINVAL: return "MRG_EINVAL: invalid argument";
+    case MRG_ENOMEM: return "MRG_ENOMEM: allocation failed";
+    case MRG_EHIP: return "MRG_EHIP: HIP runtime error";
+    case MRG_ERANGE: return "MRG_ERANGE: out of range";
+    case MRG_ENODEV: return "MRG_ENODEV: no HIP device";
+    default: return "unknown mrg_status";
+    }
+}
+
+const char *mrg_last_error(void) { return g_last_error.c_str(); }
+
+int32_t mrg_version(void) { return 100; }
+
+}  // extern "C"

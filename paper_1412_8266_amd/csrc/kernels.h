@@ -1,0 +1,35 @@
+// Internal interface between the C-ABI host code and the HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace mrg {
+
+// Windowed jump tables: T[c][w][d] = A_c^(d * 16^w) mod m_c, row-major 3x3,
+// for c in {0,1}, w in [0, 48), d in [0, 16) (d = 0: identity).
+constexpr int kTableWindows = 48;
+constexpr int kTableWindowWords = 16 * 9;
+constexpr int kTableWords = 2 * kTableWindows * kTableWindowWords;
+
+struct InitSeed { uint32_t w[6]; };
+struct JumpMatrices { uint32_t m[18]; };  // component 1 then component 2
+
+hipError_t launch_init(uint32_t *planes, uint64_t plane_stride, uint64_t count, uint64_t g0,
+                       const InitSeed &seed, const uint32_t *table, int w_lo, int w_hi,
+                       hipStream_t st);
+hipError_t launch_jump(uint32_t *planes, uint64_t plane_stride, uint64_t first, uint64_t count,
+                       const uint64_t *d_exp, const uint32_t *table, hipStream_t st);
+hipError_t launch_jump_uniform(uint32_t *planes, uint64_t plane_stride, uint64_t first,
+                               uint64_t count, const JumpMatrices &J, hipStream_t st);
+// Generation engine (0: integer lazy words, 1: binary64 centred words) and
+// bytes per row per LDS tile (128 or 256) of the stream-major fill.
+struct FillTuning {
+    int engine = 1;
+    int tile_bytes = 128;
+};
+
+hipError_t launch_fill(uint32_t *planes, uint64_t plane_stride, uint64_t first, uint64_t count,
+                       uint64_t n, int dtype, int layout, void *out, int vec_ok,
+                       const FillTuning &tune, hipStream_t st);
+
+}  // namespace mrg

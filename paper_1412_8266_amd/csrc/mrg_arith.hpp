@@ -1,0 +1,181 @@
+// MRG32k3a arithmetic shared by the kernels and the host side of the library.
+//
+// Generator (sec. 4.1; constants of L'Ecuyer 1999, which that section cites):
+//   x1[n] = (a12 * x1[n-2] - a13n * x1[n-3]) mod m1
+//   x2[n] = (a21 * x2[n-1] - a23n * x2[n-3]) mod m2
+//   z[n]  = (x1[n] - x2[n]) mod m1, reported as m1 when 0
+//
+// gfx950 formulation.  Neither modulus is reduced with a division.  Both are
+// pseudo-Mersenne: 2^32 = C (mod m) with C = 209 for m1 and 22853 for m2, so a
+// 64-bit value hi*2^32 + lo folds to hi*C + lo.  Inside the hot loop a state
+// word is any representative in [0, 2^32) of its residue ("lazy" form), which
+// removes every conditional subtraction from the recurrence:
+//   -x = ~x + 1 - 2^32 = ~x + (1 - C)  (mod m)  for every 32-bit x,
+// so a*(-x) = a*~x + K with the constant K = a*(1 - C) mod m, and each
+// product-sum is two v_mad_u64_u32 starting from K.  Folding then brings the
+// 53-bit sum back to 32 bits (two folds for m1, three for m2).  Only the
+// output combination and the state write-back map a word to its canonical
+// residue, with min(x, x + C) (x + C wraps below x exactly when x >= m).
+//
+// A second formulation keeps the state in binary64 (the "F" functions):
+// every product-sum a*s - b*t with |s|, |t| <= m/2 + 8 is below 2^53 in
+// magnitude, so one FMA forms it exactly; r = p - m * rint(p / m) is exact
+// (the quotient only needs to be near the true one) and lies within
+// m/2 + 8 of zero.  Each step is then five binary64 operations per
+// component.  Both formulations give the same residues.
+#pragma once
+#include <stdint.h>
+
+#if defined(__HIPCC__)
+#define MRG_HD __host__ __device__ __forceinline__
+#else
+#define MRG_HD static inline
+#endif
+
+namespace mrg {
+
+constexpr uint32_t M1 = 4294967087u;  // 2^32 - 209
+constexpr uint32_t M2 = 4294944443u;  // 2^32 - 22853
+constexpr uint32_t C1 = 209u;         // 2^32 mod m1
+constexpr uint32_t C2 = 22853u;       // 2^32 mod m2
+constexpr uint32_t A12 = 1403580u;
+constexpr uint32_t A13N = 810728u;
+constexpr uint32_t A21 = 527612u;
+constexpr uint32_t A23N = 1370589u;
+// K = a * (1 - C) mod m, the constant term of a*(-x) written as a*~x + K.
+constexpr uint32_t K1 = (uint32_t)(((uint64_t)A13N * (uint64_t)(M1 - (C1 - 1u))) % M1);
+constexpr uint32_t K2 = (uint32_t)(((uint64_t)A23N * (uint64_t)(M2 - (C2 - 1u))) % M2);
+constexpr double NORM = 2.328306549295727688e-10;  // nearest double to 1/(m1+1)
+
+MRG_HD uint32_t umin(uint32_t a, uint32_t b) { return a < b ? a : b; }
+
+// Canonical residue of a lazy word: x mod m for x in [0, 2^32).
+MRG_HD uint32_t canon1(uint32_t x) { return umin(x, x + C1); }
+MRG_HD uint32_t canon2(uint32_t x) { return umin(x, x + C2); }
+
+// Next component-1 word from x1[n-3] = s0 and x1[n-2] = s1 (both lazy);
+// result lazy.  t < (a13n + a12 + 1) * 2^32 < 2^53.1; u < 2^32 + 2^29.
+// The multipliers are parameters so that a kernel can pass copies held in
+// vector registers.
+MRG_HD uint32_t next1(uint32_t s0, uint32_t s1, uint32_t a13n = A13N, uint32_t a12 = A12)
+{
+    uint64_t t = (uint64_t)a13n * (uint32_t)~s0 + K1;
+    t += (uint64_t)a12 * s1;
+    uint64_t u = (uint64_t)(uint32_t)(t >> 32) * C1 + (uint32_t)t;
+    return (uint32_t)u + (uint32_t)(u >> 32) * C1;
+}
+
+// Next component-2 word from x2[n-3] = s3 and x2[n-1] = s5 (both lazy);
+// result lazy.  t < 2^52.9; u < 2^35.5; v < 2^32 + 2^18.1.
+MRG_HD uint32_t next2(uint32_t s3, uint32_t s5, uint32_t a23n = A23N, uint32_t a21 = A21)
+{
+    uint64_t t = (uint64_t)a23n * (uint32_t)~s3 + K2;
+    t += (uint64_t)a21 * s5;
+    uint64_t u = (uint64_t)(uint32_t)(t >> 32) * C2 + (uint32_t)t;
+    uint64_t v = (uint64_t)(uint32_t)(u >> 32) * C2 + (uint32_t)u;
+    return (uint32_t)v + (uint32_t)(v >> 32) * C2;
+}
+
+// Combined output z' in [1, m1] from lazy x1[n], x2[n]:
+// a = x1 mod m1, b = (x2 mod m2) + 1, y = a - b (mod 2^32);
+// a >= b: z = y + 1;  a < b (x1 <= x2): z = y + 1 + m1 = y + 1 - 209 (mod 2^32).
+MRG_HD uint32_t combine(uint32_t x1, uint32_t x2)
+{
+    uint32_t a = canon1(x1);
+    uint32_t b = canon2(x2) + 1u;
+    uint32_t y = a - b;
+    return y + (a < b ? 1u - C1 : 1u);
+}
+
+MRG_HD double to_f64(uint32_t z) { return (double)z * NORM; }
+
+// (2k + 1) * 2^-24 with k = (z - 1) >> 9, written as k * 2^-23 + 2^-24:
+// both terms and their sum are exact in binary32.
+MRG_HD float to_f32(uint32_t z)
+{
+    uint32_t k = (z - 1u) >> 9;
+    return (float)k * 0x1p-23f + 0x1p-24f;
+}
+
+// ---- matrix-vector product mod m for jumps (entries and x any 32-bit) ----
+// p = M*x < 2^64 folds to hi*C + lo < 2^32 (C + 1); three of them sum below
+// 2^48.2; one more fold leaves < 2^32 + 2^30.6, and the last fold is exact
+// in 32 bits.  Result canonical.
+template <uint32_t C>
+MRG_HD uint32_t dot3_mod(uint32_t m0, uint32_t m1_, uint32_t m2_,
+                         uint32_t x0, uint32_t x1, uint32_t x2)
+{
+    uint64_t p0 = (uint64_t)m0 * x0, p1 = (uint64_t)m1_ * x1, p2 = (uint64_t)m2_ * x2;
+    uint64_t s = (uint64_t)(uint32_t)(p0 >> 32) * C + (uint32_t)p0;
+    s += (uint64_t)(uint32_t)(p1 >> 32) * C + (uint32_t)p1;
+    s += (uint64_t)(uint32_t)(p2 >> 32) * C + (uint32_t)p2;
+    uint64_t u = (uint64_t)(uint32_t)(s >> 32) * C + (uint32_t)s;
+    uint32_t r = (uint32_t)u + (uint32_t)(u >> 32) * C;
+    return umin(r, r + C);
+}
+
+// v <- M v (mod m) for one component; M row-major 3x3.
+template <uint32_t C>
+MRG_HD void matvec3(const uint32_t *M, uint32_t &v0, uint32_t &v1, uint32_t &v2)
+{
+    uint32_t r0 = dot3_mod<C>(M[0], M[1], M[2], v0, v1, v2);
+    uint32_t r1 = dot3_mod<C>(M[3], M[4], M[5], v0, v1, v2);
+    uint32_t r2 = dot3_mod<C>(M[6], M[7], M[8], v0, v1, v2);
+    v0 = r0; v1 = r1; v2 = r2;
+}
+
+// ---- binary64 formulation -------------------------------------------------
+constexpr double M1D = 4294967087.0;
+constexpr double M2D = 4294944443.0;
+constexpr double INV1 = 1.0 / 4294967087.0;  // rounds above 1/m1: m1 * INV1 -> 1.0
+constexpr double INV2 = 1.0 / 4294944443.0;
+
+// Next centred component-1 word from x1[n-3] = s0 and x1[n-2] = s1.
+MRG_HD double next1f(double s0, double s1)
+{
+    const double p = __builtin_fma((double)A12, s1, -((double)A13N * s0));
+    return __builtin_fma(-__builtin_rint(p * INV1), M1D, p);
+}
+
+// Next centred component-2 word from x2[n-3] = s3 and x2[n-1] = s5.
+MRG_HD double next2f(double s3, double s5)
+{
+    const double p = __builtin_fma((double)A21, s5, -((double)A23N * s3));
+    return __builtin_fma(-__builtin_rint(p * INV2), M2D, p);
+}
+
+// Combined output z' in [1, m1] (as an exact binary64 integer) from centred
+// r1, r2.  With x2 the canonical residue of r2,
+//   x1 - x2 = r1 - r2 + 22644 * [r2 < 0]  (mod m1)      (m1 - m2 = 22644),
+// where [r2 < 0] = clamp(-r2, 0, 1) since r2 is an integer.  The sum w lies
+// in (-m1 + 1, 2 m1); z = w - m1 * floor((w - 1) / m1) maps it to [1, m1].
+// The quotient is exact: (w-1)/m1 is at least 1/m1 away from any integer
+// except at w - 1 in {0, m1}, where RN((w-1) * INV1) gives 0 and 1.
+MRG_HD double combinef(double r1, double r2)
+{
+    const double w = r1 - r2;
+    const double c = __builtin_fmin(__builtin_fmax(-r2, 0.0), 1.0);
+    const double w2 = __builtin_fma(c, 22644.0, w);
+    const double k = __builtin_floor(__builtin_fma(w2, INV1, -INV1));
+    return __builtin_fma(-k, M1D, w2);
+}
+
+// Canonical residue (as uint32) of a centred word.
+MRG_HD uint32_t canonf(double r, double m)
+{
+    const double c = __builtin_fmin(__builtin_fmax(-r, 0.0), 1.0);
+    return (uint32_t)__builtin_fma(c, m, r);
+}
+
+MRG_HD double to_f64f(double z) { return z * NORM; }
+
+// FP32 output from an exact binary64 z: k = floor((z - 1) / 512) is exact
+// ((z-1) * 2^-9 is representable), k * 2^-23 + 2^-24 is exact in binary64
+// and has 24 significant bits, so the conversion to binary32 is exact.
+MRG_HD float to_f32f(double z)
+{
+    const double k = __builtin_floor(__builtin_fma(z, 0x1p-9, -0x1p-9));
+    return (float)__builtin_fma(k, 0x1p-23, 0x1p-24);
+}
+
+}  // namespace mrg

@@ -1,0 +1,249 @@
+"""GPU parity: the HIP library against the CPU oracle, bit for bit.
+
+Every output of every dtype must equal the oracle's (tolerance 0: the
+generator is an exact integer recurrence and both conversions are defined
+by a single rounding or none).  Small cases span several LDS tiles and
+ragged tails; the full-size workloads are checked on sampled streams that
+the oracle recomputes one by one, plus properties over every output.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1412_8266_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+ENGINES = [0, 1]
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mg():
+    import torch
+    import paper_1412_8266_amd as m
+    assert torch.cuda.is_available()
+    return m
+
+
+@pytest.fixture(params=ENGINES, ids=["int", "f64"])
+def engine(request, mg):
+    old = mg.mrg_config_get("engine")
+    mg.mrg_config_set("engine", request.param)
+    yield request.param
+    mg.mrg_config_set("engine", old)
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def oracle_fill(base, first, count, n, dtype, layout=oracle.STREAM_MAJOR):
+    st = oracle.streams(np.asarray(base, dtype=np.uint32), first, count)
+    return oracle.fill(st, n, dtype, layout)
+
+
+def test_c1_seed_12345_u32_then_f64(mg, engine):
+    say("C1 engine", engine)
+    ss = mg.StreamSet(wl.C1_STREAMS, seed=wl.C1_SEED)
+    got = host(ss.fill(wl.C1_N, mg.U32))
+    want, st = oracle_fill(wl.C1_SEED, 0, wl.C1_STREAMS, wl.C1_N, oracle.U32)
+    assert np.array_equal(got, want)
+    assert np.array_equal(ss.get_states(), st)
+    ss.close()
+    ss = mg.StreamSet(wl.C1_STREAMS, seed=wl.C1_SEED)
+    got = host(ss.fill(wl.C1_N, mg.F64))
+    wantd, _ = oracle_fill(wl.C1_SEED, 0, wl.C1_STREAMS, wl.C1_N, oracle.F64)
+    assert np.array_equal(got.view(np.uint64), wantd.view(np.uint64))
+    # the first output of stream 0 is the worked example's
+    assert int(want[0, 0]) == 545508589
+    ss.close()
+
+
+@pytest.mark.parametrize("dtype", [0, 1, 2], ids=["u32", "f32", "f64"])
+@pytest.mark.parametrize("layout", [0, 1], ids=["sm", "il"])
+def test_ragged_shapes(mg, engine, dtype, layout):
+    base = oracle.seed_from_master(99)
+    for first, count, n in [(0, 1, 1), (3, 5, 33), (0, 63, 31), (1, 64, 32), (0, 65, 64),
+                            (7, 130, 100), (0, 129, 257), (2, 3, 0), (0, 200, 3)]:
+        say("ragged", engine, dtype, layout, first, count, n)
+        ss = mg.StreamSet(first + count + 2, seed=[int(x) for x in base])
+        out = ss.fill(n, dtype, layout, first=first, count=count)
+        got = host(out)
+        want, st = oracle_fill(base, first, count, n, dtype, layout)
+        assert got.shape == want.shape
+        assert np.array_equal(got.view(np.uint8), want.view(np.uint8)), (first, count, n)
+        assert np.array_equal(ss.get_states(first, count), st)
+        # untouched streams keep their start states
+        assert np.array_equal(ss.get_states(0, first), oracle.streams(base, 0, first))
+        ss.close()
+
+
+def test_unaligned_row_and_pointer(mg, engine):
+    import torch
+    base = oracle.seed_from_master(7)
+    say("unaligned", engine)
+    for n, off in [(37, 1), (40, 1), (64, 3)]:
+        ss = mg.StreamSet(70, seed=[int(x) for x in base])
+        buf = torch.zeros(70 * n + 8, dtype=torch.uint32, device="cuda")
+        ss.fill_ptr(n, mg.U32, mg.STREAM_MAJOR, buf.data_ptr() + 4 * off)
+        got = host(buf)[off:off + 70 * n].reshape(70, n)
+        want, _ = oracle_fill(base, 0, 70, n, oracle.U32)
+        assert np.array_equal(got, want)
+        ss.close()
+
+
+def test_chained_fills_equal_one_fill(mg, engine):
+    base = oracle.seed_from_master(11)
+    say("chained", engine)
+    ss = mg.StreamSet(77, seed=[int(x) for x in base])
+    parts = [host(ss.fill(n, mg.U32)) for n in (5, 32, 1, 100, 64)]
+    got = np.concatenate(parts, axis=1)
+    want, st = oracle_fill(base, 0, 77, 202, oracle.U32)
+    assert np.array_equal(got, want)
+    assert np.array_equal(ss.get_states(), st)
+    ss.close()
+
+
+def test_dtypes_share_one_sequence(mg, engine):
+    say("dtypes", engine)
+    u = mg.StreamSet(100, master_seed=5)
+    f = mg.StreamSet(100, master_seed=5)
+    d = mg.StreamSet(100, master_seed=5)
+    zu = host(u.fill(300, mg.U32)).astype(np.int64)
+    zf = host(f.fill(300, mg.F32))
+    zd = host(d.fill(300, mg.F64))
+    assert np.array_equal(zf, ((2 * ((zu - 1) >> 9) + 1) * 2.0**-24).astype(np.float32))
+    assert np.array_equal(zd, zu.astype(np.float64) * 2.328306549295727688e-10)
+    for s in (u, f, d):
+        s.close()
+
+
+def test_jump_per_stream_exponents(mg):
+    import torch
+    base = oracle.seed_from_master(21)
+    for bits in (17, 64, 100, 192):
+        say("jump bits", bits)
+        S = 333
+        ss = mg.StreamSet(S + 4, seed=[int(x) for x in base])
+        w = wl.random_exponents(S, bits, seed=bits)
+        ss.jump(torch.from_numpy(w.view(np.int64)).cuda(), first=2, count=S)
+        got = ss.get_states(2, S)
+        want = oracle.jump_many_words(oracle.streams(base, 2, S), w)
+        assert np.array_equal(got, want)
+        ss.close()
+
+
+def test_jump_uniform_and_substreams(mg):
+    base = oracle.seed_from_master(22)
+    ss = mg.StreamSet(50, seed=[int(x) for x in base])
+    say("jump uniform")
+    e = (1 << 150) + 12345
+    ss.jump_uniform(e, first=5, count=40)
+    want = oracle.jump_many(oracle.streams(base, 5, 40), e)
+    assert np.array_equal(ss.get_states(5, 40), want)
+    ss.jump_substreams(3, first=5, count=40)
+    want = oracle.jump_many(want, 3 << 76)
+    assert np.array_equal(ss.get_states(5, 40), want)
+    ss.close()
+
+
+def test_jump_zero_and_small_equal_stepping(mg):
+    import torch
+    base = oracle.seed_from_master(23)
+    say("jump small")
+    S = 64
+    ss = mg.StreamSet(S, seed=[int(x) for x in base])
+    e = np.arange(S, dtype=np.uint64)
+    w = np.zeros((S, 3), dtype=np.uint64)
+    w[:, 0] = e
+    ss.jump(torch.from_numpy(w.view(np.int64)).cuda())
+    got = ss.get_states()
+    st = oracle.streams(base, 0, S)
+    for i in range(S):
+        assert np.array_equal(got[i], oracle.skip(st[i], i))
+    ss.close()
+
+
+def test_streamset_first_stream_offset(mg):
+    say("first_stream offset")
+    base = oracle.seed_from_master(24)
+    for first in (1, 1000, 2**40 + 7, 2**64 - 10):
+        ss = mg.StreamSet(10, seed=[int(x) for x in base], first_stream=first)
+        assert np.array_equal(ss.get_states(), oracle.streams(base, first, 10))
+        ss.close()
+
+
+def test_state_roundtrip_and_validation(mg):
+    say("states")
+    ss = mg.StreamSet(10, master_seed=1)
+    st = ss.get_states()
+    st2 = st.copy()
+    st2[3] = [1, 2, 3, 4, 5, 6]
+    ss.set_states(st2)
+    assert np.array_equal(ss.get_states(), st2)
+    bad = st2.copy()
+    bad[0] = [0, 0, 0, 1, 1, 1]
+    with pytest.raises(mg.MRGError):
+        ss.set_states(bad)
+    assert np.array_equal(ss.get_states(), st2)
+    with pytest.raises(mg.MRGError):
+        ss.fill(4, first=8, count=5)
+    ss.close()
+
+
+def test_c3_full(mg, engine):
+    """2^16 streams, random 64-bit offsets plus one substream, 1024 outputs."""
+    import torch
+    say("C3 engine", engine)
+    base = oracle.seed_from_master(wl.MASTER_SEED)
+    S, n = wl.C3_STREAMS, wl.C3_N
+    ss = mg.StreamSet(S, master_seed=wl.MASTER_SEED)
+    off = wl.c3_offsets(S)
+    ss.jump(torch.from_numpy(wl.c3_exponents(off).view(np.int64)).cuda())
+    got = host(ss.fill(n, mg.U32))
+    st = oracle.streams(base, 0, S)
+    st = oracle.jump_many_words(st, np.stack([off, np.zeros_like(off), np.zeros_like(off)], 1))
+    st = oracle.jump_many(st, 1 << 76)
+    want, st2 = oracle.fill(st, n, oracle.U32)
+    assert np.array_equal(got, want)
+    assert np.array_equal(ss.get_states(), st2)
+    ss.close()
+
+
+@pytest.mark.parametrize("dtype", [0, 1], ids=["u32", "f32"])
+def test_c2_full_size_sampled(mg, dtype):
+    """The benchmark's launch: 2^20 streams x 4096 outputs (16 GiB).  Sampled
+    streams are recomputed by the oracle in full; every output is range
+    checked; end states of sampled streams equal the oracle's."""
+    import torch
+    say("C2 full", dtype)
+    base = oracle.seed_from_master(wl.MASTER_SEED)
+    S, n = wl.C2_STREAMS, wl.C2_N
+    ss = mg.StreamSet(S, master_seed=wl.MASTER_SEED)
+    out = ss.fill(n, dtype)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(1234)
+    idx = np.unique(np.concatenate([[0, 1, 63, 64, S - 1], rng.integers(0, S, 300)]))
+    rows = host(out[torch.from_numpy(idx).cuda()])
+    for j, g in enumerate(idx):
+        want, st = oracle.fill(oracle.stream_start(base, int(g))[None, :], n, dtype)
+        assert np.array_equal(rows[j].view(np.uint32), want[0].view(np.uint32)), g
+        assert np.array_equal(ss.get_states(int(g), 1)[0], st[0]), g
+    if dtype == 0:
+        o = out.view(torch.int32)
+        # uint32 values lie in [1, m1]: as int32, either >= 1 or <= m1 - 2^32
+        lo = (o >= 1) | (o <= oracle.M1 - 2**32)
+        assert bool(lo.all())
+    else:
+        assert bool(((out > 0) & (out < 1)).all())
+    del out
+    ss.close()
