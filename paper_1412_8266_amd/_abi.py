@@ -25,6 +25,14 @@ class MRGError(RuntimeError):
 
 
 def _load() -> ctypes.CDLL:
+    # PyTorch ships its own HIP runtime.  Importing it first makes the
+    # library's libamdhip64.so.7 / libhsa-runtime64.so.1 resolve to the copies
+    # already in the process, so that the library and torch share one runtime
+    # (two runtimes in one process cannot both open the device).
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             "libmrg32k3a_gpu.so is not built (expected at %s); build it with "

@@ -18,6 +18,8 @@ SOURCES = ["kernels.hip", "batch.hip", "host.cpp", "batch_host.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",
+    # code object v5: loadable by the HIP runtime bundled with PyTorch too
+    "-mcode-object-version=5",
     "-O3",
     "-std=c++17",
     "-fPIC",
