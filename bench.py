@@ -43,6 +43,8 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--engine", type=int, default=None, help="0 integer, 1 binary64")
     ap.add_argument("--tile-bytes", type=int, default=None)
+    ap.add_argument("--strategy", type=int, default=None, help="0 auto, 1 lane/stream, 2 wave/stream")
+    ap.add_argument("--coop-wgs-per-cu", type=int, default=None)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--quick", action="store_true", help="headline only (for profiling)")
     return ap.parse_args()
@@ -103,6 +105,10 @@ def main():
         mg.mrg_config_set("engine", args.engine)
     if args.tile_bytes is not None:
         mg.mrg_config_set("tile_bytes", args.tile_bytes)
+    if args.strategy is not None:
+        mg.mrg_config_set("strategy", args.strategy)
+    if args.coop_wgs_per_cu is not None:
+        mg.mrg_config_set("coop_wgs_per_cu", args.coop_wgs_per_cu)
     engine = mg.mrg_config_get("engine")
     tile = mg.mrg_config_get("tile_bytes")
     stream = torch.cuda.current_stream()

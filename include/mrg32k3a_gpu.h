@@ -175,8 +175,12 @@ mrg_status mrg_state_check(const uint32_t state6[6]);
 /* Process-wide tuning of the generation kernels (no effect on results):
  *   "engine"     0 = 32-bit integer arithmetic with lazy residues,
  *                1 = binary64 arithmetic with centred residues (default);
- *   "tile_bytes" bytes per stream per LDS tile of the stream-major fill,
- *                128 (default) or 256.
+ *   "tile_bytes" bytes per stream per LDS tile of the lane-per-stream
+ *                stream-major fill, 128 or 256 (default);
+ *   "strategy"   stream-major fill: 0 = automatic (default: one wave per
+ *                stream when a stream has at least 64 x 128 bytes of output,
+ *                else one lane per stream), 1 = always lane per stream,
+ *                2 = always wave per stream.
  * Unknown keys or values: MRG_EINVAL.  Takes effect for later launches. */
 mrg_status mrg_config_set(const char *key, int64_t value);
 mrg_status mrg_config_get(const char *key, int64_t *value);

@@ -122,8 +122,27 @@ const std::vector<uint32_t> &host_tables()
 
 // ---- per-device context ----------------------------------------------------
 struct DevCtx {
-    uint32_t *d_table = nullptr;
+    uint32_t *d_table = nullptr;     // windowed jump tables
+    uint32_t *d_lane_tab = nullptr;  // [3][64][18]: A^(l*L) for L in kLaneSegs
+    int cus = 256;                   // compute units of the device
 };
+
+// A^(l*L) for l in [0, 64) and each lane-segment length L, both components.
+std::vector<uint32_t> build_lane_tables()
+{
+    std::vector<uint32_t> t(3 * 64 * 18);
+    for (int k = 0; k < 3; ++k) {
+        const uint64_t L = (uint64_t)mrg::kLaneSegs[k];
+        for (int l = 0; l < 64; ++l) {
+            const uint64_t e[3] = {L * (uint64_t)l, 0, 0};
+            for (int c = 0; c < 2; ++c) {
+                const Mat P = power(c, e);
+                std::memcpy(&t[(k * 64 + l) * 18 + 9 * c], P.data(), 36);
+            }
+        }
+    }
+    return t;
+}
 
 std::mutex g_mu;
 std::map<int, DevCtx> g_dev;
@@ -162,6 +181,21 @@ mrg_status device_ctx(int dev, DevCtx **out)
         (void)hipFree(ctx.d_table);
         return hip_fail(e, "hipMemcpy(jump tables)");
     }
+    const std::vector<uint32_t> lt = build_lane_tables();
+    e = hipMalloc(&ctx.d_lane_tab, lt.size() * sizeof(uint32_t));
+    if (e != hipSuccess) {
+        (void)hipFree(ctx.d_table);
+        return fail(MRG_ENOMEM, "hipMalloc(lane tables): %s", hipGetErrorString(e));
+    }
+    e = hipMemcpy(ctx.d_lane_tab, lt.data(), lt.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        (void)hipFree(ctx.d_table);
+        (void)hipFree(ctx.d_lane_tab);
+        return hip_fail(e, "hipMemcpy(lane tables)");
+    }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
+        ctx.cus = cus;
     auto res = g_dev.emplace(dev, ctx);
     *out = &res.first->second;
     return MRG_OK;
@@ -397,8 +431,34 @@ mrg_status mrg_fill(mrg_streamset ss, uint64_t first, uint64_t count, uint64_t n
     if (n_per_stream > UINT64_MAX / es / count)
         return fail(MRG_ERANGE, "output size overflows 64 bits");
     const int vec_ok = ((uintptr_t)d_out % 16 == 0) && ((n_per_stream * es) % 16 == 0);
+    const mrg::FillTuning tune = tuning();
+    mrg::FillLaunch fl;
+    if (layout == MRG_STREAM_MAJOR) {
+        // wave per stream when a stream fills at least one chunk of 64 lanes x
+        // 128 bytes (or when forced); lane per stream for short streams
+        const uint64_t min_chunk = 64 * (128 / es);
+        const bool coop = tune.strategy == 2 || (tune.strategy == 0 && n_per_stream >= min_chunk);
+        if (coop) {
+            DevCtx *ctx;
+            if ((st = device_ctx(ss->device, &ctx))) return st;
+            // 256 bytes per lane per chunk for long streams, 128 otherwise
+            const int L = (int)(128 / es) * (n_per_stream >= 2 * min_chunk ? 2 : 1);
+            const int k = L == 16 ? 0 : (L == 32 ? 1 : 2);
+            fl.kernel = 1;
+            fl.L = L;
+            fl.lane_tab = ctx->d_lane_tab + k * 64 * 18;
+            const uint64_t e[3] = {n_per_stream, 0, 0};
+            const Mat P1 = power(0, e), P2 = power(1, e);
+            std::memcpy(fl.Mn.m, P1.data(), 36);
+            std::memcpy(fl.Mn.m + 9, P2.data(), 36);
+            // resident workgroups stride over the streams, or one per stream
+            const uint64_t cap = tune.coop_wgs_per_cu ? (uint64_t)ctx->cus * tune.coop_wgs_per_cu
+                                                      : ((uint64_t)1 << 31) - 1;
+            fl.grid = (unsigned)(count < cap ? count : cap);
+        }
+    }
     hipError_t e = mrg::launch_fill(ss->d_planes, ss->n, first, count, n_per_stream, (int)dtype,
-                                    (int)layout, d_out, vec_ok, tuning(), (hipStream_t)stream);
+                                    (int)layout, d_out, vec_ok, fl, tune, (hipStream_t)stream);
     return e == hipSuccess ? MRG_OK : hip_fail(e, "fill kernel launch");
 }
 
@@ -454,6 +514,12 @@ mrg_status mrg_config_set(const char *key, int64_t value)
     if (!std::strcmp(key, "engine")) {
         if (value != 0 && value != 1) return fail(MRG_EINVAL, "engine must be 0 or 1");
         g_tune.engine = (int)value;
+    } else if (!std::strcmp(key, "coop_wgs_per_cu")) {
+        if (value < 0 || value > 1024) return fail(MRG_EINVAL, "coop_wgs_per_cu must be in [0, 1024]");
+        g_tune.coop_wgs_per_cu = (int)value;
+    } else if (!std::strcmp(key, "strategy")) {
+        if (value < 0 || value > 2) return fail(MRG_EINVAL, "strategy must be 0, 1 or 2");
+        g_tune.strategy = (int)value;
     } else if (!std::strcmp(key, "tile_bytes")) {
         if (value != 128 && value != 256) return fail(MRG_EINVAL, "tile_bytes must be 128 or 256");
         g_tune.tile_bytes = (int)value;
@@ -469,6 +535,8 @@ mrg_status mrg_config_get(const char *key, int64_t *value)
     std::lock_guard<std::mutex> lk(g_mu);
     if (!std::strcmp(key, "engine")) *value = g_tune.engine;
     else if (!std::strcmp(key, "tile_bytes")) *value = g_tune.tile_bytes;
+    else if (!std::strcmp(key, "strategy")) *value = g_tune.strategy;
+    else if (!std::strcmp(key, "coop_wgs_per_cu")) *value = g_tune.coop_wgs_per_cu;
     else return fail(MRG_EINVAL, "unknown key '%s'", key);
     return MRG_OK;
 }

@@ -21,15 +21,31 @@ hipError_t launch_jump(uint32_t *planes, uint64_t plane_stride, uint64_t first, 
                        const uint64_t *d_exp, const uint32_t *table, hipStream_t st);
 hipError_t launch_jump_uniform(uint32_t *planes, uint64_t plane_stride, uint64_t first,
                                uint64_t count, const JumpMatrices &J, hipStream_t st);
-// Generation engine (0: integer lazy words, 1: binary64 centred words) and
-// bytes per row per LDS tile (128 or 256) of the stream-major fill.
+// Generation engine (0: integer lazy words, 1: binary64 centred words),
+// bytes per row per LDS tile (128 or 256) of the lane-per-stream fill, and
+// the stream-major strategy (0: automatic, 1: lane per stream, 2: wave per
+// stream).
 struct FillTuning {
     int engine = 1;
-    int tile_bytes = 128;
+    int tile_bytes = 256;
+    int strategy = 0;
+    int coop_wgs_per_cu = 0;  // wave per stream: 0 = one workgroup per stream
+};
+
+// Lane-segment lengths of the wave-per-stream fill and their tables.
+constexpr int kLaneSegs[3] = {16, 32, 64};
+
+// How one stream-major fill is launched (chosen on the host).
+struct FillLaunch {
+    int kernel = 0;                     // 0 lane per stream, 1 wave per stream
+    int L = 0;                          // values per lane per chunk (wave per stream)
+    const uint32_t *lane_tab = nullptr; // [64][18]: A^(l*L), component 1 then 2
+    JumpMatrices Mn = {};               // A^n: end state of each stream
+    unsigned grid = 0;                  // workgroups (wave per stream)
 };
 
 hipError_t launch_fill(uint32_t *planes, uint64_t plane_stride, uint64_t first, uint64_t count,
                        uint64_t n, int dtype, int layout, void *out, int vec_ok,
-                       const FillTuning &tune, hipStream_t st);
+                       const FillLaunch &fl, const FillTuning &tune, hipStream_t st);
 
 }  // namespace mrg

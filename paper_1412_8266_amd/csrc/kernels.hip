@@ -268,11 +268,18 @@ fill_sm_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t fi
         __syncthreads();
         const uint64_t off = t * TB;
         if (vec_ok) {
+            // all LDS reads first, one wait, then the stores
+            uint4 v[NJ];
 #pragma unroll
-            for (int j = 0; j < NJ; ++j) {
-                const int r = lane / LPR + RPI * j;
-                const uint4 v = *(const uint4 *)(lds + r * RS + chunk * 16);
-                if (rowa[j]) *(uint4 *)(rowp[j] + off) = v;
+            for (int j = 0; j < NJ; ++j)
+                v[j] = *(const uint4 *)(lds + (lane / LPR + RPI * j) * RS + chunk * 16);
+            if (nrows == 64) {
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) *(uint4 *)(rowp[j] + off) = v[j];
+            } else {
+#pragma unroll
+                for (int j = 0; j < NJ; ++j)
+                    if (rowa[j]) *(uint4 *)(rowp[j] + off) = v[j];
             }
         } else {
             // element stores: lane e covers (row e / TV, col e % TV)
@@ -343,6 +350,102 @@ fill_il_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t fi
     store_state(planes, plane_stride, idx, w);
 }
 
+// Stream-major output with one wave per stream (sequence splitting inside the
+// stream, sec. 2.3): the stream's n outputs are cut into chunks of 64*L
+// values and lane l generates the L consecutive values [l*L, l*L + L) of each
+// chunk, starting from A^(l*L) applied to the chunk's first state
+// (lane_tab[l], formed on the host).  The next chunk starts where lane 63
+// ended.  Every LDS flush then writes 64 pieces of 128 bytes that tile the
+// chunk's 64*L*ES contiguous bytes, so the HBM write stream is nearly
+// sequential.  The end state A^n * state (Mn) is written back by lane 0.
+// Workgroups stride over the streams so that the streams in flight stay
+// adjacent in memory.
+template <int DT, int L, class G>
+__global__ void __launch_bounds__(64)
+fill_coop_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t first,
+                 uint64_t count, uint64_t n, unsigned char *__restrict__ out, int vec_ok,
+                 const uint32_t *__restrict__ lane_tab, JumpMatrices Mn)
+{
+    constexpr int ES = Elem<DT>::size;
+    constexpr int TV = 128 / ES;   // values per 128-byte piece
+    constexpr int NH = L / TV;     // pieces per lane per chunk
+    constexpr int RS = 128 + 16;   // LDS row pitch (bytes)
+    static_assert(NH >= 1 && L % TV == 0, "chunk must be whole pieces");
+    __shared__ __attribute__((aligned(16))) unsigned char lds[64 * RS];
+
+    const int lane = threadIdx.x;
+    uint32_t m[18];
+#pragma unroll
+    for (int i = 0; i < 18; ++i) m[i] = lane_tab[lane * 18 + i];
+    unsigned char *my_lds = lds + lane * RS;
+    const uint64_t chunk_vals = (uint64_t)64 * L;
+    const uint64_t nchunks = (n + chunk_vals - 1) / chunk_vals;
+    const int prow = lane >> 3;        // flush: 8 lanes per 128-byte piece
+    const int pcol = (lane & 7) * 16;  //        8 pieces per instruction
+
+    // whole chunks only: the end state is lane 63's after the last chunk;
+    // otherwise it is A^n * state, computed up front
+    const bool whole = n % chunk_vals == 0;
+
+    for (uint64_t s = blockIdx.x; s < count; s += gridDim.x) {
+        const uint64_t idx = first + s;
+        uint32_t w[6];
+        load_state(planes, plane_stride, idx, w);
+        uint32_t fin[6] = {w[0], w[1], w[2], w[3], w[4], w[5]};
+        if (!whole) {
+            matvec3<C1>(Mn.m, fin[0], fin[1], fin[2]);
+            matvec3<C2>(Mn.m + 9, fin[3], fin[4], fin[5]);
+        }
+        unsigned char *srow = out + s * n * ES;
+
+        for (uint64_t c = 0; c < nchunks; ++c) {
+            uint32_t st[6] = {w[0], w[1], w[2], w[3], w[4], w[5]};
+            matvec3<C1>(m, st[0], st[1], st[2]);
+            matvec3<C2>(m + 9, st[3], st[4], st[5]);
+            G g;
+            g.load(st);
+            const uint64_t v0 = c * chunk_vals;
+            const bool full = v0 + chunk_vals <= n;
+            for (int h = 0; h < NH; ++h) {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) *(uint4 *)(my_lds + q * 16) = gen16<DT>(g);
+                __syncthreads();
+                if (full && vec_ok) {
+                    uint4 v[8];
+#pragma unroll
+                    for (int j = 0; j < 8; ++j)
+                        v[j] = *(const uint4 *)(lds + (prow + 8 * j) * RS + pcol);
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const uint64_t pos = v0 + (uint64_t)(prow + 8 * j) * L + h * TV;
+                        *(uint4 *)(srow + pos * ES + pcol) = v[j];
+                    }
+                } else {
+                    for (int e = lane; e < 64 * TV; e += 64) {
+                        const int r = e / TV, i = e % TV;
+                        const uint64_t pos = v0 + (uint64_t)r * L + h * TV + i;
+                        if (pos < n) {
+                            const unsigned char *src = lds + r * RS + i * ES;
+                            if constexpr (ES == 4) *(uint32_t *)(srow + pos * ES) = *(const uint32_t *)src;
+                            else *(uint64_t *)(srow + pos * ES) = *(const uint64_t *)src;
+                        }
+                    }
+                }
+                __syncthreads();
+            }
+            if (c + 1 < nchunks) {  // chunk c was full: lane 63 ends at the next chunk's start
+                uint32_t e[6];
+                g.store(e);
+#pragma unroll
+                for (int k = 0; k < 6; ++k) w[k] = __shfl(e[k], 63);
+            } else if (whole) {
+                g.store(fin);
+            }
+        }
+        if (lane == (whole ? 63 : 0)) store_state(planes, plane_stride, idx, fin);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // launchers (host side)
 // ---------------------------------------------------------------------------
@@ -384,21 +487,32 @@ hipError_t launch_jump_uniform(uint32_t *planes, uint64_t plane_stride, uint64_t
 
 template <int DT, class G>
 static hipError_t launch_fill_g(uint32_t *planes, uint64_t plane_stride, uint64_t first,
-                                uint64_t count, uint64_t n, int layout, void *out,
-                                int vec_ok, int tile_bytes, hipStream_t st)
+                                uint64_t count, uint64_t n, int layout, void *out, int vec_ok,
+                                const FillLaunch &fl, int tile_bytes, hipStream_t st)
 {
-    if (layout == 0) {
-        if (tile_bytes >= 256)
-            hipLaunchKernelGGL((fill_sm_kernel<DT, 256, G>), dim3(grid_of(count, 64)), dim3(64), 0,
-                               st, planes, plane_stride, first, count, n, (unsigned char *)out,
-                               vec_ok);
-        else
-            hipLaunchKernelGGL((fill_sm_kernel<DT, 128, G>), dim3(grid_of(count, 64)), dim3(64), 0,
-                               st, planes, plane_stride, first, count, n, (unsigned char *)out,
-                               vec_ok);
-    } else {
+    unsigned char *o = (unsigned char *)out;
+    if (layout == 1) {
         hipLaunchKernelGGL((fill_il_kernel<DT, G>), dim3(grid_of(count, 256)), dim3(256), 0, st,
-                           planes, plane_stride, first, count, n, (unsigned char *)out);
+                           planes, plane_stride, first, count, n, o);
+    } else if (fl.kernel == 1) {
+        const dim3 grid(fl.grid), block(64);
+        if (fl.L == 64 && DT != 2)
+            hipLaunchKernelGGL((fill_coop_kernel<DT, 64, G>), grid, block, 0, st, planes,
+                               plane_stride, first, count, n, o, vec_ok, fl.lane_tab, fl.Mn);
+        else if (fl.L == 32)
+            hipLaunchKernelGGL((fill_coop_kernel<DT, 32, G>), grid, block, 0, st, planes,
+                               plane_stride, first, count, n, o, vec_ok, fl.lane_tab, fl.Mn);
+        else if (fl.L == 16 && DT == 2)
+            hipLaunchKernelGGL((fill_coop_kernel<2, 16, G>), grid, block, 0, st, planes,
+                               plane_stride, first, count, n, o, vec_ok, fl.lane_tab, fl.Mn);
+        else
+            return hipErrorInvalidValue;
+    } else if (tile_bytes >= 256) {
+        hipLaunchKernelGGL((fill_sm_kernel<DT, 256, G>), dim3(grid_of(count, 64)), dim3(64), 0, st,
+                           planes, plane_stride, first, count, n, o, vec_ok);
+    } else {
+        hipLaunchKernelGGL((fill_sm_kernel<DT, 128, G>), dim3(grid_of(count, 64)), dim3(64), 0, st,
+                           planes, plane_stride, first, count, n, o, vec_ok);
     }
     return hipGetLastError();
 }
@@ -406,24 +520,24 @@ static hipError_t launch_fill_g(uint32_t *planes, uint64_t plane_stride, uint64_
 template <class G>
 static hipError_t launch_fill_d(uint32_t *planes, uint64_t plane_stride, uint64_t first,
                                 uint64_t count, uint64_t n, int dtype, int layout, void *out,
-                                int vec_ok, int tile_bytes, hipStream_t st)
+                                int vec_ok, const FillLaunch &fl, int tile_bytes, hipStream_t st)
 {
     switch (dtype) {
-    case 0: return launch_fill_g<0, G>(planes, plane_stride, first, count, n, layout, out, vec_ok, tile_bytes, st);
-    case 1: return launch_fill_g<1, G>(planes, plane_stride, first, count, n, layout, out, vec_ok, tile_bytes, st);
-    default: return launch_fill_g<2, G>(planes, plane_stride, first, count, n, layout, out, vec_ok, tile_bytes, st);
+    case 0: return launch_fill_g<0, G>(planes, plane_stride, first, count, n, layout, out, vec_ok, fl, tile_bytes, st);
+    case 1: return launch_fill_g<1, G>(planes, plane_stride, first, count, n, layout, out, vec_ok, fl, tile_bytes, st);
+    default: return launch_fill_g<2, G>(planes, plane_stride, first, count, n, layout, out, vec_ok, fl, tile_bytes, st);
     }
 }
 
 hipError_t launch_fill(uint32_t *planes, uint64_t plane_stride, uint64_t first, uint64_t count,
                        uint64_t n, int dtype, int layout, void *out, int vec_ok,
-                       const FillTuning &tune, hipStream_t st)
+                       const FillLaunch &fl, const FillTuning &tune, hipStream_t st)
 {
     if (tune.engine == 1)
         return launch_fill_d<GenF>(planes, plane_stride, first, count, n, dtype, layout, out,
-                                   vec_ok, tune.tile_bytes, st);
+                                   vec_ok, fl, tune.tile_bytes, st);
     return launch_fill_d<GenI>(planes, plane_stride, first, count, n, dtype, layout, out, vec_ok,
-                               tune.tile_bytes, st);
+                               fl, tune.tile_bytes, st);
 }
 
 }  // namespace mrg

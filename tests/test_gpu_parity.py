@@ -16,7 +16,10 @@ from paper_1412_8266_amd import workloads as wl
 
 pytestmark = pytest.mark.gpu
 
-ENGINES = [0, 1]
+# (engine, stream-major strategy): integer / binary64 arithmetic, lane per
+# stream / wave per stream
+CONFIGS = [(0, 1), (1, 1), (0, 2), (1, 2)]
+CONFIG_IDS = ["int-lane", "f64-lane", "int-wave", "f64-wave"]
 
 
 def say(*a):
@@ -32,12 +35,14 @@ def mg():
     return m
 
 
-@pytest.fixture(params=ENGINES, ids=["int", "f64"])
+@pytest.fixture(params=CONFIGS, ids=CONFIG_IDS)
 def engine(request, mg):
-    old = mg.mrg_config_get("engine")
-    mg.mrg_config_set("engine", request.param)
+    old = (mg.mrg_config_get("engine"), mg.mrg_config_get("strategy"))
+    mg.mrg_config_set("engine", request.param[0])
+    mg.mrg_config_set("strategy", request.param[1])
     yield request.param
-    mg.mrg_config_set("engine", old)
+    mg.mrg_config_set("engine", old[0])
+    mg.mrg_config_set("strategy", old[1])
 
 
 def host(t):
@@ -73,7 +78,9 @@ def test_c1_seed_12345_u32_then_f64(mg, engine):
 def test_ragged_shapes(mg, engine, dtype, layout):
     base = oracle.seed_from_master(99)
     for first, count, n in [(0, 1, 1), (3, 5, 33), (0, 63, 31), (1, 64, 32), (0, 65, 64),
-                            (7, 130, 100), (0, 129, 257), (2, 3, 0), (0, 200, 3)]:
+                            (7, 130, 100), (0, 129, 257), (2, 3, 0), (0, 200, 3),
+                            (1, 3, 2048), (0, 2, 4096), (2, 3, 4097), (0, 4, 9000),
+                            (0, 70, 1100)]:
         say("ragged", engine, dtype, layout, first, count, n)
         ss = mg.StreamSet(first + count + 2, seed=[int(x) for x in base])
         out = ss.fill(n, dtype, layout, first=first, count=count)
@@ -91,7 +98,7 @@ def test_unaligned_row_and_pointer(mg, engine):
     import torch
     base = oracle.seed_from_master(7)
     say("unaligned", engine)
-    for n, off in [(37, 1), (40, 1), (64, 3)]:
+    for n, off in [(37, 1), (40, 1), (64, 3), (2050, 1), (4096, 2)]:
         ss = mg.StreamSet(70, seed=[int(x) for x in base])
         buf = torch.zeros(70 * n + 8, dtype=torch.uint32, device="cuda")
         ss.fill_ptr(n, mg.U32, mg.STREAM_MAJOR, buf.data_ptr() + 4 * off)
@@ -105,9 +112,10 @@ def test_chained_fills_equal_one_fill(mg, engine):
     base = oracle.seed_from_master(11)
     say("chained", engine)
     ss = mg.StreamSet(77, seed=[int(x) for x in base])
-    parts = [host(ss.fill(n, mg.U32)) for n in (5, 32, 1, 100, 64)]
+    ns = (5, 32, 1, 100, 64, 4096, 2049)
+    parts = [host(ss.fill(n, mg.U32)) for n in ns]
     got = np.concatenate(parts, axis=1)
-    want, st = oracle_fill(base, 0, 77, 202, oracle.U32)
+    want, st = oracle_fill(base, 0, 77, sum(ns), oracle.U32)
     assert np.array_equal(got, want)
     assert np.array_equal(ss.get_states(), st)
     ss.close()
@@ -200,20 +208,33 @@ def test_state_roundtrip_and_validation(mg):
     ss.close()
 
 
+_C3_CACHE = {}
+
+
+def c3_expected():
+    """Oracle: stream starts, jump by the offsets, then by one substream, then
+    1024 outputs (computed once per session)."""
+    if "want" not in _C3_CACHE:
+        base = oracle.seed_from_master(wl.MASTER_SEED)
+        S, n = wl.C3_STREAMS, wl.C3_N
+        off = wl.c3_offsets(S)
+        st = oracle.streams(base, 0, S)
+        st = oracle.jump_many_words(st, np.stack([off, np.zeros_like(off), np.zeros_like(off)], 1))
+        st = oracle.jump_many(st, 1 << 76)
+        _C3_CACHE["want"] = oracle.fill(st, n, oracle.U32)
+    return _C3_CACHE["want"]
+
+
 def test_c3_full(mg, engine):
     """2^16 streams, random 64-bit offsets plus one substream, 1024 outputs."""
     import torch
     say("C3 engine", engine)
-    base = oracle.seed_from_master(wl.MASTER_SEED)
     S, n = wl.C3_STREAMS, wl.C3_N
     ss = mg.StreamSet(S, master_seed=wl.MASTER_SEED)
     off = wl.c3_offsets(S)
     ss.jump(torch.from_numpy(wl.c3_exponents(off).view(np.int64)).cuda())
     got = host(ss.fill(n, mg.U32))
-    st = oracle.streams(base, 0, S)
-    st = oracle.jump_many_words(st, np.stack([off, np.zeros_like(off), np.zeros_like(off)], 1))
-    st = oracle.jump_many(st, 1 << 76)
-    want, st2 = oracle.fill(st, n, oracle.U32)
+    want, st2 = c3_expected()
     assert np.array_equal(got, want)
     assert np.array_equal(ss.get_states(), st2)
     ss.close()
