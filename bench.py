@@ -33,20 +33,22 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
 METRIC = "uint32 Gsamples/s (% HBM write roofline), batched vs plain; p50/p99 latency"
 # HBM bytes per launch read by rocprofv3 (FETCH_SIZE + WRITE_SIZE, scaled by a
 # copy-kernel calibration); None until measured for the current kernel.
-COUNTER_TRAFFIC = None
+COUNTER_TRAFFIC = 17644557467  # fill_coop_kernel<u32,64>: profiles/fill_coop_u32_2p20x4096.md
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--engine", type=int, default=None, help="0 integer, 1 binary64")
     ap.add_argument("--tile-bytes", type=int, default=None)
     ap.add_argument("--strategy", type=int, default=None, help="0 auto, 1 lane/stream, 2 wave/stream")
     ap.add_argument("--coop-wgs-per-cu", type=int, default=None)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--quick", action="store_true", help="headline only (for profiling)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 2 GiB device-to-device copy 3 times (to scale HBM counters)")
     return ap.parse_args()
 
 
@@ -98,6 +100,14 @@ def main():
               "(streams shard by index with no exchange; see DESIGN.md)", file=sys.stderr)
         sys.exit(2)
     import torch
+    if args.copy_calibration:
+        src = torch.ones(1 << 29, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4}))
+        return
     import paper_1412_8266_amd as mg
     from paper_1412_8266_amd import workloads as wl
 
@@ -164,7 +174,8 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": COUNTER_TRAFFIC,
-            "kernel": "fill_sm_kernel<u32>",
+            "kernel": "fill_coop_kernel<u32>" if n >= 2048 and mg.mrg_config_get("strategy") != 1
+                      else "fill_sm_kernel<u32>",
             "alg_bytes_per_launch": alg_bytes,
             "avg_launch_ms": round(ms, 4),
         },
