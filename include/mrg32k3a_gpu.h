@@ -155,6 +155,93 @@ mrg_status mrg_set_states(mrg_streamset ss, uint64_t first, uint64_t count,
                           const uint32_t *h_in, void *stream);
 
 /* ---------------------------------------------------------------------- */
+/* Batched generation: many fill requests in one persistent launch         */
+/* ---------------------------------------------------------------------- */
+
+/* Request flag: the request's streams are substreams (sec. 4.1) of ONE
+ * stream of the set -- stream j of the request starts at that stream's state
+ * jumped by (substream0 + j) * 2^76 -- and the stored state is not changed. */
+#define MRG_REQ_SUBSTREAMS 1u
+
+/* One generation request.  Without flags it is exactly
+ * mrg_fill(set, first, count, n_per_stream, dtype, MRG_STREAM_MAJOR, d_out):
+ * streams first .. first+count-1 of the set, advanced by n_per_stream.
+ * With MRG_REQ_SUBSTREAMS, `first` names the one stream and count substreams
+ * starting at substream0 are generated.  d_out is device memory holding
+ * count * n_per_stream elements of dtype, stream-major, aligned to the
+ * element size (16 bytes enables vector stores).  Requests with count or
+ * n_per_stream equal to 0 are skipped. */
+typedef struct {
+    uint64_t first;
+    uint64_t count;
+    uint64_t n_per_stream;
+    uint64_t substream0;
+    void *d_out;
+    int32_t dtype;    /* mrg_dtype */
+    uint32_t flags;   /* 0 or MRG_REQ_SUBSTREAMS */
+} mrg_request;
+
+#define MRG_SCHEDULE_DYNAMIC 1u /* waves claim work items from an atomic counter */
+#define MRG_SCHEDULE_STATIC 2u  /* wave w takes items w, w + grid, ... */
+
+/* Work decomposition of a batch (0 in any field selects its default). */
+typedef struct {
+    uint64_t segment_bytes;   /* output bytes per work item of a long stream (256 KiB) */
+    uint64_t wave_min_bytes;  /* streams of at least this many output bytes get a whole
+                                 wave per segment, shorter ones one lane each (16 KiB) */
+    uint32_t waves_per_cu;    /* persistent one-wave workgroups per compute unit (16) */
+    uint32_t schedule;        /* MRG_SCHEDULE_DYNAMIC (default) or MRG_SCHEDULE_STATIC */
+} mrg_batch_config;
+
+typedef struct {
+    uint64_t requests;        /* non-empty requests */
+    uint64_t items;           /* work items */
+    uint64_t samples;         /* outputs per run */
+    uint64_t bytes;           /* output bytes per run */
+    uint64_t scratch_states;  /* end states staged before copy-back */
+    uint32_t grid;            /* persistent workgroups */
+    uint32_t pad;
+    mrg_batch_config config;  /* effective configuration */
+} mrg_batch_info_t;
+
+typedef struct mrg_batch_s *mrg_batch;
+
+/* Plan a batch over stream set ss: validate the requests (plain requests
+ * must cover disjoint stream ranges, else MRG_EINVAL), cut them into one-wave
+ * work items, upload the plan and capture one hipGraph (counter reset,
+ * persistent kernel, copy-back of end states).  reqs is copied; cfg may be
+ * NULL.  The plan refers to ss and to the output buffers, which must outlive
+ * it.  Free with mrg_batch_destroy. */
+mrg_status mrg_batch_create(mrg_batch *out, mrg_streamset ss, const mrg_request *reqs,
+                            uint64_t n_reqs, const mrg_batch_config *cfg);
+
+/* Run the batch: one hipGraph launch on `stream` (asynchronous).  Every run
+ * continues the plain requests' streams, like repeating the fills. */
+mrg_status mrg_batch_run(mrg_batch b, void *stream);
+
+/* Same kernels launched directly on `stream` instead of through the graph. */
+mrg_status mrg_batch_run_direct(mrg_batch b, void *stream);
+
+/* Reference schedule with the same results: one launch per request (plain
+ * requests through mrg_fill, substream requests through the batch kernel
+ * restricted to that request). */
+mrg_status mrg_batch_run_per_request(mrg_batch b, void *stream);
+
+mrg_status mrg_batch_info(mrg_batch b, mrg_batch_info_t *info);
+
+/* Time each candidate configuration (reps runs after one warm-up, on
+ * `stream`), keep the fastest and re-plan with it.  The stream states are
+ * restored afterwards, so autotuning has no visible effect on results.
+ * best_out (may be NULL) receives the chosen index; ms_out (may be NULL,
+ * else n_cands floats) the average milliseconds per run of each candidate.
+ * Synchronous. */
+mrg_status mrg_batch_autotune(mrg_batch b, const mrg_batch_config *cands, uint32_t n_cands,
+                              uint32_t reps, void *stream, uint32_t *best_out, float *ms_out);
+
+/* Release the plan (synchronises the device first).  NULL is ignored. */
+mrg_status mrg_batch_destroy(mrg_batch b);
+
+/* ---------------------------------------------------------------------- */
 /* Host-only helpers (no device work; usable without a GPU)               */
 /* ---------------------------------------------------------------------- */
 

@@ -157,3 +157,68 @@ __all__ = [
     "mrg_seed_from_master", "mrg_jump_matrix", "mrg_state_check", "mrg_config_set",
     "mrg_config_get", "mrg_version", "torch_dtype",
 ]
+
+
+# ---------------------------------------------------------------------------
+# batched generation
+# ---------------------------------------------------------------------------
+from ._abi import MRG_REQ_SUBSTREAMS, MRG_SCHEDULE_DYNAMIC, MRG_SCHEDULE_STATIC  # noqa: E402
+
+REQ_SUBSTREAMS = MRG_REQ_SUBSTREAMS
+SCHEDULE_DYNAMIC, SCHEDULE_STATIC = MRG_SCHEDULE_DYNAMIC, MRG_SCHEDULE_STATIC
+
+
+def batch_config(segment_bytes=0, wave_min_bytes=0, waves_per_cu=0, schedule=0):
+    return _abi.make_config(segment_bytes, wave_min_bytes, waves_per_cu, schedule)
+
+
+class Batch:
+    """Many fill requests over one StreamSet run by one persistent,
+    hipGraph-captured launch.
+
+    ``requests`` rows are (first, count, n_per_stream, substream0, d_out,
+    dtype, flags); d_out is a device pointer (int) to a [count, n] array.
+    The outputs and the stream set must outlive the batch.
+    """
+
+    def __init__(self, streamset: StreamSet, requests, config=None):
+        rows = list(requests)
+        self._arr = _abi.make_requests(rows)
+        self.n_requests = len(rows)
+        self.streamset = streamset
+        self._h = _abi.mrg_batch_create(streamset.handle, self._arr, len(rows), config)
+
+    def run(self, stream=None) -> None:
+        _abi.mrg_batch_run(self._h, _stream_handle(stream))
+
+    def run_direct(self, stream=None) -> None:
+        _abi.mrg_batch_run_direct(self._h, _stream_handle(stream))
+
+    def run_per_request(self, stream=None) -> None:
+        _abi.mrg_batch_run_per_request(self._h, _stream_handle(stream))
+
+    def info(self) -> dict:
+        return _abi.mrg_batch_info(self._h)
+
+    def autotune(self, configs, reps: int = 1, stream=None):
+        return _abi.mrg_batch_autotune(self._h, configs, reps, _stream_handle(stream))
+
+    def close(self) -> None:
+        if getattr(self, "_h", None):
+            _abi.mrg_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+
+__all__ += ["Batch", "batch_config", "REQ_SUBSTREAMS", "SCHEDULE_DYNAMIC", "SCHEDULE_STATIC"]

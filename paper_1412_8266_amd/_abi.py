@@ -67,6 +67,40 @@ _SIGS = {
     "mrg_config_set": [ctypes.c_char_p, _I64],
     "mrg_config_get": [ctypes.c_char_p, ctypes.POINTER(_I64)],
 }
+MRG_REQ_SUBSTREAMS = 1
+MRG_SCHEDULE_DYNAMIC, MRG_SCHEDULE_STATIC = 1, 2
+
+
+class mrg_request(ctypes.Structure):
+    _fields_ = [("first", ctypes.c_uint64), ("count", ctypes.c_uint64),
+                ("n_per_stream", ctypes.c_uint64), ("substream0", ctypes.c_uint64),
+                ("d_out", ctypes.c_void_p), ("dtype", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class mrg_batch_config(ctypes.Structure):
+    _fields_ = [("segment_bytes", ctypes.c_uint64), ("wave_min_bytes", ctypes.c_uint64),
+                ("waves_per_cu", ctypes.c_uint32), ("schedule", ctypes.c_uint32)]
+
+
+class mrg_batch_info_t(ctypes.Structure):
+    _fields_ = [("requests", ctypes.c_uint64), ("items", ctypes.c_uint64),
+                ("samples", ctypes.c_uint64), ("bytes", ctypes.c_uint64),
+                ("scratch_states", ctypes.c_uint64), ("grid", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32), ("config", mrg_batch_config)]
+
+
+_SIGS.update({
+    "mrg_batch_create": [ctypes.POINTER(_P), _P, ctypes.POINTER(mrg_request), _U64,
+                         ctypes.POINTER(mrg_batch_config)],
+    "mrg_batch_run": [_P, _P],
+    "mrg_batch_run_direct": [_P, _P],
+    "mrg_batch_run_per_request": [_P, _P],
+    "mrg_batch_info": [_P, ctypes.POINTER(mrg_batch_info_t)],
+    "mrg_batch_autotune": [_P, ctypes.POINTER(mrg_batch_config), ctypes.c_uint32, ctypes.c_uint32,
+                           _P, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_float)],
+    "mrg_batch_destroy": [_P],
+})
+
 for _name, _args in _SIGS.items():
     _f = getattr(lib, _name)
     _f.argtypes = _args
@@ -196,3 +230,58 @@ def mrg_last_error() -> str:
 
 def mrg_version() -> int:
     return int(lib.mrg_version())
+
+
+def make_requests(rows) -> "ctypes.Array":
+    """rows: iterable of (first, count, n_per_stream, substream0, d_out, dtype, flags)."""
+    rows = list(rows)
+    arr = (mrg_request * max(len(rows), 1))()
+    for i, r in enumerate(rows):
+        arr[i] = mrg_request(*[int(v) for v in r])
+    return arr
+
+
+def make_config(segment_bytes=0, wave_min_bytes=0, waves_per_cu=0, schedule=0):
+    return mrg_batch_config(segment_bytes, wave_min_bytes, waves_per_cu, schedule)
+
+
+def mrg_batch_create(ss: int, reqs, n_reqs: int, cfg=None) -> int:
+    h = _P()
+    _call("mrg_batch_create", ctypes.byref(h), ss, reqs, n_reqs,
+          ctypes.byref(cfg) if cfg is not None else None)
+    return h.value
+
+
+def mrg_batch_run(b: int, stream: int = 0) -> None:
+    _call("mrg_batch_run", b, stream)
+
+
+def mrg_batch_run_direct(b: int, stream: int = 0) -> None:
+    _call("mrg_batch_run_direct", b, stream)
+
+
+def mrg_batch_run_per_request(b: int, stream: int = 0) -> None:
+    _call("mrg_batch_run_per_request", b, stream)
+
+
+def mrg_batch_info(b: int) -> dict:
+    info = mrg_batch_info_t()
+    _call("mrg_batch_info", b, ctypes.byref(info))
+    c = info.config
+    return {"requests": info.requests, "items": info.items, "samples": info.samples,
+            "bytes": info.bytes, "scratch_states": info.scratch_states, "grid": info.grid,
+            "segment_bytes": c.segment_bytes, "wave_min_bytes": c.wave_min_bytes,
+            "waves_per_cu": c.waves_per_cu, "schedule": c.schedule}
+
+
+def mrg_batch_autotune(b: int, configs, reps: int = 1, stream: int = 0):
+    n = len(configs)
+    arr = (mrg_batch_config * n)(*configs)
+    best = ctypes.c_uint32()
+    ms = (ctypes.c_float * n)()
+    _call("mrg_batch_autotune", b, arr, n, reps, stream, ctypes.byref(best), ms)
+    return best.value, list(ms)
+
+
+def mrg_batch_destroy(b: int) -> None:
+    _call("mrg_batch_destroy", b)

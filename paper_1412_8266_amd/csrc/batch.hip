@@ -1,0 +1,164 @@
+// Persistent batched generation: many fill requests of uneven stream counts
+// and lengths in one launch.
+//
+// Each request is cut into work items of one wave:
+//   - a wave item is one segment [v0, v1) of one stream, written with
+//     wave_fill (lane l owns consecutive L-value pieces); the segment's first
+//     state is the stream's state jumped by v0 with the windowed tables
+//     (sequence splitting inside a stream, sec. 2.3);
+//   - a row item is up to 64 streams of a short-stream request, one per lane,
+//     written with rows_fill.
+// Persistent workgroups (one wave each) claim items from a global counter or
+// take them round robin; item i belongs to the request r with
+// prefix[r] <= i < prefix[r+1].  A request in substream mode draws its streams
+// from one stream: stream j is substream sub0 + j, i.e. that stream's state
+// jumped by (sub0 + j) * 2^76 (sec. 4.1), and leaves the state unchanged.
+// Otherwise each stream's end state is written back: in place when one item
+// covers the stream, else to a scratch slot that batch_copyback_kernel moves
+// to the state planes after the persistent kernel (a later segment of the
+// same stream may still be reading the old state).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "batch.h"
+#include "gen_device.hpp"
+
+namespace mrg {
+
+__global__ void batch_reset_kernel(unsigned long long *counter) { *counter = 0ull; }
+
+__device__ __forceinline__ uint32_t find_req(const uint64_t *__restrict__ prefix, uint32_t nreq,
+                                             uint64_t item)
+{
+    uint32_t lo = 0, hi = nreq;  // prefix[lo] <= item < prefix[hi]
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (prefix[mid] <= item) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src)
+{
+    const uint32_t lo = __shfl((uint32_t)v, src), hi = __shfl((uint32_t)(v >> 32), src);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+template <int DT, class G>
+__device__ void wave_item(const BatchReq &R, uint64_t local, unsigned char *lds, int lane,
+                          const BatchArgs &A)
+{
+    constexpr int ES = Elem<DT>::size;
+    constexpr int L = ES == 4 ? 64 : 32;  // 256 bytes per lane per chunk
+    constexpr int k = L == 64 ? 2 : 1;    // index into kLaneSegs {16, 32, 64}
+    const uint64_t j = local / R.segs, q = local % R.segs;
+    const uint64_t v0 = q * R.seg;
+    const uint64_t v1 = v0 + R.seg < R.n ? v0 + R.seg : R.n;
+    const bool subs = R.flags & kReqSubstreams;
+    uint32_t w[6];
+    load_state(A.planes, A.plane_stride, subs ? R.stream0 : R.stream0 + j, w);
+    const uint64_t sub = subs ? R.sub0 + j : 0;
+    // exponent v0 + sub * 2^76 (v0 < 2^64: no carry between the words)
+    jump_global(A.table, v0, sub << 12, sub >> 52, 0, kTableWindows, w);
+    uint32_t m[18];
+#pragma unroll
+    for (int i = 0; i < 18; ++i) m[i] = A.lane_tab[(k * 64 + lane) * 18 + i];
+    const bool whole = wave_fill<DT, L, G>(w, m, lds, lane, R.out + j * R.n * ES, v0, v1,
+                                           R.vec_ok != 0);
+    if ((R.flags & kReqWriteBack) && v1 == R.n) {
+        if (!whole) jump_global(A.table, (v1 - v0) % ((uint64_t)64 * L), 0, 0, 0, 16, w);
+        if (lane == 0) {
+            if (R.segs == 1) store_state(A.planes, A.plane_stride, R.stream0 + j, w);
+            else store_state(A.scratch, A.scratch_stride, R.scratch0 + j, w);
+        }
+    }
+}
+
+template <int DT, class G>
+__device__ void row_item(const BatchReq &R, uint64_t local, unsigned char *lds, int lane,
+                         const BatchArgs &A)
+{
+    constexpr int ES = Elem<DT>::size;
+    const uint64_t r0 = local * 64;
+    const uint64_t nrows = R.k - r0 < 64 ? R.k - r0 : 64;
+    const bool active = (uint64_t)lane < nrows;
+    const uint64_t j = r0 + lane;
+    const bool subs = R.flags & kReqSubstreams;
+    uint32_t w[6] = {1u, 1u, 1u, 1u, 1u, 1u};
+    if (active) load_state(A.planes, A.plane_stride, subs ? R.stream0 : R.stream0 + j, w);
+    if (subs) {
+        const uint64_t sub = active ? R.sub0 + j : 0;
+        jump_global(A.table, 0, sub << 12, sub >> 52, 19, kTableWindows, w);
+    }
+    G g;
+    g.load(w);
+    rows_fill<DT, 128, G>(g, lds, lane, nrows, R.out + r0 * R.n * ES, R.n * ES, R.n,
+                          R.vec_ok != 0);
+    if ((R.flags & kReqWriteBack) && active) {
+        g.store(w);
+        store_state(A.planes, A.plane_stride, R.stream0 + j, w);
+    }
+}
+
+template <class G>
+__global__ void __launch_bounds__(64) batch_kernel(BatchArgs A)
+{
+    __shared__ __attribute__((aligned(16))) unsigned char lds[64 * 144];
+    const int lane = threadIdx.x;
+    uint64_t next = blockIdx.x;  // static schedule: blockIdx.x + t * gridDim.x
+    for (;;) {
+        uint64_t item;
+        if (A.dynamic) {
+            uint64_t mine = 0;
+            if (lane == 0) mine = atomicAdd(A.counter, 1ull);
+            item = shfl64(mine, 0);
+        } else {
+            item = next;
+            next += gridDim.x;
+        }
+        if (item >= A.total_items) break;
+        const uint32_t r = find_req(A.prefix, A.nreq, item);
+        const BatchReq R = A.reqs[r];
+        const uint64_t local = item - A.prefix[r];
+        if (R.seg) {
+            if (R.dtype == 0) wave_item<0, G>(R, local, lds, lane, A);
+            else if (R.dtype == 1) wave_item<1, G>(R, local, lds, lane, A);
+            else wave_item<2, G>(R, local, lds, lane, A);
+        } else {
+            if (R.dtype == 0) row_item<0, G>(R, local, lds, lane, A);
+            else if (R.dtype == 1) row_item<1, G>(R, local, lds, lane, A);
+            else row_item<2, G>(R, local, lds, lane, A);
+        }
+    }
+}
+
+// Move the end states of multi-segment streams from scratch to the planes.
+// Copy-back slot s belongs to entry e with cb_prefix[e] <= s < cb_prefix[e+1];
+// it is stream cb_stream0[e] + (s - cb_prefix[e]) and scratch slot
+// cb_scratch0[e] + (s - cb_prefix[e]).
+__global__ void __launch_bounds__(256) batch_copyback_kernel(BatchArgs A)
+{
+    const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= A.cb_slots) return;
+    const uint32_t e = find_req(A.cb_prefix, A.n_cb, s);
+    const uint64_t off = s - A.cb_prefix[e];
+    uint32_t w[6];
+    load_state(A.scratch, A.scratch_stride, A.cb_scratch0[e] + off, w);
+    store_state(A.planes, A.plane_stride, A.cb_stream0[e] + off, w);
+}
+
+hipError_t launch_batch(const BatchArgs &A, unsigned grid, int engine, hipStream_t st)
+{
+    if (A.dynamic) hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(1), 0, st, A.counter);
+    if (engine == 1)
+        hipLaunchKernelGGL(batch_kernel<GenF>, dim3(grid), dim3(64), 0, st, A);
+    else
+        hipLaunchKernelGGL(batch_kernel<GenI>, dim3(grid), dim3(64), 0, st, A);
+    if (A.cb_slots)
+        hipLaunchKernelGGL(batch_copyback_kernel, dim3((unsigned)((A.cb_slots + 255) / 256)),
+                           dim3(256), 0, st, A);
+    return hipGetLastError();
+}
+
+}  // namespace mrg

@@ -1,0 +1,301 @@
+// Device building blocks shared by the fill kernels and the persistent batch
+// kernel: the two generator engines, 16-byte output packing, state planes,
+// jump-table application, and the two LDS-staged writers
+//   rows_fill -- one stream per lane (rows of the LDS tile are streams);
+//   wave_fill -- one stream per wave, lane l owning consecutive L-value
+//                segments, so that each flush tiles contiguous memory.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.h"
+#include "mrg_arith.hpp"
+
+namespace mrg {
+
+// Digit w (4 bits) of a 192-bit exponent given as 3 little-endian words.
+__device__ __forceinline__ uint32_t exp_digit(uint64_t e0, uint64_t e1, uint64_t e2, int w)
+{
+    const uint64_t word = w < 16 ? e0 : (w < 32 ? e1 : e2);
+    return (uint32_t)(word >> (4 * (w & 15))) & 15u;
+}
+
+// st <- A^e st with the tables read from global memory (L2-resident), over
+// windows [w_lo, w_hi).  Windows whose digit is zero in every lane are
+// skipped; when e is the same in every lane the table reads are uniform.
+__device__ __forceinline__ void jump_global(const uint32_t *__restrict__ table, uint64_t e0,
+                                            uint64_t e1, uint64_t e2, int w_lo, int w_hi,
+                                            uint32_t *st)
+{
+    for (int w = w_lo; w < w_hi; ++w) {
+        const uint32_t d = exp_digit(e0, e1, e2, w);
+        if (!__any(d != 0u)) continue;
+        if (d == 0u) continue;  // this lane's identity (exec-masked)
+        matvec3<C1>(table + ((0 * kTableWindows + w) * 16 + d) * 9, st[0], st[1], st[2]);
+        matvec3<C2>(table + ((1 * kTableWindows + w) * 16 + d) * 9, st[3], st[4], st[5]);
+    }
+}
+
+// Integer generator: lazy 32-bit words, v_mad_u64_u32 product-sums.  The
+// multipliers live in VGPRs so that each v_mad_u64_u32 can take the constant
+// addend K from an SGPR pair (one scalar operand per VOP3 instruction).
+struct GenI {
+    uint32_t a0, a1, a2, b0, b1, b2;  // lazy words, oldest first
+    uint32_t m13, m12, m23, m21;      // multipliers held in VGPRs
+
+    __device__ __forceinline__ void load(const uint32_t *w)
+    {
+        a0 = w[0]; a1 = w[1]; a2 = w[2]; b0 = w[3]; b1 = w[4]; b2 = w[5];
+        m13 = A13N; m12 = A12; m23 = A23N; m21 = A21;
+        asm volatile("" : "+v"(m13), "+v"(m12), "+v"(m23), "+v"(m21));
+    }
+    __device__ __forceinline__ void store(uint32_t *w) const
+    {
+        w[0] = canon1(a0); w[1] = canon1(a1); w[2] = canon1(a2);
+        w[3] = canon2(b0); w[4] = canon2(b1); w[5] = canon2(b2);
+    }
+    __device__ __forceinline__ uint32_t step()
+    {
+        const uint32_t p1 = next1(a0, a1, m13, m12);
+        const uint32_t p2 = next2(b0, b2, m23, m21);
+        a0 = a1; a1 = a2; a2 = p1;
+        b0 = b1; b1 = b2; b2 = p2;
+        return combine(p1, p2);
+    }
+    __device__ __forceinline__ uint32_t next_u32() { return step(); }
+    __device__ __forceinline__ float next_f32() { return to_f32(step()); }
+    __device__ __forceinline__ double next_f64() { return to_f64(step()); }
+};
+
+// Binary64 generator: centred integer-valued doubles, five FP64 operations
+// per component per step.
+struct GenF {
+    double a0, a1, a2, b0, b1, b2;
+
+    __device__ __forceinline__ void load(const uint32_t *w)
+    {
+        a0 = w[0]; a1 = w[1]; a2 = w[2]; b0 = w[3]; b1 = w[4]; b2 = w[5];
+    }
+    __device__ __forceinline__ void store(uint32_t *w) const
+    {
+        w[0] = canonf(a0, M1D); w[1] = canonf(a1, M1D); w[2] = canonf(a2, M1D);
+        w[3] = canonf(b0, M2D); w[4] = canonf(b1, M2D); w[5] = canonf(b2, M2D);
+    }
+    __device__ __forceinline__ double step()
+    {
+        const double r1 = next1f(a0, a1);
+        const double r2 = next2f(b0, b2);
+        a0 = a1; a1 = a2; a2 = r1;
+        b0 = b1; b1 = b2; b2 = r2;
+        return combinef(r1, r2);
+    }
+    __device__ __forceinline__ uint32_t next_u32() { return (uint32_t)step(); }
+    __device__ __forceinline__ float next_f32() { return to_f32f(step()); }
+    __device__ __forceinline__ double next_f64() { return to_f64f(step()); }
+};
+
+template <int DT> struct Elem;
+template <> struct Elem<0> { static constexpr int size = 4; };
+template <> struct Elem<1> { static constexpr int size = 4; };
+template <> struct Elem<2> { static constexpr int size = 8; };
+
+// 16 bytes of output: 4 uint32 / 4 float / 2 double values.
+template <int DT, class G>
+__device__ __forceinline__ uint4 gen16(G &g)
+{
+    uint4 v;
+    if constexpr (DT == 0) {
+        v.x = g.next_u32(); v.y = g.next_u32(); v.z = g.next_u32(); v.w = g.next_u32();
+    } else if constexpr (DT == 1) {
+        v.x = __float_as_uint(g.next_f32());
+        v.y = __float_as_uint(g.next_f32());
+        v.z = __float_as_uint(g.next_f32());
+        v.w = __float_as_uint(g.next_f32());
+    } else {
+        const uint64_t u0 = (uint64_t)__double_as_longlong(g.next_f64());
+        const uint64_t u1 = (uint64_t)__double_as_longlong(g.next_f64());
+        v.x = (uint32_t)u0; v.y = (uint32_t)(u0 >> 32);
+        v.z = (uint32_t)u1; v.w = (uint32_t)(u1 >> 32);
+    }
+    return v;
+}
+
+template <int DT, class G>
+__device__ __forceinline__ void put1(unsigned char *p, G &g)
+{
+    if constexpr (DT == 0) *(uint32_t *)p = g.next_u32();
+    else if constexpr (DT == 1) *(float *)p = g.next_f32();
+    else *(double *)p = g.next_f64();
+}
+
+__device__ __forceinline__ void load_state(const uint32_t *planes, uint64_t stride, uint64_t idx,
+                                           uint32_t *w)
+{
+#pragma unroll
+    for (int c = 0; c < 6; ++c) w[c] = planes[c * stride + idx];
+}
+
+__device__ __forceinline__ void store_state(uint32_t *planes, uint64_t stride, uint64_t idx,
+                                            const uint32_t *w)
+{
+#pragma unroll
+    for (int c = 0; c < 6; ++c) planes[c * stride + idx] = w[c];
+}
+
+template <int ES>
+__device__ __forceinline__ void copy_elem(unsigned char *dst, const unsigned char *src)
+{
+    if constexpr (ES == 4) *(uint32_t *)dst = *(const uint32_t *)src;
+    else *(uint64_t *)dst = *(const uint64_t *)src;
+}
+
+// ---------------------------------------------------------------------------
+// rows_fill: one wave, lane r generates n values of its own stream (rows
+// r < nrows are written).  Each full tile of TB bytes per row goes through the
+// lane's LDS row and is written back as 16-byte chunks, TB/16 lanes per row,
+// so one store instruction covers 64*16/TB rows x TB contiguous bytes.  The
+// row pitch TB+16 keeps both the b128 writes (lanes on different rows) and
+// the reads (lanes along a row) free of bank conflicts.  Row r's output starts
+// at out0 + r * row_stride.  `lds` holds 64 * (TB + 16) bytes; the caller's
+// workgroup is this one wave.
+// ---------------------------------------------------------------------------
+template <int DT, int TB, class G>
+__device__ __forceinline__ void rows_fill(G &g, unsigned char *lds, int lane, uint64_t nrows,
+                                          unsigned char *out0, uint64_t row_stride, uint64_t n,
+                                          bool vec_ok)
+{
+    constexpr int ES = Elem<DT>::size;
+    constexpr int TV = TB / ES;      // values per row per tile
+    constexpr int RS = TB + 16;      // LDS row pitch (bytes)
+    constexpr int LPR = TB / 16;     // lanes per row when flushing
+    constexpr int RPI = 64 / LPR;    // rows per flush instruction
+    constexpr int NJ = 64 / RPI;     // flush instructions per tile
+
+    unsigned char *my_lds = lds + lane * RS;
+    const int chunk = lane % LPR;
+    unsigned char *rowp[NJ];
+    bool rowa[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const int r = lane / LPR + RPI * j;
+        rowa[j] = (uint64_t)r < nrows;
+        rowp[j] = out0 + (uint64_t)r * row_stride + chunk * 16;
+    }
+
+    const uint64_t nfull = n / TV;
+    for (uint64_t t = 0; t < nfull; ++t) {
+#pragma unroll
+        for (int c = 0; c < TB / 16; ++c) *(uint4 *)(my_lds + c * 16) = gen16<DT>(g);
+        __syncthreads();
+        const uint64_t off = t * TB;
+        if (vec_ok) {
+            // all LDS reads first, one wait, then the stores
+            uint4 v[NJ];
+#pragma unroll
+            for (int j = 0; j < NJ; ++j)
+                v[j] = *(const uint4 *)(lds + (lane / LPR + RPI * j) * RS + chunk * 16);
+            if (nrows == 64) {
+#pragma unroll
+                for (int j = 0; j < NJ; ++j) *(uint4 *)(rowp[j] + off) = v[j];
+            } else {
+#pragma unroll
+                for (int j = 0; j < NJ; ++j)
+                    if (rowa[j]) *(uint4 *)(rowp[j] + off) = v[j];
+            }
+        } else {
+            // element stores: lane e covers (row e / TV, col e % TV)
+            for (int e = lane; e < 64 * TV; e += 64) {
+                const int r = e / TV, col = e % TV;
+                if ((uint64_t)r < nrows)
+                    copy_elem<ES>(out0 + (uint64_t)r * row_stride + off + (uint64_t)col * ES,
+                                  lds + r * RS + col * ES);
+            }
+        }
+        __syncthreads();
+    }
+    // tail: fewer than TV values per row
+    const int tail = (int)(n - nfull * TV);
+    if (tail) {
+        for (int c = 0; c < tail; ++c) put1<DT>(my_lds + c * ES, g);
+        __syncthreads();
+        const uint64_t off = nfull * TB;
+        for (int e = lane; e < 64 * tail; e += 64) {
+            const int r = e / tail, col = e % tail;
+            if ((uint64_t)r < nrows)
+                copy_elem<ES>(out0 + (uint64_t)r * row_stride + off + (uint64_t)col * ES,
+                              lds + r * RS + col * ES);
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// wave_fill: values [v0, v1) of one stream whose state at v0 is w (the same
+// in every lane), written at srow + v * ES.  The range is cut into chunks of
+// 64*L values; lane l generates the L consecutive values [l*L, l*L + L) of
+// each chunk starting from A^(l*L) applied to the chunk's first state (m: the
+// lane's 18-word matrix pair), and the next chunk starts where lane 63 ended
+// (sequence splitting, sec. 2.3).  Every LDS flush writes 64 pieces of 128
+// bytes that tile contiguous memory.  If v1 - v0 is a whole number of chunks,
+// w receives the state at v1 and the function returns true; otherwise w is
+// left as the last chunk's first state and it returns false.  `lds` holds
+// 64 * 144 bytes.
+// ---------------------------------------------------------------------------
+template <int DT, int L, class G>
+__device__ __forceinline__ bool wave_fill(uint32_t *w, const uint32_t *m, unsigned char *lds,
+                                          int lane, unsigned char *srow, uint64_t v0, uint64_t v1,
+                                          bool vec_ok)
+{
+    constexpr int ES = Elem<DT>::size;
+    constexpr int TV = 128 / ES;   // values per 128-byte piece
+    constexpr int NH = L / TV;     // pieces per lane per chunk
+    constexpr int RS = 128 + 16;   // LDS row pitch (bytes)
+    static_assert(NH >= 1 && L % TV == 0, "chunk must be whole pieces");
+    const uint64_t chunk_vals = (uint64_t)64 * L;
+    unsigned char *my_lds = lds + lane * RS;
+    const int prow = lane >> 3;        // flush: 8 lanes per 128-byte piece
+    const int pcol = (lane & 7) * 16;  //        8 pieces per instruction
+    bool whole = true;
+
+    for (uint64_t c0 = v0; c0 < v1; c0 += chunk_vals) {
+        uint32_t st[6] = {w[0], w[1], w[2], w[3], w[4], w[5]};
+        matvec3<C1>(m, st[0], st[1], st[2]);
+        matvec3<C2>(m + 9, st[3], st[4], st[5]);
+        G g;
+        g.load(st);
+        const bool full = c0 + chunk_vals <= v1;
+        for (int h = 0; h < NH; ++h) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) *(uint4 *)(my_lds + q * 16) = gen16<DT>(g);
+            __syncthreads();
+            if (full && vec_ok) {
+                uint4 v[8];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) v[j] = *(const uint4 *)(lds + (prow + 8 * j) * RS + pcol);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) {
+                    const uint64_t pos = c0 + (uint64_t)(prow + 8 * j) * L + h * TV;
+                    *(uint4 *)(srow + pos * ES + pcol) = v[j];
+                }
+            } else {
+                for (int e = lane; e < 64 * TV; e += 64) {
+                    const int r = e / TV, i = e % TV;
+                    const uint64_t pos = c0 + (uint64_t)r * L + h * TV + i;
+                    if (pos < v1) copy_elem<ES>(srow + pos * ES, lds + r * RS + i * ES);
+                }
+            }
+            __syncthreads();
+        }
+        if (full) {  // lane 63 ends at the next chunk's first state
+            uint32_t e[6];
+            g.store(e);
+#pragma unroll
+            for (int k = 0; k < 6; ++k) w[k] = __shfl(e[k], 63);
+        } else {
+            whole = false;
+        }
+    }
+    return whole;
+}
+
+}  // namespace mrg

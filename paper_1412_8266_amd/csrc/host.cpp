@@ -16,23 +16,16 @@
 #include <string>
 #include <vector>
 
-#include "mrg32k3a_gpu.h"
-#include "kernels.h"
+#include "internal.h"
 #include "mrg_arith.hpp"
 
-struct mrg_streamset_s {
-    int device = -1;
-    uint64_t n = 0;         // streams in the set
-    uint64_t first = 0;     // global index of stream 0 of the set
-    uint32_t seed[6] = {};  // base state (global stream 0)
-    uint32_t *d_planes = nullptr;  // [6][n]
-};
-
 namespace {
-
 thread_local std::string g_last_error;
+}
 
-mrg_status fail(mrg_status s, const char *fmt, ...)
+namespace mrg {
+
+mrg_status set_error(mrg_status s, const char *fmt, ...)
 {
     char buf[512];
     va_list ap;
@@ -43,10 +36,17 @@ mrg_status fail(mrg_status s, const char *fmt, ...)
     return s;
 }
 
-mrg_status hip_fail(hipError_t e, const char *what)
+mrg_status hip_error(hipError_t e, const char *what)
 {
-    return fail(MRG_EHIP, "%s: %s", what, hipGetErrorString(e));
+    return set_error(MRG_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
+
+}  // namespace mrg
+
+namespace {
+
+using mrg::set_error;
+using mrg::hip_error;
 
 // ---- host jump matrices (sec. 2.3) ---------------------------------------
 using Mat = std::array<uint32_t, 9>;
@@ -158,9 +158,9 @@ mrg_status current_device(int *dev)
 {
     int count = 0;
     hipError_t e = hipGetDeviceCount(&count);
-    if (e != hipSuccess || count <= 0) return fail(MRG_ENODEV, "no HIP device available");
+    if (e != hipSuccess || count <= 0) return set_error(MRG_ENODEV, "no HIP device available");
     e = hipGetDevice(dev);
-    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (e != hipSuccess) return hip_error(e, "hipGetDevice");
     return MRG_OK;
 }
 
@@ -175,23 +175,23 @@ mrg_status device_ctx(int dev, DevCtx **out)
     const std::vector<uint32_t> &t = host_tables();
     DevCtx ctx;
     hipError_t e = hipMalloc(&ctx.d_table, t.size() * sizeof(uint32_t));
-    if (e != hipSuccess) return fail(MRG_ENOMEM, "hipMalloc(jump tables): %s", hipGetErrorString(e));
+    if (e != hipSuccess) return set_error(MRG_ENOMEM, "hipMalloc(jump tables): %s", hipGetErrorString(e));
     e = hipMemcpy(ctx.d_table, t.data(), t.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(ctx.d_table);
-        return hip_fail(e, "hipMemcpy(jump tables)");
+        return hip_error(e, "hipMemcpy(jump tables)");
     }
     const std::vector<uint32_t> lt = build_lane_tables();
     e = hipMalloc(&ctx.d_lane_tab, lt.size() * sizeof(uint32_t));
     if (e != hipSuccess) {
         (void)hipFree(ctx.d_table);
-        return fail(MRG_ENOMEM, "hipMalloc(lane tables): %s", hipGetErrorString(e));
+        return set_error(MRG_ENOMEM, "hipMalloc(lane tables): %s", hipGetErrorString(e));
     }
     e = hipMemcpy(ctx.d_lane_tab, lt.data(), lt.size() * sizeof(uint32_t), hipMemcpyHostToDevice);
     if (e != hipSuccess) {
         (void)hipFree(ctx.d_table);
         (void)hipFree(ctx.d_lane_tab);
-        return hip_fail(e, "hipMemcpy(lane tables)");
+        return hip_error(e, "hipMemcpy(lane tables)");
     }
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && cus > 0)
@@ -209,26 +209,50 @@ bool state_ok(const uint32_t *s)
     return true;
 }
 
-mrg_status check_set(mrg_streamset ss)
+}  // namespace
+
+namespace mrg {
+
+FillTuning current_tuning() { return tuning(); }
+
+mrg_status device_tables(int dev, DeviceTables *out)
 {
-    if (!ss || !ss->d_planes) return fail(MRG_EINVAL, "null stream set");
+    DevCtx *ctx;
+    mrg_status st = device_ctx(dev, &ctx);
+    if (st) return st;
+    out->table = ctx->d_table;
+    out->lane_tab = ctx->d_lane_tab;
+    out->cus = ctx->cus;
+    return MRG_OK;
+}
+
+mrg_status check_streamset(mrg_streamset ss)
+{
+    if (!ss || !ss->d_planes) return set_error(MRG_EINVAL, "null stream set");
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess || dev != ss->device)
-        return fail(MRG_EINVAL, "stream set lives on device %d, current device is %d", ss->device, dev);
+        return set_error(MRG_EINVAL, "stream set lives on device %d, current device is %d", ss->device, dev);
     return MRG_OK;
 }
 
 mrg_status check_range(mrg_streamset ss, uint64_t first, uint64_t count)
 {
     if (first > ss->n || count > ss->n - first)
-        return fail(MRG_ERANGE, "streams [%llu, %llu+%llu) outside the set of %llu",
+        return set_error(MRG_ERANGE, "streams [%llu, %llu+%llu) outside the set of %llu",
                     (unsigned long long)first, (unsigned long long)first,
                     (unsigned long long)count, (unsigned long long)ss->n);
     // one lane per stream, gridDim.x < 2^31 blocks of 64
     if (count > ((uint64_t)1 << 36))
-        return fail(MRG_ERANGE, "count %llu above the per-call limit 2^36", (unsigned long long)count);
+        return set_error(MRG_ERANGE, "count %llu above the per-call limit 2^36", (unsigned long long)count);
     return MRG_OK;
 }
+
+}  // namespace mrg
+
+namespace {
+
+using mrg::check_range;
+mrg_status check_set(mrg_streamset ss) { return mrg::check_streamset(ss); }
 
 uint64_t splitmix64_next(uint64_t &x)
 {
@@ -252,7 +276,7 @@ extern "C" {
 
 mrg_status mrg_seed_from_master(uint64_t master_seed, uint32_t out6[6])
 {
-    if (!out6) return fail(MRG_EINVAL, "null output");
+    if (!out6) return set_error(MRG_EINVAL, "null output");
     uint64_t x = master_seed;
     for (int c = 0; c < 2; ++c) {
         const uint64_t m = modulus(c);
@@ -270,8 +294,8 @@ mrg_status mrg_seed_from_master(uint64_t master_seed, uint32_t out6[6])
 
 mrg_status mrg_jump_matrix(int component, const uint64_t h_exp[3], uint32_t out9[9])
 {
-    if (!h_exp || !out9) return fail(MRG_EINVAL, "null argument");
-    if (component != 0 && component != 1) return fail(MRG_EINVAL, "component must be 0 or 1");
+    if (!h_exp || !out9) return set_error(MRG_EINVAL, "null argument");
+    if (component != 0 && component != 1) return set_error(MRG_EINVAL, "component must be 0 or 1");
     const Mat R = power(component, h_exp);
     std::memcpy(out9, R.data(), 36);
     return MRG_OK;
@@ -279,22 +303,22 @@ mrg_status mrg_jump_matrix(int component, const uint64_t h_exp[3], uint32_t out9
 
 mrg_status mrg_state_check(const uint32_t state6[6])
 {
-    if (!state6) return fail(MRG_EINVAL, "null state");
-    if (!state_ok(state6)) return fail(MRG_EINVAL, "invalid MRG32k3a state");
+    if (!state6) return set_error(MRG_EINVAL, "null state");
+    if (!state_ok(state6)) return set_error(MRG_EINVAL, "invalid MRG32k3a state");
     return MRG_OK;
 }
 
 mrg_status mrg_streamset_create(mrg_streamset *out, uint64_t n_streams, uint64_t first_stream,
                                 const uint32_t seed6[6], void *stream)
 {
-    if (!out || !seed6) return fail(MRG_EINVAL, "null argument");
+    if (!out || !seed6) return set_error(MRG_EINVAL, "null argument");
     *out = nullptr;
-    if (!state_ok(seed6)) return fail(MRG_EINVAL, "invalid seed state");
-    if (n_streams == 0) return fail(MRG_ERANGE, "n_streams must be >= 1");
+    if (!state_ok(seed6)) return set_error(MRG_EINVAL, "invalid seed state");
+    if (n_streams == 0) return set_error(MRG_ERANGE, "n_streams must be >= 1");
     if (n_streams - 1 > UINT64_MAX - first_stream)
-        return fail(MRG_ERANGE, "first_stream + n_streams exceeds 2^64");
+        return set_error(MRG_ERANGE, "first_stream + n_streams exceeds 2^64");
     if (n_streams > ((uint64_t)1 << 36))
-        return fail(MRG_ERANGE, "n_streams above the limit 2^36");
+        return set_error(MRG_ERANGE, "n_streams above the limit 2^36");
     int dev;
     mrg_status st = current_device(&dev);
     if (st) return st;
@@ -302,7 +326,7 @@ mrg_status mrg_streamset_create(mrg_streamset *out, uint64_t n_streams, uint64_t
     if ((st = device_ctx(dev, &ctx))) return st;
 
     auto *ss = new (std::nothrow) mrg_streamset_s;
-    if (!ss) return fail(MRG_ENOMEM, "host allocation");
+    if (!ss) return set_error(MRG_ENOMEM, "host allocation");
     ss->device = dev;
     ss->n = n_streams;
     ss->first = first_stream;
@@ -310,7 +334,7 @@ mrg_status mrg_streamset_create(mrg_streamset *out, uint64_t n_streams, uint64_t
     hipError_t e = hipMalloc(&ss->d_planes, 6 * n_streams * sizeof(uint32_t));
     if (e != hipSuccess) {
         delete ss;
-        return fail(MRG_ENOMEM, "hipMalloc(%llu states): %s", (unsigned long long)n_streams,
+        return set_error(MRG_ENOMEM, "hipMalloc(%llu states): %s", (unsigned long long)n_streams,
                     hipGetErrorString(e));
     }
     // exponent g * 2^127 uses bits 127 .. 126 + bit_length(g): windows 31 ..
@@ -324,7 +348,7 @@ mrg_status mrg_streamset_create(mrg_streamset *out, uint64_t n_streams, uint64_t
     if (e != hipSuccess) {
         (void)hipFree(ss->d_planes);
         delete ss;
-        return hip_fail(e, "init kernel launch");
+        return hip_error(e, "init kernel launch");
     }
     *out = ss;
     return MRG_OK;
@@ -348,9 +372,9 @@ mrg_status mrg_streamset_destroy(mrg_streamset ss)
         (void)hipGetDevice(&prev);
         if (prev != ss->device) (void)hipSetDevice(ss->device);
         hipError_t e = hipDeviceSynchronize();
-        if (e != hipSuccess) st = hip_fail(e, "hipDeviceSynchronize before free");
+        if (e != hipSuccess) st = hip_error(e, "hipDeviceSynchronize before free");
         e = hipFree(ss->d_planes);
-        if (e != hipSuccess && st == MRG_OK) st = hip_fail(e, "hipFree(states)");
+        if (e != hipSuccess && st == MRG_OK) st = hip_error(e, "hipFree(states)");
         if (prev != ss->device && prev >= 0) (void)hipSetDevice(prev);
     }
     delete ss;
@@ -360,7 +384,7 @@ mrg_status mrg_streamset_destroy(mrg_streamset ss)
 mrg_status mrg_streamset_info(mrg_streamset ss, uint64_t *n_streams, uint64_t *first_stream,
                               uint32_t seed6[6])
 {
-    if (!ss) return fail(MRG_EINVAL, "null stream set");
+    if (!ss) return set_error(MRG_EINVAL, "null stream set");
     if (n_streams) *n_streams = ss->n;
     if (first_stream) *first_stream = ss->first;
     if (seed6) std::memcpy(seed6, ss->seed, sizeof ss->seed);
@@ -369,7 +393,7 @@ mrg_status mrg_streamset_info(mrg_streamset ss, uint64_t *n_streams, uint64_t *f
 
 mrg_status mrg_streamset_states_ptr(mrg_streamset ss, void **d_states)
 {
-    if (!ss || !d_states) return fail(MRG_EINVAL, "null argument");
+    if (!ss || !d_states) return set_error(MRG_EINVAL, "null argument");
     *d_states = ss->d_planes;
     return MRG_OK;
 }
@@ -381,12 +405,12 @@ mrg_status mrg_jump(mrg_streamset ss, uint64_t first, uint64_t count, const uint
     if (st) return st;
     if ((st = check_range(ss, first, count))) return st;
     if (count == 0) return MRG_OK;
-    if (!d_exp) return fail(MRG_EINVAL, "null exponent array");
+    if (!d_exp) return set_error(MRG_EINVAL, "null exponent array");
     DevCtx *ctx;
     if ((st = device_ctx(ss->device, &ctx))) return st;
     hipError_t e = mrg::launch_jump(ss->d_planes, ss->n, first, count, d_exp, ctx->d_table,
                                     (hipStream_t)stream);
-    return e == hipSuccess ? MRG_OK : hip_fail(e, "jump kernel launch");
+    return e == hipSuccess ? MRG_OK : hip_error(e, "jump kernel launch");
 }
 
 mrg_status mrg_jump_uniform(mrg_streamset ss, uint64_t first, uint64_t count,
@@ -395,7 +419,7 @@ mrg_status mrg_jump_uniform(mrg_streamset ss, uint64_t first, uint64_t count,
     mrg_status st = check_set(ss);
     if (st) return st;
     if ((st = check_range(ss, first, count))) return st;
-    if (!h_exp) return fail(MRG_EINVAL, "null exponent");
+    if (!h_exp) return set_error(MRG_EINVAL, "null exponent");
     if (count == 0) return MRG_OK;
     mrg::JumpMatrices J;
     const Mat P1 = power(0, h_exp), P2 = power(1, h_exp);
@@ -403,7 +427,7 @@ mrg_status mrg_jump_uniform(mrg_streamset ss, uint64_t first, uint64_t count,
     std::memcpy(J.m + 9, P2.data(), 36);
     hipError_t e = mrg::launch_jump_uniform(ss->d_planes, ss->n, first, count, J,
                                             (hipStream_t)stream);
-    return e == hipSuccess ? MRG_OK : hip_fail(e, "jump kernel launch");
+    return e == hipSuccess ? MRG_OK : hip_error(e, "jump kernel launch");
 }
 
 mrg_status mrg_jump_substreams(mrg_streamset ss, uint64_t first, uint64_t count, uint64_t k,
@@ -421,15 +445,15 @@ mrg_status mrg_fill(mrg_streamset ss, uint64_t first, uint64_t count, uint64_t n
     if (st) return st;
     if ((st = check_range(ss, first, count))) return st;
     if (dtype != MRG_U32 && dtype != MRG_F32 && dtype != MRG_F64)
-        return fail(MRG_EINVAL, "unknown dtype %d", (int)dtype);
+        return set_error(MRG_EINVAL, "unknown dtype %d", (int)dtype);
     if (layout != MRG_STREAM_MAJOR && layout != MRG_INTERLEAVED)
-        return fail(MRG_EINVAL, "unknown layout %d", (int)layout);
+        return set_error(MRG_EINVAL, "unknown layout %d", (int)layout);
     if (count == 0 || n_per_stream == 0) return MRG_OK;
-    if (!d_out) return fail(MRG_EINVAL, "null output");
+    if (!d_out) return set_error(MRG_EINVAL, "null output");
     const uint64_t es = dtype == MRG_F64 ? 8 : 4;
-    if ((uintptr_t)d_out % es) return fail(MRG_EINVAL, "output not aligned to its element size");
+    if ((uintptr_t)d_out % es) return set_error(MRG_EINVAL, "output not aligned to its element size");
     if (n_per_stream > UINT64_MAX / es / count)
-        return fail(MRG_ERANGE, "output size overflows 64 bits");
+        return set_error(MRG_ERANGE, "output size overflows 64 bits");
     const int vec_ok = ((uintptr_t)d_out % 16 == 0) && ((n_per_stream * es) % 16 == 0);
     const mrg::FillTuning tune = tuning();
     mrg::FillLaunch fl;
@@ -447,10 +471,7 @@ mrg_status mrg_fill(mrg_streamset ss, uint64_t first, uint64_t count, uint64_t n
             fl.kernel = 1;
             fl.L = L;
             fl.lane_tab = ctx->d_lane_tab + k * 64 * 18;
-            const uint64_t e[3] = {n_per_stream, 0, 0};
-            const Mat P1 = power(0, e), P2 = power(1, e);
-            std::memcpy(fl.Mn.m, P1.data(), 36);
-            std::memcpy(fl.Mn.m + 9, P2.data(), 36);
+            fl.table = ctx->d_table;
             // resident workgroups stride over the streams, or one per stream
             const uint64_t cap = tune.coop_wgs_per_cu ? (uint64_t)ctx->cus * tune.coop_wgs_per_cu
                                                       : ((uint64_t)1 << 31) - 1;
@@ -459,7 +480,7 @@ mrg_status mrg_fill(mrg_streamset ss, uint64_t first, uint64_t count, uint64_t n
     }
     hipError_t e = mrg::launch_fill(ss->d_planes, ss->n, first, count, n_per_stream, (int)dtype,
                                     (int)layout, d_out, vec_ok, fl, tune, (hipStream_t)stream);
-    return e == hipSuccess ? MRG_OK : hip_fail(e, "fill kernel launch");
+    return e == hipSuccess ? MRG_OK : hip_error(e, "fill kernel launch");
 }
 
 mrg_status mrg_get_states(mrg_streamset ss, uint64_t first, uint64_t count, uint32_t *h_out,
@@ -469,15 +490,15 @@ mrg_status mrg_get_states(mrg_streamset ss, uint64_t first, uint64_t count, uint
     if (st) return st;
     if ((st = check_range(ss, first, count))) return st;
     if (count == 0) return MRG_OK;
-    if (!h_out) return fail(MRG_EINVAL, "null output");
+    if (!h_out) return set_error(MRG_EINVAL, "null output");
     std::vector<uint32_t> tmp(6 * count);
     for (int c = 0; c < 6; ++c) {
         hipError_t e = hipMemcpyAsync(tmp.data() + c * count, ss->d_planes + c * ss->n + first,
                                       count * 4, hipMemcpyDeviceToHost, (hipStream_t)stream);
-        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(states)");
+        if (e != hipSuccess) return hip_error(e, "hipMemcpyAsync(states)");
     }
     hipError_t e = hipStreamSynchronize((hipStream_t)stream);
-    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    if (e != hipSuccess) return hip_error(e, "hipStreamSynchronize");
     for (uint64_t i = 0; i < count; ++i)
         for (int c = 0; c < 6; ++c) h_out[6 * i + c] = tmp[c * count + i];
     return MRG_OK;
@@ -490,10 +511,10 @@ mrg_status mrg_set_states(mrg_streamset ss, uint64_t first, uint64_t count, cons
     if (st) return st;
     if ((st = check_range(ss, first, count))) return st;
     if (count == 0) return MRG_OK;
-    if (!h_in) return fail(MRG_EINVAL, "null input");
+    if (!h_in) return set_error(MRG_EINVAL, "null input");
     for (uint64_t i = 0; i < count; ++i)
         if (!state_ok(h_in + 6 * i))
-            return fail(MRG_EINVAL, "state %llu is not a valid MRG32k3a state",
+            return set_error(MRG_EINVAL, "state %llu is not a valid MRG32k3a state",
                         (unsigned long long)i);
     std::vector<uint32_t> tmp(6 * count);
     for (uint64_t i = 0; i < count; ++i)
@@ -501,43 +522,43 @@ mrg_status mrg_set_states(mrg_streamset ss, uint64_t first, uint64_t count, cons
     for (int c = 0; c < 6; ++c) {
         hipError_t e = hipMemcpyAsync(ss->d_planes + c * ss->n + first, tmp.data() + c * count,
                                       count * 4, hipMemcpyHostToDevice, (hipStream_t)stream);
-        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync(states)");
+        if (e != hipSuccess) return hip_error(e, "hipMemcpyAsync(states)");
     }
     hipError_t e = hipStreamSynchronize((hipStream_t)stream);
-    return e == hipSuccess ? MRG_OK : hip_fail(e, "hipStreamSynchronize");
+    return e == hipSuccess ? MRG_OK : hip_error(e, "hipStreamSynchronize");
 }
 
 mrg_status mrg_config_set(const char *key, int64_t value)
 {
-    if (!key) return fail(MRG_EINVAL, "null key");
+    if (!key) return set_error(MRG_EINVAL, "null key");
     std::lock_guard<std::mutex> lk(g_mu);
     if (!std::strcmp(key, "engine")) {
-        if (value != 0 && value != 1) return fail(MRG_EINVAL, "engine must be 0 or 1");
+        if (value != 0 && value != 1) return set_error(MRG_EINVAL, "engine must be 0 or 1");
         g_tune.engine = (int)value;
     } else if (!std::strcmp(key, "coop_wgs_per_cu")) {
-        if (value < 0 || value > 1024) return fail(MRG_EINVAL, "coop_wgs_per_cu must be in [0, 1024]");
+        if (value < 0 || value > 1024) return set_error(MRG_EINVAL, "coop_wgs_per_cu must be in [0, 1024]");
         g_tune.coop_wgs_per_cu = (int)value;
     } else if (!std::strcmp(key, "strategy")) {
-        if (value < 0 || value > 2) return fail(MRG_EINVAL, "strategy must be 0, 1 or 2");
+        if (value < 0 || value > 2) return set_error(MRG_EINVAL, "strategy must be 0, 1 or 2");
         g_tune.strategy = (int)value;
     } else if (!std::strcmp(key, "tile_bytes")) {
-        if (value != 128 && value != 256) return fail(MRG_EINVAL, "tile_bytes must be 128 or 256");
+        if (value != 128 && value != 256) return set_error(MRG_EINVAL, "tile_bytes must be 128 or 256");
         g_tune.tile_bytes = (int)value;
     } else {
-        return fail(MRG_EINVAL, "unknown key '%s'", key);
+        return set_error(MRG_EINVAL, "unknown key '%s'", key);
     }
     return MRG_OK;
 }
 
 mrg_status mrg_config_get(const char *key, int64_t *value)
 {
-    if (!key || !value) return fail(MRG_EINVAL, "null argument");
+    if (!key || !value) return set_error(MRG_EINVAL, "null argument");
     std::lock_guard<std::mutex> lk(g_mu);
     if (!std::strcmp(key, "engine")) *value = g_tune.engine;
     else if (!std::strcmp(key, "tile_bytes")) *value = g_tune.tile_bytes;
     else if (!std::strcmp(key, "strategy")) *value = g_tune.strategy;
     else if (!std::strcmp(key, "coop_wgs_per_cu")) *value = g_tune.coop_wgs_per_cu;
-    else return fail(MRG_EINVAL, "unknown key '%s'", key);
+    else return set_error(MRG_EINVAL, "unknown key '%s'", key);
     return MRG_OK;
 }
 

@@ -1,0 +1,37 @@
+// Library-internal declarations shared by the C-ABI translation units.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.h"
+#include "mrg32k3a_gpu.h"
+
+struct mrg_streamset_s {
+    int device = -1;
+    uint64_t n = 0;                // streams in the set
+    uint64_t first = 0;            // global index of stream 0 of the set
+    uint32_t seed[6] = {};         // base state (global stream 0)
+    uint32_t *d_planes = nullptr;  // [6][n]
+};
+
+namespace mrg {
+
+// Record the calling thread's error text and return s.
+mrg_status set_error(mrg_status s, const char *fmt, ...);
+mrg_status hip_error(hipError_t e, const char *what);
+
+// Device-resident tables of one device (created on first use).
+struct DeviceTables {
+    const uint32_t *table = nullptr;     // windowed jump tables, kTableWords words
+    const uint32_t *lane_tab = nullptr;  // [3][64][18]
+    int cus = 256;
+};
+mrg_status device_tables(int dev, DeviceTables *out);
+
+FillTuning current_tuning();
+
+// Stream set usable on the current device; range inside the set.
+mrg_status check_streamset(mrg_streamset ss);
+mrg_status check_range(mrg_streamset ss, uint64_t first, uint64_t count);
+
+}  // namespace mrg

@@ -40,7 +40,7 @@ struct FillLaunch {
     int kernel = 0;                     // 0 lane per stream, 1 wave per stream
     int L = 0;                          // values per lane per chunk (wave per stream)
     const uint32_t *lane_tab = nullptr; // [64][18]: A^(l*L), component 1 then 2
-    JumpMatrices Mn = {};               // A^n: end state of each stream
+    const uint32_t *table = nullptr;    // windowed jump tables (end state of a partial chunk)
     unsigned grid = 0;                  // workgroups (wave per stream)
 };
 

@@ -12,21 +12,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "mrg_arith.hpp"
+#include "gen_device.hpp"
 #include "kernels.h"
 
 namespace mrg {
-
-// ---------------------------------------------------------------------------
-// jump tables: T[c][w][d][9], c in {0,1}, w in [0,48), d in [0,16); d = 0 is
-// the identity.  Exponent digit w of e (3 little-endian words) is
-// (e >> 4w) & 15.
-// ---------------------------------------------------------------------------
-__device__ __forceinline__ uint32_t exp_digit(uint64_t e0, uint64_t e1, uint64_t e2, int w)
-{
-    uint64_t word = w < 16 ? e0 : (w < 32 ? e1 : e2);
-    return (uint32_t)(word >> (4 * (w & 15))) & 15u;
-}
 
 // Stage windows [w_lo, w_hi) of both components into LDS, then apply them.
 __global__ void __launch_bounds__(256)
@@ -111,131 +100,15 @@ jumpu_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t firs
 // ---------------------------------------------------------------------------
 // generation
 // ---------------------------------------------------------------------------
-// Integer generator: lazy 32-bit words, v_mad_u64_u32 product-sums.  The
-// multipliers live in VGPRs so that each v_mad_u64_u32 can take the constant
-// addend K from an SGPR pair (one scalar operand per VOP3 instruction).
-struct GenI {
-    uint32_t a0, a1, a2, b0, b1, b2;  // lazy words, oldest first
-    uint32_t m13, m12, m23, m21;      // multipliers held in VGPRs
-
-    __device__ __forceinline__ void load(const uint32_t *w)
-    {
-        a0 = w[0]; a1 = w[1]; a2 = w[2]; b0 = w[3]; b1 = w[4]; b2 = w[5];
-        m13 = A13N; m12 = A12; m23 = A23N; m21 = A21;
-        asm volatile("" : "+v"(m13), "+v"(m12), "+v"(m23), "+v"(m21));
-    }
-    __device__ __forceinline__ void store(uint32_t *w) const
-    {
-        w[0] = canon1(a0); w[1] = canon1(a1); w[2] = canon1(a2);
-        w[3] = canon2(b0); w[4] = canon2(b1); w[5] = canon2(b2);
-    }
-    __device__ __forceinline__ uint32_t step()
-    {
-        const uint32_t p1 = next1(a0, a1, m13, m12);
-        const uint32_t p2 = next2(b0, b2, m23, m21);
-        a0 = a1; a1 = a2; a2 = p1;
-        b0 = b1; b1 = b2; b2 = p2;
-        return combine(p1, p2);
-    }
-    __device__ __forceinline__ uint32_t next_u32() { return step(); }
-    __device__ __forceinline__ float next_f32() { return to_f32(step()); }
-    __device__ __forceinline__ double next_f64() { return to_f64(step()); }
-};
-
-// Binary64 generator: centred integer-valued doubles, five FP64 operations
-// per component per step.
-struct GenF {
-    double a0, a1, a2, b0, b1, b2;
-
-    __device__ __forceinline__ void load(const uint32_t *w)
-    {
-        a0 = w[0]; a1 = w[1]; a2 = w[2]; b0 = w[3]; b1 = w[4]; b2 = w[5];
-    }
-    __device__ __forceinline__ void store(uint32_t *w) const
-    {
-        w[0] = canonf(a0, M1D); w[1] = canonf(a1, M1D); w[2] = canonf(a2, M1D);
-        w[3] = canonf(b0, M2D); w[4] = canonf(b1, M2D); w[5] = canonf(b2, M2D);
-    }
-    __device__ __forceinline__ double step()
-    {
-        const double r1 = next1f(a0, a1);
-        const double r2 = next2f(b0, b2);
-        a0 = a1; a1 = a2; a2 = r1;
-        b0 = b1; b1 = b2; b2 = r2;
-        return combinef(r1, r2);
-    }
-    __device__ __forceinline__ uint32_t next_u32() { return (uint32_t)step(); }
-    __device__ __forceinline__ float next_f32() { return to_f32f(step()); }
-    __device__ __forceinline__ double next_f64() { return to_f64f(step()); }
-};
-
-template <int DT> struct Elem;
-template <> struct Elem<0> { static constexpr int size = 4; };
-template <> struct Elem<1> { static constexpr int size = 4; };
-template <> struct Elem<2> { static constexpr int size = 8; };
-
-// 16 bytes of output: 4 uint32 / 4 float / 2 double values.
-template <int DT, class G>
-__device__ __forceinline__ uint4 gen16(G &g)
-{
-    uint4 v;
-    if constexpr (DT == 0) {
-        v.x = g.next_u32(); v.y = g.next_u32(); v.z = g.next_u32(); v.w = g.next_u32();
-    } else if constexpr (DT == 1) {
-        v.x = __float_as_uint(g.next_f32());
-        v.y = __float_as_uint(g.next_f32());
-        v.z = __float_as_uint(g.next_f32());
-        v.w = __float_as_uint(g.next_f32());
-    } else {
-        const uint64_t u0 = (uint64_t)__double_as_longlong(g.next_f64());
-        const uint64_t u1 = (uint64_t)__double_as_longlong(g.next_f64());
-        v.x = (uint32_t)u0; v.y = (uint32_t)(u0 >> 32);
-        v.z = (uint32_t)u1; v.w = (uint32_t)(u1 >> 32);
-    }
-    return v;
-}
-
-template <int DT, class G>
-__device__ __forceinline__ void put1(unsigned char *p, G &g)
-{
-    if constexpr (DT == 0) *(uint32_t *)p = g.next_u32();
-    else if constexpr (DT == 1) *(float *)p = g.next_f32();
-    else *(double *)p = g.next_f64();
-}
-
-__device__ __forceinline__ void load_state(const uint32_t *planes, uint64_t stride, uint64_t idx,
-                                           uint32_t *w)
-{
-#pragma unroll
-    for (int c = 0; c < 6; ++c) w[c] = planes[c * stride + idx];
-}
-
-__device__ __forceinline__ void store_state(uint32_t *planes, uint64_t stride, uint64_t idx,
-                                            const uint32_t *w)
-{
-#pragma unroll
-    for (int c = 0; c < 6; ++c) planes[c * stride + idx] = w[c];
-}
-
-// One wave (64 lanes) per workgroup; lane = stream.  Each full tile of TV
-// values per stream is generated into the lane's LDS row and written back
-// as 16-byte chunks, LPR lanes per row, so every store instruction covers
-// RPI rows x TB contiguous bytes.  The LDS row pitch TB+16 keeps both the
-// b128 writes (lanes on different rows) and the reads (lanes along a row)
-// free of bank conflicts.
+// Lane-per-stream stream-major fill: one wave per 64 streams, each lane
+// generating its stream's n values through the LDS tile writer rows_fill.
 template <int DT, int TB, class G>
 __global__ void __launch_bounds__(64)
 fill_sm_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t first,
                uint64_t count, uint64_t n, unsigned char *__restrict__ out, int vec_ok)
 {
     constexpr int ES = Elem<DT>::size;
-    constexpr int TV = TB / ES;      // values per row per tile
-    constexpr int RS = TB + 16;      // LDS row pitch (bytes)
-    constexpr int LPR = TB / 16;     // lanes per row when flushing
-    constexpr int RPI = 64 / LPR;    // rows per flush instruction
-    constexpr int NJ = 64 / RPI;     // flush instructions per tile
-    __shared__ __attribute__((aligned(16))) unsigned char lds[64 * RS];
-
+    __shared__ __attribute__((aligned(16))) unsigned char lds[64 * (TB + 16)];
     const int lane = threadIdx.x;
     const uint64_t s0 = (uint64_t)blockIdx.x * 64;
     const uint64_t nrows = count - s0 < 64 ? count - s0 : 64;
@@ -246,71 +119,7 @@ fill_sm_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t fi
     if (active) load_state(planes, plane_stride, idx, w);
     G g;
     g.load(w);
-
-    const uint64_t row_bytes = n * ES;
-    unsigned char *my_lds = lds + lane * RS;
-    // rows this lane flushes: r_j = lane / LPR + RPI * j, chunk lane % LPR
-    const int chunk = lane % LPR;
-    unsigned char *rowp[NJ];
-    bool rowa[NJ];
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-        const int r = lane / LPR + RPI * j;
-        rowa[j] = (uint64_t)r < nrows;
-        rowp[j] = out + (s0 + r) * row_bytes + chunk * 16;
-    }
-
-    const uint64_t nfull = n / TV;
-    for (uint64_t t = 0; t < nfull; ++t) {
-#pragma unroll
-        for (int c = 0; c < TB / 16; ++c)
-            *(uint4 *)(my_lds + c * 16) = gen16<DT>(g);
-        __syncthreads();
-        const uint64_t off = t * TB;
-        if (vec_ok) {
-            // all LDS reads first, one wait, then the stores
-            uint4 v[NJ];
-#pragma unroll
-            for (int j = 0; j < NJ; ++j)
-                v[j] = *(const uint4 *)(lds + (lane / LPR + RPI * j) * RS + chunk * 16);
-            if (nrows == 64) {
-#pragma unroll
-                for (int j = 0; j < NJ; ++j) *(uint4 *)(rowp[j] + off) = v[j];
-            } else {
-#pragma unroll
-                for (int j = 0; j < NJ; ++j)
-                    if (rowa[j]) *(uint4 *)(rowp[j] + off) = v[j];
-            }
-        } else {
-            // element stores: lane e covers (row e / TV, col e % TV)
-            for (int e = lane; e < 64 * TV; e += 64) {
-                const int r = e / TV, col = e % TV;
-                if ((uint64_t)r < nrows) {
-                    unsigned char *dst = out + (s0 + r) * row_bytes + off + (uint64_t)col * ES;
-                    const unsigned char *src = lds + r * RS + col * ES;
-                    if constexpr (ES == 4) *(uint32_t *)dst = *(const uint32_t *)src;
-                    else *(uint64_t *)dst = *(const uint64_t *)src;
-                }
-            }
-        }
-        __syncthreads();
-    }
-    // tail: fewer than TV values per row
-    const int tail = (int)(n - nfull * TV);
-    if (tail) {
-        for (int c = 0; c < tail; ++c) put1<DT>(my_lds + c * ES, g);
-        __syncthreads();
-        const uint64_t off = nfull * TB;
-        for (int e = lane; e < 64 * tail; e += 64) {
-            const int r = e / tail, col = e % tail;
-            if ((uint64_t)r < nrows) {
-                unsigned char *dst = out + (s0 + r) * row_bytes + off + (uint64_t)col * ES;
-                const unsigned char *src = lds + r * RS + col * ES;
-                if constexpr (ES == 4) *(uint32_t *)dst = *(const uint32_t *)src;
-                else *(uint64_t *)dst = *(const uint64_t *)src;
-            }
-        }
-    }
+    rows_fill<DT, TB, G>(g, lds, lane, nrows, out + s0 * n * ES, n * ES, n, vec_ok != 0);
     if (active) {
         g.store(w);
         store_state(planes, plane_stride, idx, w);
@@ -350,99 +159,33 @@ fill_il_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t fi
     store_state(planes, plane_stride, idx, w);
 }
 
-// Stream-major output with one wave per stream (sequence splitting inside the
-// stream, sec. 2.3): the stream's n outputs are cut into chunks of 64*L
-// values and lane l generates the L consecutive values [l*L, l*L + L) of each
-// chunk, starting from A^(l*L) applied to the chunk's first state
-// (lane_tab[l], formed on the host).  The next chunk starts where lane 63
-// ended.  Every LDS flush then writes 64 pieces of 128 bytes that tile the
-// chunk's 64*L*ES contiguous bytes, so the HBM write stream is nearly
-// sequential.  The end state A^n * state (Mn) is written back by lane 0.
-// Workgroups stride over the streams so that the streams in flight stay
-// adjacent in memory.
+// Wave-per-stream stream-major fill: workgroups (one wave each) stride over
+// the streams; each stream is written by wave_fill, so that every flush tiles
+// contiguous memory and the streams in flight stay adjacent.  The end state
+// is lane 63's after the last whole chunk, advanced by the windowed tables
+// over a final partial chunk.
 template <int DT, int L, class G>
 __global__ void __launch_bounds__(64)
 fill_coop_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t first,
                  uint64_t count, uint64_t n, unsigned char *__restrict__ out, int vec_ok,
-                 const uint32_t *__restrict__ lane_tab, JumpMatrices Mn)
+                 const uint32_t *__restrict__ lane_tab, const uint32_t *__restrict__ table)
 {
     constexpr int ES = Elem<DT>::size;
-    constexpr int TV = 128 / ES;   // values per 128-byte piece
-    constexpr int NH = L / TV;     // pieces per lane per chunk
-    constexpr int RS = 128 + 16;   // LDS row pitch (bytes)
-    static_assert(NH >= 1 && L % TV == 0, "chunk must be whole pieces");
-    __shared__ __attribute__((aligned(16))) unsigned char lds[64 * RS];
-
+    __shared__ __attribute__((aligned(16))) unsigned char lds[64 * 144];
     const int lane = threadIdx.x;
     uint32_t m[18];
 #pragma unroll
     for (int i = 0; i < 18; ++i) m[i] = lane_tab[lane * 18 + i];
-    unsigned char *my_lds = lds + lane * RS;
     const uint64_t chunk_vals = (uint64_t)64 * L;
-    const uint64_t nchunks = (n + chunk_vals - 1) / chunk_vals;
-    const int prow = lane >> 3;        // flush: 8 lanes per 128-byte piece
-    const int pcol = (lane & 7) * 16;  //        8 pieces per instruction
-
-    // whole chunks only: the end state is lane 63's after the last chunk;
-    // otherwise it is A^n * state, computed up front
-    const bool whole = n % chunk_vals == 0;
+    const uint64_t rem = n % chunk_vals;
 
     for (uint64_t s = blockIdx.x; s < count; s += gridDim.x) {
         const uint64_t idx = first + s;
         uint32_t w[6];
         load_state(planes, plane_stride, idx, w);
-        uint32_t fin[6] = {w[0], w[1], w[2], w[3], w[4], w[5]};
-        if (!whole) {
-            matvec3<C1>(Mn.m, fin[0], fin[1], fin[2]);
-            matvec3<C2>(Mn.m + 9, fin[3], fin[4], fin[5]);
-        }
-        unsigned char *srow = out + s * n * ES;
-
-        for (uint64_t c = 0; c < nchunks; ++c) {
-            uint32_t st[6] = {w[0], w[1], w[2], w[3], w[4], w[5]};
-            matvec3<C1>(m, st[0], st[1], st[2]);
-            matvec3<C2>(m + 9, st[3], st[4], st[5]);
-            G g;
-            g.load(st);
-            const uint64_t v0 = c * chunk_vals;
-            const bool full = v0 + chunk_vals <= n;
-            for (int h = 0; h < NH; ++h) {
-#pragma unroll
-                for (int q = 0; q < 8; ++q) *(uint4 *)(my_lds + q * 16) = gen16<DT>(g);
-                __syncthreads();
-                if (full && vec_ok) {
-                    uint4 v[8];
-#pragma unroll
-                    for (int j = 0; j < 8; ++j)
-                        v[j] = *(const uint4 *)(lds + (prow + 8 * j) * RS + pcol);
-#pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        const uint64_t pos = v0 + (uint64_t)(prow + 8 * j) * L + h * TV;
-                        *(uint4 *)(srow + pos * ES + pcol) = v[j];
-                    }
-                } else {
-                    for (int e = lane; e < 64 * TV; e += 64) {
-                        const int r = e / TV, i = e % TV;
-                        const uint64_t pos = v0 + (uint64_t)r * L + h * TV + i;
-                        if (pos < n) {
-                            const unsigned char *src = lds + r * RS + i * ES;
-                            if constexpr (ES == 4) *(uint32_t *)(srow + pos * ES) = *(const uint32_t *)src;
-                            else *(uint64_t *)(srow + pos * ES) = *(const uint64_t *)src;
-                        }
-                    }
-                }
-                __syncthreads();
-            }
-            if (c + 1 < nchunks) {  // chunk c was full: lane 63 ends at the next chunk's start
-                uint32_t e[6];
-                g.store(e);
-#pragma unroll
-                for (int k = 0; k < 6; ++k) w[k] = __shfl(e[k], 63);
-            } else if (whole) {
-                g.store(fin);
-            }
-        }
-        if (lane == (whole ? 63 : 0)) store_state(planes, plane_stride, idx, fin);
+        if (!wave_fill<DT, L, G>(w, m, lds, lane, out + s * n * ES, 0, n, vec_ok != 0))
+            jump_global(table, rem, 0, 0, 0, 16, w);
+        if (lane == 0) store_state(planes, plane_stride, idx, w);
     }
 }
 
@@ -498,13 +241,13 @@ static hipError_t launch_fill_g(uint32_t *planes, uint64_t plane_stride, uint64_
         const dim3 grid(fl.grid), block(64);
         if (fl.L == 64 && DT != 2)
             hipLaunchKernelGGL((fill_coop_kernel<DT, 64, G>), grid, block, 0, st, planes,
-                               plane_stride, first, count, n, o, vec_ok, fl.lane_tab, fl.Mn);
+                               plane_stride, first, count, n, o, vec_ok, fl.lane_tab, fl.table);
         else if (fl.L == 32)
             hipLaunchKernelGGL((fill_coop_kernel<DT, 32, G>), grid, block, 0, st, planes,
-                               plane_stride, first, count, n, o, vec_ok, fl.lane_tab, fl.Mn);
+                               plane_stride, first, count, n, o, vec_ok, fl.lane_tab, fl.table);
         else if (fl.L == 16 && DT == 2)
             hipLaunchKernelGGL((fill_coop_kernel<2, 16, G>), grid, block, 0, st, planes,
-                               plane_stride, first, count, n, o, vec_ok, fl.lane_tab, fl.Mn);
+                               plane_stride, first, count, n, o, vec_ok, fl.lane_tab, fl.table);
         else
             return hipErrorInvalidValue;
     } else if (tile_bytes >= 256) {

@@ -1,0 +1,213 @@
+"""GPU parity of the persistent batched path against the CPU oracle.
+
+A batch must produce, bit for bit, what the oracle produces for each request
+on its own: plain requests continue their streams (and advance them),
+substream requests draw substreams (sec. 4.1) of one stream and leave it
+unchanged.  Work decompositions (segment length, lane/wave threshold, static
+or dynamic schedule), the graph launch, the direct launch and the
+per-request reference schedule must all agree.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1412_8266_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+SEED = 0xBA7C4
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mg():
+    import torch
+    import paper_1412_8266_amd as m
+    assert torch.cuda.is_available()
+    return m
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def make_plain(mg, rng, n_req, max_k, max_n, budget):
+    """Contiguous plain requests; returns rows, tensors, specs."""
+    import torch
+    rows, outs, specs = [], [], []
+    first = 0
+    total = 0
+    while len(rows) < n_req:
+        k = int(wl.log_uniform_int(rng, max_k, 1)[0])
+        n = int(wl.log_uniform_int(rng, max_n, 1)[0])
+        if total + k * n > budget:
+            continue
+        dt = int(rng.integers(0, 3))
+        if rng.random() < 0.1:
+            k, n = (0, n) if rng.random() < 0.5 else (k, 0)  # empty requests are skipped
+        t = torch.empty((k, n), dtype=mg.torch_dtype(dt), device="cuda")
+        rows.append((first, k, n, 0, t.data_ptr() if t.numel() else 0, dt, 0))
+        outs.append(t)
+        specs.append((first, k, n, dt))
+        first += k
+        total += k * n
+    return rows, outs, specs, first
+
+
+def check_plain(base, specs, outs, states_before):
+    """Each request against the oracle from the given start states."""
+    for (first, k, n, dt), t in zip(specs, outs):
+        if k == 0 or n == 0:
+            continue
+        want, _ = oracle.fill(states_before[first:first + k], n, dt)
+        got = host(t)
+        assert np.array_equal(got.view(np.uint8), want.view(np.uint8)), (first, k, n, dt)
+
+
+CONFIGS = {
+    "default": dict(),
+    "small-seg": dict(segment_bytes=16 * 1024),
+    "static": dict(schedule=2, waves_per_cu=4),
+    "all-rows": dict(wave_min_bytes=1 << 40),
+    "all-waves": dict(wave_min_bytes=4, segment_bytes=32 * 1024),
+}
+
+
+@pytest.mark.parametrize("name", list(CONFIGS))
+@pytest.mark.parametrize("engine", [0, 1], ids=["int", "f64"])
+def test_plain_batch_matches_oracle(mg, name, engine):
+    say("batch", name, engine)
+    old = mg.mrg_config_get("engine")
+    mg.mrg_config_set("engine", engine)
+    try:
+        rng = np.random.default_rng(SEED + len(name))
+        rows, outs, specs, nstreams = make_plain(mg, rng, 40, 150, 60000, 6_000_000)
+        base = oracle.seed_from_master(SEED)
+        ss = mg.StreamSet(nstreams, seed=[int(x) for x in base])
+        st0 = oracle.streams(base, 0, nstreams)
+        b = mg.Batch(ss, rows, mg.batch_config(**CONFIGS[name]))
+        info = b.info()
+        assert info["requests"] == sum(1 for s in specs if s[1] and s[2])
+        b.run()
+        check_plain(base, specs, outs, st0)
+        # end states advanced by n for every stream of every request
+        st1 = st0.copy()
+        for first, k, n, dt in specs:
+            if k and n:
+                st1[first:first + k] = oracle.jump_many(st0[first:first + k], n)
+        assert np.array_equal(ss.get_states(), st1)
+        # a second run continues the streams
+        b.run()
+        check_plain(base, specs, outs, st1)
+        b.close()
+        ss.close()
+    finally:
+        mg.mrg_config_set("engine", old)
+
+
+def test_substream_requests(mg):
+    import torch
+    say("substreams")
+    rng = np.random.default_rng(SEED + 7)
+    base = oracle.seed_from_master(SEED + 7)
+    ss = mg.StreamSet(12, seed=[int(x) for x in base])
+    st0 = ss.get_states()
+    rows, outs, specs = [], [], []
+    for i in range(30):
+        s = int(rng.integers(0, 12))
+        k = int(wl.log_uniform_int(rng, 100, 1)[0])
+        n = int(wl.log_uniform_int(rng, 20000, 1)[0])
+        if k * n > 400_000:
+            n = max(1, 400_000 // k)
+        sub0 = int(rng.integers(0, 1 << 40))
+        dt = int(rng.integers(0, 3))
+        t = torch.empty((k, n), dtype=mg.torch_dtype(dt), device="cuda")
+        rows.append((s, k, n, sub0, t.data_ptr(), dt, mg.REQ_SUBSTREAMS))
+        outs.append(t)
+        specs.append((s, k, n, sub0, dt))
+    b = mg.Batch(ss, rows, mg.batch_config(segment_bytes=16 * 1024))
+    for rep in range(2):
+        b.run()
+        for (s, k, n, sub0, dt), t in zip(specs, outs):
+            starts = np.stack([oracle.jump(st0[s], (sub0 + j) << 76) for j in range(k)])
+            want, _ = oracle.fill(starts, n, dt)
+            assert np.array_equal(host(t).view(np.uint8), want.view(np.uint8)), (s, k, n, sub0)
+        assert np.array_equal(ss.get_states(), st0)  # unchanged
+    b.close()
+    ss.close()
+
+
+def test_graph_direct_and_per_request_agree(mg):
+    import torch
+    say("graph vs direct vs per-request")
+    rng = np.random.default_rng(SEED + 3)
+    sets, batches, outsets = [], [], []
+    for mode in range(3):
+        rng = np.random.default_rng(SEED + 3)
+        rows, outs, specs, nstreams = make_plain(mg, rng, 50, 300, 40000, 8_000_000)
+        ss = mg.StreamSet(nstreams, master_seed=SEED + 3)
+        sets.append(ss)
+        batches.append(mg.Batch(ss, rows, mg.batch_config(segment_bytes=64 * 1024)))
+        outsets.append(outs)
+    for rep in range(3):
+        batches[0].run()
+        junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+        batches[1].run_direct()
+        batches[2].run_per_request()
+        torch.cuda.synchronize()
+        del junk
+        for t0, t1, t2 in zip(*outsets):
+            a, b_, c = host(t0), host(t1), host(t2)
+            assert np.array_equal(a.view(np.uint8), b_.view(np.uint8))
+            assert np.array_equal(a.view(np.uint8), c.view(np.uint8))
+        s0 = sets[0].get_states()
+        assert np.array_equal(s0, sets[1].get_states())
+        assert np.array_equal(s0, sets[2].get_states())
+    for b in batches:
+        b.close()
+    for s in sets:
+        s.close()
+
+
+def test_autotune_restores_states_and_keeps_results(mg):
+    say("autotune")
+    rng = np.random.default_rng(SEED + 5)
+    rows, outs, specs, nstreams = make_plain(mg, rng, 40, 200, 50000, 6_000_000)
+    base = oracle.seed_from_master(SEED + 5)
+    ss = mg.StreamSet(nstreams, seed=[int(x) for x in base])
+    st0 = oracle.streams(base, 0, nstreams)
+    b = mg.Batch(ss, rows)
+    cands = [mg.batch_config(segment_bytes=s, waves_per_cu=w, schedule=sc)
+             for s, w, sc in [(64 << 10, 8, 1), (256 << 10, 16, 1), (1 << 20, 16, 2)]]
+    best, ms = b.autotune(cands, reps=1)
+    assert 0 <= best < 3 and all(x > 0 for x in ms)
+    assert np.array_equal(ss.get_states(), st0)
+    assert b.info()["segment_bytes"] == cands[best].segment_bytes
+    b.run()
+    check_plain(base, specs, outs, st0)
+    b.close()
+    ss.close()
+
+
+def test_batch_validation(mg):
+    import torch
+    ss = mg.StreamSet(100, master_seed=1)
+    t = torch.empty((10, 10), dtype=torch.uint32, device="cuda")
+    with pytest.raises(mg.MRGError):  # overlapping streams
+        mg.Batch(ss, [(0, 10, 10, 0, t.data_ptr(), 0, 0), (5, 10, 10, 0, t.data_ptr(), 0, 0)])
+    with pytest.raises(mg.MRGError):  # outside the set
+        mg.Batch(ss, [(95, 10, 10, 0, t.data_ptr(), 0, 0)])
+    with pytest.raises(mg.MRGError):  # bad dtype
+        mg.Batch(ss, [(0, 10, 10, 0, t.data_ptr(), 7, 0)])
+    b = mg.Batch(ss, [])  # empty batch runs as a no-op
+    b.run()
+    b.close()
+    ss.close()
