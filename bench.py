@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--strategy", type=int, default=None, help="0 auto, 1 lane/stream, 2 wave/stream")
     ap.add_argument("--coop-wgs-per-cu", type=int, default=None)
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched request mix")
+    ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--quick", action="store_true", help="headline only (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device-to-device copy 3 times (to scale HBM counters)")
@@ -91,6 +93,66 @@ def cpu_baseline(streams: int, n: int):
         "cpu": platform.processor() or platform.machine(),
         "host_cpus": os.cpu_count(),
     }
+
+
+def batched(mg, wl, torch, stream, reps):
+    """The 10,000-request mix (stream counts log-uniform in [1, 4096], lengths
+    log-uniform in [1, 2^20] per stream, dtypes mixed) as one persistent
+    graph launch against one launch per request.  The batch writes about
+    1.8 TiB per run, more than HBM holds, so every request's output is placed
+    in a 32 GiB arena at a rolling offset (timing only: overlapping requests
+    overwrite each other; the outputs are verified in the tests)."""
+    req = wl.c4_requests()
+    nbytes = req.bytes()
+    arena_bytes = 32 << 30
+    assert int(nbytes.max()) <= arena_bytes
+    arena = torch.empty(arena_bytes // 8, dtype=torch.float64, device="cuda")
+    base = arena.data_ptr()
+    rows, off = [], 0
+    for i in range(len(req)):
+        b = int(nbytes[i])
+        if off + b > arena_bytes:
+            off = 0
+        rows.append((int(req.first_stream[i]), int(req.n_streams[i]), int(req.length[i]), 0,
+                     base + off, int(req.dtype[i]), 0))
+        off = (off + b + 255) // 256 * 256
+    S = int(req.n_streams.sum())
+    ss = mg.StreamSet(S, master_seed=wl.MASTER_SEED)
+    b = mg.Batch(ss, rows)
+    cands = [mg.batch_config(segment_bytes=sb, waves_per_cu=w, schedule=sc)
+             for sb, w, sc in [(256 << 10, 16, 1), (1 << 20, 16, 1), (256 << 10, 8, 1),
+                               (64 << 10, 16, 1), (256 << 10, 16, 2)]]
+    t0 = time.perf_counter()
+    best, cand_ms = b.autotune(cands, reps=1)
+    tune_s = time.perf_counter() - t0
+    info = b.info()
+    per_b, _ = timed(lambda: b.run(), reps, 1, stream)
+    per_r, _ = timed(lambda: b.run_per_request(), reps, 1, stream)
+    ms_b = sum(per_b) / len(per_b)
+    ms_r = sum(per_r) / len(per_r)
+    samples = info["samples"]
+    out = {
+        "requests": len(req),
+        "streams": S,
+        "samples_per_run": samples,
+        "bytes_per_run": info["bytes"],
+        "work_items": info["items"],
+        "batched_graph_ms": round(ms_b, 3),
+        "per_request_launches_ms": round(ms_r, 3),
+        "batched_Gsamples_s": round(samples / ms_b / 1e6, 2),
+        "per_request_Gsamples_s": round(samples / ms_r / 1e6, 2),
+        "batched_over_per_request": round(ms_r / ms_b, 3),
+        "batched_hbm_frac": round(info["bytes"] / ms_b / 1e6 / HBM_PEAK_GBS, 4),
+        "autotune": {"chosen": {"segment_bytes": info["segment_bytes"],
+                                "waves_per_cu": info["waves_per_cu"],
+                                "schedule": "static" if info["schedule"] == 2 else "dynamic"},
+                     "candidate_ms": [round(x, 3) for x in cand_ms], "seconds": round(tune_s, 2)},
+    }
+    b.close()
+    ss.close()
+    del arena
+    torch.cuda.synchronize()
+    return out
 
 
 def main():
@@ -213,9 +275,12 @@ def main():
         per_j, _ = timed(lambda: ss3.jump(ex), 10, 1, stream)
         extra["jump_2^16_streams_ms"] = round(sum(per_j) / len(per_j), 4)
         ss3.close()
-    res["extra"] = extra
     ss.close()
     torch.cuda.synchronize()
+    if not args.quick and not args.no_batch:
+        print("[bench] batched request mix", file=sys.stderr, flush=True)
+        extra["batched"] = batched(mg, wl, torch, stream, args.batch_reps)
+    res["extra"] = extra
 
     if not args.no_cpu and not args.quick:
         print("[bench] CPU oracle baseline", file=sys.stderr, flush=True)

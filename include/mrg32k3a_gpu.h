@@ -57,6 +57,7 @@ typedef int32_t mrg_status;
 #define MRG_EHIP   (-3)  /* a HIP runtime call failed (see mrg_last_error) */
 #define MRG_ERANGE (-4)  /* stream range or size outside the stream set / limits */
 #define MRG_ENODEV (-5)  /* no usable HIP device */
+#define MRG_EBUSY  (-6)  /* serving: waiting on memory or time that did not come */
 
 typedef enum { MRG_U32 = 0, MRG_F32 = 1, MRG_F64 = 2 } mrg_dtype;
 typedef enum { MRG_STREAM_MAJOR = 0, MRG_INTERLEAVED = 1 } mrg_layout;
@@ -240,6 +241,93 @@ mrg_status mrg_batch_autotune(mrg_batch b, const mrg_batch_config *cands, uint32
 
 /* Release the plan (synchronises the device first).  NULL is ignored. */
 mrg_status mrg_batch_destroy(mrg_batch b);
+
+/* ---------------------------------------------------------------------- */
+/* Serving: continuous batching of client requests                         */
+/* ---------------------------------------------------------------------- */
+/* Each client c owns global stream first_stream + c (its state stays on the
+ * device and never changes) and a substream cursor: a request of client c
+ * for k streams gets the client's next k substreams (sec. 4.1), assigned at
+ * admission.  A scheduler thread admits queued requests in arrival order
+ * while the output arena has room, launches every admitted group as one
+ * persistent batch launch on the next of max_inflight HIP streams (groups
+ * overlap on the device), and retires them when their completion events
+ * fire.  A request's output is a [k, n] stream-major array of its dtype in
+ * the arena, identical to generating that request alone. */
+typedef struct mrg_server_s *mrg_server;
+
+typedef struct {
+    uint64_t n_clients;     /* client streams */
+    uint64_t first_stream;  /* global index of client 0's stream */
+    uint64_t master_seed;   /* base state via mrg_seed_from_master */
+    uint64_t arena_bytes;   /* device output arena: the admission cap */
+    uint32_t max_inflight;  /* HIP streams, i.e. groups in flight (0: 4; at most 64) */
+    uint32_t max_batch;     /* requests per group (0: 4096) */
+    uint32_t waves_per_cu;  /* persistent workgroups per CU per group (0: 16) */
+    uint32_t auto_release;  /* 1: free each output when it completes (throughput runs) */
+} mrg_server_config;
+
+typedef struct {
+    uint64_t ticket, client, n_streams, n_per_stream, substream0;
+    void *d_out;            /* arena pointer (NULL with auto_release) */
+    int32_t dtype;
+    int32_t pad;
+    double latency_s;       /* completion seen by the scheduler - submission */
+    double queue_s;         /* admission - submission */
+    double t_submit;        /* submission time (steady clock, seconds) */
+} mrg_server_result;
+
+typedef struct {
+    uint64_t pending, inflight, completed, ticks, samples, bytes, arena_used, arena_bytes;
+} mrg_server_stats_t;
+
+typedef struct {
+    double t;               /* arrival time, seconds from the start of the trace */
+    uint64_t client, n_streams, n_per_stream;
+    int32_t dtype;
+    int32_t pad;
+} mrg_arrival;
+
+/* Create the client stream set, the arena, the streams and start the
+ * scheduler thread (on the device current at the call). */
+mrg_status mrg_server_create(mrg_server *out, const mrg_server_config *cfg);
+
+/* Queue a request (thread-safe).  *ticket (may be NULL) identifies it.
+ * MRG_ERANGE if it can never fit in the arena. */
+mrg_status mrg_server_submit(mrg_server s, uint64_t client, uint64_t n_streams,
+                             uint64_t n_per_stream, int32_t dtype, uint64_t *ticket);
+
+/* Take up to max_out finished requests (oldest first); *n_out receives the
+ * count.  Returns the scheduler's error status, if it stopped on one. */
+mrg_status mrg_server_poll(mrg_server s, mrg_server_result *out, uint64_t max_out,
+                           uint64_t *n_out);
+
+/* Free a finished request's output (not needed with auto_release). */
+mrg_status mrg_server_release(mrg_server s, uint64_t ticket);
+
+/* Copy the first `bytes` of a finished, held output to host memory
+ * (synchronous). */
+mrg_status mrg_server_copy_output(mrg_server s, uint64_t ticket, void *h_dst, uint64_t bytes);
+
+mrg_status mrg_server_stats(mrg_server s, mrg_server_stats_t *st);
+
+/* Wait until nothing is queued or in flight (MRG_EBUSY on timeout or when
+ * the queue waits for outputs that are not released). */
+mrg_status mrg_server_drain(mrg_server s, double timeout_s);
+
+/* Replay a trace: submit arrival i at time arr[i].t * time_scale after the
+ * call (arrivals sorted by t), then drain.  *wall_s (may be NULL) receives
+ * the elapsed time.  The results are collected with mrg_server_poll. */
+mrg_status mrg_server_run_trace(mrg_server s, const mrg_arrival *arr, uint64_t n,
+                                double time_scale, double *wall_s);
+
+/* A client's (fixed) stream state and its next substream. */
+mrg_status mrg_server_client_state(mrg_server s, uint64_t client, uint32_t out6[6],
+                                   uint64_t *next_substream);
+
+/* Stop the scheduler after the groups in flight, drop queued requests and
+ * free everything.  NULL is ignored. */
+mrg_status mrg_server_destroy(mrg_server s);
 
 /* ---------------------------------------------------------------------- */
 /* Host-only helpers (no device work; usable without a GPU)               */

@@ -36,7 +36,7 @@ def _load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             "libmrg32k3a_gpu.so is not built (expected at %s); build it with "
-            "`python -m paper_1412_8266_amd.build`" % LIB_PATH)
+            "`python paper_1412_8266_amd/build.py`" % LIB_PATH)
     return ctypes.CDLL(LIB_PATH)
 
 
@@ -99,6 +99,47 @@ _SIGS.update({
     "mrg_batch_autotune": [_P, ctypes.POINTER(mrg_batch_config), ctypes.c_uint32, ctypes.c_uint32,
                            _P, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_float)],
     "mrg_batch_destroy": [_P],
+})
+
+class mrg_server_config(ctypes.Structure):
+    _fields_ = [("n_clients", ctypes.c_uint64), ("first_stream", ctypes.c_uint64),
+                ("master_seed", ctypes.c_uint64), ("arena_bytes", ctypes.c_uint64),
+                ("max_inflight", ctypes.c_uint32), ("max_batch", ctypes.c_uint32),
+                ("waves_per_cu", ctypes.c_uint32), ("auto_release", ctypes.c_uint32)]
+
+
+class mrg_server_result(ctypes.Structure):
+    _fields_ = [("ticket", ctypes.c_uint64), ("client", ctypes.c_uint64),
+                ("n_streams", ctypes.c_uint64), ("n_per_stream", ctypes.c_uint64),
+                ("substream0", ctypes.c_uint64), ("d_out", ctypes.c_void_p),
+                ("dtype", ctypes.c_int32), ("pad", ctypes.c_int32),
+                ("latency_s", ctypes.c_double), ("queue_s", ctypes.c_double),
+                ("t_submit", ctypes.c_double)]
+
+
+class mrg_server_stats_t(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_uint64) for f in ("pending", "inflight", "completed", "ticks",
+                                               "samples", "bytes", "arena_used", "arena_bytes")]
+
+
+class mrg_arrival(ctypes.Structure):
+    _fields_ = [("t", ctypes.c_double), ("client", ctypes.c_uint64),
+                ("n_streams", ctypes.c_uint64), ("n_per_stream", ctypes.c_uint64),
+                ("dtype", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+_SIGS.update({
+    "mrg_server_create": [ctypes.POINTER(_P), ctypes.POINTER(mrg_server_config)],
+    "mrg_server_submit": [_P, _U64, _U64, _U64, _I32, ctypes.POINTER(_U64)],
+    "mrg_server_poll": [_P, ctypes.POINTER(mrg_server_result), _U64, ctypes.POINTER(_U64)],
+    "mrg_server_release": [_P, _U64],
+    "mrg_server_copy_output": [_P, _U64, _P, _U64],
+    "mrg_server_stats": [_P, ctypes.POINTER(mrg_server_stats_t)],
+    "mrg_server_drain": [_P, ctypes.c_double],
+    "mrg_server_run_trace": [_P, ctypes.POINTER(mrg_arrival), _U64, ctypes.c_double,
+                             ctypes.POINTER(ctypes.c_double)],
+    "mrg_server_client_state": [_P, _U64, _PU32, ctypes.POINTER(_U64)],
+    "mrg_server_destroy": [_P],
 })
 
 for _name, _args in _SIGS.items():
@@ -285,3 +326,60 @@ def mrg_batch_autotune(b: int, configs, reps: int = 1, stream: int = 0):
 
 def mrg_batch_destroy(b: int) -> None:
     _call("mrg_batch_destroy", b)
+
+
+def mrg_server_create(n_clients, first_stream, master_seed, arena_bytes, max_inflight=0,
+                      max_batch=0, waves_per_cu=0, auto_release=0) -> int:
+    cfg = mrg_server_config(n_clients, first_stream, master_seed & ((1 << 64) - 1), arena_bytes,
+                            max_inflight, max_batch, waves_per_cu, auto_release)
+    h = _P()
+    _call("mrg_server_create", ctypes.byref(h), ctypes.byref(cfg))
+    return h.value
+
+
+def mrg_server_submit(s: int, client: int, n_streams: int, n_per_stream: int, dtype: int) -> int:
+    t = _U64()
+    _call("mrg_server_submit", s, client, n_streams, n_per_stream, dtype, ctypes.byref(t))
+    return t.value
+
+
+def mrg_server_poll(s: int, max_out: int = 4096):
+    buf = (mrg_server_result * max(max_out, 1))()
+    n = _U64()
+    _call("mrg_server_poll", s, buf, max_out, ctypes.byref(n))
+    return buf, n.value
+
+
+def mrg_server_release(s: int, ticket: int) -> None:
+    _call("mrg_server_release", s, ticket)
+
+
+def mrg_server_copy_output(s: int, ticket: int, h_dst: int, nbytes: int) -> None:
+    _call("mrg_server_copy_output", s, ticket, h_dst, nbytes)
+
+
+def mrg_server_stats(s: int) -> dict:
+    st = mrg_server_stats_t()
+    _call("mrg_server_stats", s, ctypes.byref(st))
+    return {f: getattr(st, f) for f, _ in mrg_server_stats_t._fields_}
+
+
+def mrg_server_drain(s: int, timeout_s: float) -> None:
+    _call("mrg_server_drain", s, timeout_s)
+
+
+def mrg_server_run_trace(s: int, arrivals, n: int, time_scale: float = 1.0) -> float:
+    wall = ctypes.c_double()
+    _call("mrg_server_run_trace", s, arrivals, n, time_scale, ctypes.byref(wall))
+    return wall.value
+
+
+def mrg_server_client_state(s: int, client: int):
+    out = (ctypes.c_uint32 * 6)()
+    nxt = _U64()
+    _call("mrg_server_client_state", s, client, out, ctypes.byref(nxt))
+    return list(out), nxt.value
+
+
+def mrg_server_destroy(s: int) -> None:
+    _call("mrg_server_destroy", s)

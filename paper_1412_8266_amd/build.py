@@ -1,6 +1,7 @@
 """Build the HIP library ``libmrg32k3a_gpu.so`` in-tree for gfx950.
 
-Usage: ``python -m paper_1412_8266_amd.build`` (or ``build()`` from Python).
+Usage: ``python paper_1412_8266_amd/build.py`` (a script: importing the package
+needs the library this builds).
 hipcc cross-compiles for gfx950 without a GPU present.
 """
 from __future__ import annotations
@@ -14,7 +15,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmrg32k3a_gpu.so")
 
-SOURCES = ["kernels.hip", "batch.hip", "host.cpp", "batch_host.cpp"]
+SOURCES = ["kernels.hip", "batch.hip", "host.cpp", "batch_host.cpp", "serve.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

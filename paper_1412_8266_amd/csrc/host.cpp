@@ -571,6 +571,7 @@ const char *mrg_status_string(mrg_status s)
     case MRG_EHIP: return "MRG_EHIP: HIP runtime error";
     case MRG_ERANGE: return "MRG_ERANGE: out of range";
     case MRG_ENODEV: return "MRG_ENODEV: no HIP device";
+    case MRG_EBUSY: return "MRG_EBUSY: waiting on memory or time";
     default: return "unknown mrg_status";
     }
 }
