@@ -13,7 +13,10 @@ Printed: ONE JSON line with the headline value plus
                    on the launch stream), and the counter-measured traffic;
   cpu_baseline  -- the CPU oracle (plain single-threaded C) timed on a bounded
                    sample of the same workload;
-  extra         -- FP32 and interleaved fills, jump and create timings.
+  extra         -- FP32 and interleaved fills, jump and create timings, the
+                   batched request mix against per-request launches, and
+                   p50/p99 latency of the serving engine under Poisson
+                   arrivals.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--engine 0|1]
 """
@@ -48,6 +51,9 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched request mix")
     ap.add_argument("--batch-reps", type=int, default=3)
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
+    ap.add_argument("--serve-seconds", type=float, default=10.0,
+                    help="length of the replayed arrival trace (the full trace is 60 s)")
     ap.add_argument("--quick", action="store_true", help="headline only (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device-to-device copy 3 times (to scale HBM counters)")
@@ -153,6 +159,43 @@ def batched(mg, wl, torch, stream, reps):
     del arena
     torch.cuda.synchronize()
     return out
+
+
+def serving(mg, wl, seconds):
+    """Continuous batching under Poisson arrivals: 20,000 requests/s from
+    50,000 clients, request sizes drawn as in the batched mix, a 64 GiB
+    output arena as the admission cap, outputs freed on completion.  The
+    first `seconds` of the 60-second trace are replayed in real time; the
+    latency of a request runs from its submission to its completion event."""
+    import numpy as np
+    arr = wl.c5_arrivals()
+    keep = arr.t < seconds
+    t, client = arr.t[keep], arr.client[keep]
+    k, n, dt = arr.req.n_streams[keep], arr.req.length[keep], arr.req.dtype[keep]
+    es = np.where(dt == 2, 8, 4)
+    from paper_1412_8266_amd.serve import Server
+    srv = Server(wl.C5_CLIENTS, wl.MASTER_SEED, wl.C5_ARENA_BYTES, auto_release=True)
+    wall = srv.run_trace(t, client, k, n, dt)
+    res = srv.poll()
+    st = srv.stats()
+    srv.close()
+    lat = np.sort(res["latency_s"]) * 1e3
+    que = np.sort(res["queue_s"]) * 1e3
+    samples = int((k * n).sum())
+
+    def pct(a, q):
+        return round(float(a[min(len(a) - 1, int(q * len(a)))]), 3) if len(a) else None
+
+    return {
+        "trace_seconds": seconds, "rate_per_s": wl.C5_RATE, "clients": wl.C5_CLIENTS,
+        "arena_GiB": wl.C5_ARENA_BYTES >> 30, "requests": int(keep.sum()),
+        "completed": int(len(res)), "ticks": int(st["ticks"]), "wall_s": round(wall, 3),
+        "offered_Gsamples_s": round(samples / seconds / 1e9, 2),
+        "served_Gsamples_s": round(samples / wall / 1e9, 2),
+        "served_GB_s": round(float((k * n * es).sum()) / wall / 1e9, 1),
+        "latency_ms": {"p50": pct(lat, 0.50), "p99": pct(lat, 0.99), "max": pct(lat, 1.0)},
+        "queue_ms": {"p50": pct(que, 0.50), "p99": pct(que, 0.99)},
+    }
 
 
 def main():
@@ -280,6 +323,10 @@ def main():
     if not args.quick and not args.no_batch:
         print("[bench] batched request mix", file=sys.stderr, flush=True)
         extra["batched"] = batched(mg, wl, torch, stream, args.batch_reps)
+    if not args.quick and not args.no_serve:
+        print("[bench] serving trace (%g s)" % args.serve_seconds, file=sys.stderr, flush=True)
+        torch.cuda.empty_cache()
+        extra["serving"] = serving(mg, wl, args.serve_seconds)
     res["extra"] = extra
 
     if not args.no_cpu and not args.quick:

@@ -208,9 +208,11 @@ typedef struct {
 typedef struct mrg_batch_s *mrg_batch;
 
 /* Plan a batch over stream set ss: validate the requests (plain requests
- * must cover disjoint stream ranges, else MRG_EINVAL), cut them into one-wave
- * work items, upload the plan and capture one hipGraph (counter reset,
- * persistent kernel, copy-back of end states).  reqs is copied; cfg may be
+ * must cover disjoint stream ranges and no substream request may name a
+ * stream that a plain request advances, else MRG_EINVAL), cut them into
+ * one-wave work items, group them by (dtype, item kind) and capture one
+ * hipGraph (per group a counter reset and a persistent kernel, then the
+ * copy-back of end states).  reqs is copied; cfg may be
  * NULL.  The plan refers to ss and to the output buffers, which must outlive
  * it.  Free with mrg_batch_destroy. */
 mrg_status mrg_batch_create(mrg_batch *out, mrg_streamset ss, const mrg_request *reqs,
@@ -355,7 +357,10 @@ mrg_status mrg_state_check(const uint32_t state6[6]);
  *   "strategy"   stream-major fill: 0 = automatic (default: one wave per
  *                stream when a stream has at least 64 x 128 bytes of output,
  *                else one lane per stream), 1 = always lane per stream,
- *                2 = always wave per stream.
+ *                2 = always wave per stream;
+ *   "coop_wgs_per_cu" wave-per-stream fill: one-wave workgroups per compute
+ *                unit, each looping over streams (0 = one workgroup per
+ *                stream, the default), 0 .. 1024.
  * Unknown keys or values: MRG_EINVAL.  Takes effect for later launches. */
 mrg_status mrg_config_set(const char *key, int64_t value);
 mrg_status mrg_config_get(const char *key, int64_t *value);

@@ -13,7 +13,7 @@ import os
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmrg32k3a_gpu.so")
 
-MRG_OK, MRG_EINVAL, MRG_ENOMEM, MRG_EHIP, MRG_ERANGE, MRG_ENODEV = 0, -1, -2, -3, -4, -5
+MRG_OK, MRG_EINVAL, MRG_ENOMEM, MRG_EHIP, MRG_ERANGE, MRG_ENODEV, MRG_EBUSY = 0, -1, -2, -3, -4, -5, -6
 MRG_U32, MRG_F32, MRG_F64 = 0, 1, 2
 MRG_STREAM_MAJOR, MRG_INTERLEAVED = 0, 1
 

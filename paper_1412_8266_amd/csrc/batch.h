@@ -1,8 +1,11 @@
-// Device descriptors of the persistent batch kernel (shared by batch.hip and
-// the host planner in batch_host.cpp).
+// Descriptors of the persistent batch kernels and the grouping of requests
+// into per-(dtype, kind) launches (shared by batch.hip, the planner in
+// batch_host.cpp and the server in serve.cpp).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+
+#include <vector>
 
 #include "kernels.h"
 
@@ -10,6 +13,9 @@ namespace mrg {
 
 constexpr uint32_t kReqSubstreams = 1u;  // streams are substreams of one stream; no write-back
 constexpr uint32_t kReqWriteBack = 2u;   // store each stream's end state
+
+constexpr int kKindWave = 0;  // one wave per stream segment
+constexpr int kKindRow = 1;   // one lane per stream, 64 streams per item
 
 // One request as the kernel sees it.  seg > 0: wave items, one per segment of
 // seg values of one stream (segs per stream); seg == 0: row items of up to 64
@@ -50,6 +56,37 @@ struct BatchArgs {
     uint64_t cb_slots;
 };
 
-hipError_t launch_batch(const BatchArgs &A, unsigned grid, int engine, hipStream_t st);
+inline int kind_of(const BatchReq &R) { return R.seg ? kKindWave : kKindRow; }
+inline uint64_t items_of(const BatchReq &R) { return R.seg ? R.k * R.segs : (R.k + 63) / 64; }
+
+// Requests reordered into (dtype, kind) groups, each with its own item
+// prefix; built on the host, uploaded as one request array and one prefix
+// array.
+struct Grouped {
+    struct Group {
+        int dtype, kind;
+        uint32_t req_off, nreq;  // slice of `reqs`
+        uint32_t prefix_off;     // slice of `prefix` (nreq + 1 entries)
+        uint64_t items;
+    };
+    std::vector<BatchReq> reqs;
+    std::vector<uint64_t> prefix;
+    std::vector<Group> groups;   // non-empty groups only
+    std::vector<uint32_t> pos;   // input request i -> index in reqs
+    uint64_t total_items = 0;
+};
+
+void group_requests(const std::vector<BatchReq> &in, Grouped *out);
+
+// Launch every group (counter reset + persistent kernel) on one stream.
+// base carries the state planes, tables, scratch and schedule; counters holds
+// one counter per group.
+hipError_t launch_grouped(const Grouped &g, const BatchReq *d_reqs, const uint64_t *d_prefix,
+                          unsigned long long *d_counters, const BatchArgs &base,
+                          uint64_t grid_cap, int engine, hipStream_t st);
+
+hipError_t launch_batch_group(const BatchArgs &A, int dtype, int kind, unsigned grid, int engine,
+                              hipStream_t st);
+hipError_t launch_copyback(const BatchArgs &A, hipStream_t st);
 
 }  // namespace mrg

@@ -39,14 +39,18 @@ __device__ __forceinline__ uint32_t find_req(const uint64_t *__restrict__ prefix
     return lo;
 }
 
-__device__ __forceinline__ uint64_t shfl64(uint64_t v, int src)
+// Lane 0's value in a scalar register, so that everything derived from it
+// (request index, descriptor fields, addresses) stays wave-uniform: scalar
+// loads, and no vector registers spent on it.
+__device__ __forceinline__ uint64_t lane0_uniform(uint64_t v)
 {
-    const uint32_t lo = __shfl((uint32_t)v, src), hi = __shfl((uint32_t)(v >> 32), src);
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
     return ((uint64_t)hi << 32) | lo;
 }
 
 template <int DT, class G>
-__device__ void wave_item(const BatchReq &R, uint64_t local, unsigned char *lds, int lane,
+__device__ __forceinline__ void wave_item(const BatchReq &R, uint64_t local, unsigned char *lds, int lane,
                           const BatchArgs &A)
 {
     constexpr int ES = Elem<DT>::size;
@@ -64,8 +68,8 @@ __device__ void wave_item(const BatchReq &R, uint64_t local, unsigned char *lds,
     uint32_t m[18];
 #pragma unroll
     for (int i = 0; i < 18; ++i) m[i] = A.lane_tab[(k * 64 + lane) * 18 + i];
-    const bool whole = wave_fill<DT, L, G>(w, m, lds, lane, R.out + j * R.n * ES, v0, v1,
-                                           R.vec_ok != 0);
+    const bool whole = wave_fill<DT, L, G, false>(w, m, lds, lane, R.out + j * R.n * ES, v0, v1,
+                                                  R.vec_ok != 0);
     if ((R.flags & kReqWriteBack) && v1 == R.n) {
         if (!whole) jump_global(A.table, (v1 - v0) % ((uint64_t)64 * L), 0, 0, 0, 16, w);
         if (lane == 0) {
@@ -76,7 +80,7 @@ __device__ void wave_item(const BatchReq &R, uint64_t local, unsigned char *lds,
 }
 
 template <int DT, class G>
-__device__ void row_item(const BatchReq &R, uint64_t local, unsigned char *lds, int lane,
+__device__ __forceinline__ void row_item(const BatchReq &R, uint64_t local, unsigned char *lds, int lane,
                          const BatchArgs &A)
 {
     constexpr int ES = Elem<DT>::size;
@@ -93,15 +97,20 @@ __device__ void row_item(const BatchReq &R, uint64_t local, unsigned char *lds, 
     }
     G g;
     g.load(w);
-    rows_fill<DT, 128, G>(g, lds, lane, nrows, R.out + r0 * R.n * ES, R.n * ES, R.n,
-                          R.vec_ok != 0);
+    rows_fill<DT, 128, G, false>(g, lds, lane, nrows, R.out + r0 * R.n * ES, R.n * ES, R.n,
+                                 R.vec_ok != 0);
     if ((R.flags & kReqWriteBack) && active) {
         g.store(w);
         store_state(A.planes, A.plane_stride, R.stream0 + j, w);
     }
 }
 
-template <class G>
+// One persistent kernel per (dtype, kind) group keeps each instantiation's
+// register use at that of the plain fill kernels.  The writers move each LDS
+// piece straight to memory (READ_ALL = false): staging all eight pieces in an
+// array first, as the plain fill kernels do, sends that array to scratch
+// memory inside this loop.
+template <int DT, int KIND, class G>
 __global__ void __launch_bounds__(64) batch_kernel(BatchArgs A)
 {
     __shared__ __attribute__((aligned(16))) unsigned char lds[64 * 144];
@@ -112,7 +121,7 @@ __global__ void __launch_bounds__(64) batch_kernel(BatchArgs A)
         if (A.dynamic) {
             uint64_t mine = 0;
             if (lane == 0) mine = atomicAdd(A.counter, 1ull);
-            item = shfl64(mine, 0);
+            item = lane0_uniform(mine);
         } else {
             item = next;
             next += gridDim.x;
@@ -121,15 +130,8 @@ __global__ void __launch_bounds__(64) batch_kernel(BatchArgs A)
         const uint32_t r = find_req(A.prefix, A.nreq, item);
         const BatchReq R = A.reqs[r];
         const uint64_t local = item - A.prefix[r];
-        if (R.seg) {
-            if (R.dtype == 0) wave_item<0, G>(R, local, lds, lane, A);
-            else if (R.dtype == 1) wave_item<1, G>(R, local, lds, lane, A);
-            else wave_item<2, G>(R, local, lds, lane, A);
-        } else {
-            if (R.dtype == 0) row_item<0, G>(R, local, lds, lane, A);
-            else if (R.dtype == 1) row_item<1, G>(R, local, lds, lane, A);
-            else row_item<2, G>(R, local, lds, lane, A);
-        }
+        if constexpr (KIND == kKindWave) wave_item<DT, G>(R, local, lds, lane, A);
+        else row_item<DT, G>(R, local, lds, lane, A);
     }
 }
 
@@ -148,13 +150,32 @@ __global__ void __launch_bounds__(256) batch_copyback_kernel(BatchArgs A)
     store_state(A.planes, A.plane_stride, A.cb_stream0[e] + off, w);
 }
 
-hipError_t launch_batch(const BatchArgs &A, unsigned grid, int engine, hipStream_t st)
+template <class G>
+static void launch_group_g(const BatchArgs &A, int dtype, int kind, unsigned grid, hipStream_t st)
+{
+    const dim3 g(grid), b(64);
+    if (kind == kKindWave) {
+        if (dtype == 0) hipLaunchKernelGGL((batch_kernel<0, kKindWave, G>), g, b, 0, st, A);
+        else if (dtype == 1) hipLaunchKernelGGL((batch_kernel<1, kKindWave, G>), g, b, 0, st, A);
+        else hipLaunchKernelGGL((batch_kernel<2, kKindWave, G>), g, b, 0, st, A);
+    } else {
+        if (dtype == 0) hipLaunchKernelGGL((batch_kernel<0, kKindRow, G>), g, b, 0, st, A);
+        else if (dtype == 1) hipLaunchKernelGGL((batch_kernel<1, kKindRow, G>), g, b, 0, st, A);
+        else hipLaunchKernelGGL((batch_kernel<2, kKindRow, G>), g, b, 0, st, A);
+    }
+}
+
+hipError_t launch_batch_group(const BatchArgs &A, int dtype, int kind, unsigned grid, int engine,
+                              hipStream_t st)
 {
     if (A.dynamic) hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(1), 0, st, A.counter);
-    if (engine == 1)
-        hipLaunchKernelGGL(batch_kernel<GenF>, dim3(grid), dim3(64), 0, st, A);
-    else
-        hipLaunchKernelGGL(batch_kernel<GenI>, dim3(grid), dim3(64), 0, st, A);
+    if (engine == 1) launch_group_g<GenF>(A, dtype, kind, grid, st);
+    else launch_group_g<GenI>(A, dtype, kind, grid, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_copyback(const BatchArgs &A, hipStream_t st)
+{
     if (A.cb_slots)
         hipLaunchKernelGGL(batch_copyback_kernel, dim3((unsigned)((A.cb_slots + 255) / 256)),
                            dim3(256), 0, st, A);

@@ -1,9 +1,10 @@
-// Batched generation: planner, hipGraph capture, per-request baseline and the
-// autotuner of the persistent batch kernel (batch.hip).
+// Batched generation: planner, hipGraph capture, per-request reference
+// schedule and the autotuner of the persistent batch kernels (batch.hip).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cstring>
+#include <iterator>
 #include <new>
 #include <vector>
 
@@ -12,6 +13,58 @@
 
 using mrg::hip_error;
 using mrg::set_error;
+
+namespace mrg {
+
+void group_requests(const std::vector<BatchReq> &in, Grouped *out)
+{
+    out->reqs.clear();
+    out->prefix.clear();
+    out->groups.clear();
+    out->pos.assign(in.size(), 0);
+    out->total_items = 0;
+    for (int dtype = 0; dtype < 3; ++dtype)
+        for (int kind = 0; kind < 2; ++kind) {
+            Grouped::Group g = {dtype, kind, (uint32_t)out->reqs.size(), 0,
+                                (uint32_t)out->prefix.size(), 0};
+            out->prefix.push_back(0);
+            for (size_t i = 0; i < in.size(); ++i) {
+                if ((int)in[i].dtype != dtype || kind_of(in[i]) != kind) continue;
+                out->pos[i] = (uint32_t)out->reqs.size();
+                out->reqs.push_back(in[i]);
+                g.items += items_of(in[i]);
+                out->prefix.push_back(g.items);
+                ++g.nreq;
+            }
+            if (g.nreq) {
+                out->groups.push_back(g);
+                out->total_items += g.items;
+            } else {
+                out->prefix.pop_back();
+            }
+        }
+}
+
+hipError_t launch_grouped(const Grouped &g, const BatchReq *d_reqs, const uint64_t *d_prefix,
+                          unsigned long long *d_counters, const BatchArgs &base,
+                          uint64_t grid_cap, int engine, hipStream_t st)
+{
+    for (size_t i = 0; i < g.groups.size(); ++i) {
+        const Grouped::Group &G = g.groups[i];
+        BatchArgs A = base;
+        A.reqs = d_reqs + G.req_off;
+        A.prefix = d_prefix + G.prefix_off;
+        A.nreq = G.nreq;
+        A.total_items = G.items;
+        A.counter = d_counters + i;
+        const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min(grid_cap, G.items));
+        hipError_t e = launch_batch_group(A, G.dtype, G.kind, grid, engine, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace mrg
 
 struct mrg_batch_s {
     mrg_streamset ss = nullptr;
@@ -22,17 +75,17 @@ struct mrg_batch_s {
     int engine = 1;
 
     // plan (host mirror and device copies)
-    std::vector<mrg::BatchReq> breqs;
-    std::vector<uint64_t> prefix;    // [nreq + 1]
+    mrg::Grouped plan;
+    std::vector<uint32_t> req_of;    // non-empty request -> input index
     std::vector<uint64_t> cb_prefix, cb_stream0, cb_scratch0;
-    uint64_t total_items = 0, scratch_slots = 0, samples = 0, bytes = 0;
+    uint64_t scratch_slots = 0, samples = 0, bytes = 0;
     mrg::BatchReq *d_reqs = nullptr;
     uint64_t *d_prefix = nullptr;
     uint64_t *d_solo = nullptr;      // [nreq][2]: {0, items of request r}
     uint64_t *d_cb = nullptr;        // cb_prefix | cb_stream0 | cb_scratch0
-    unsigned long long *d_counter = nullptr;
+    unsigned long long *d_counter = nullptr;  // one per group
     uint32_t *d_scratch = nullptr;
-    unsigned grid = 0;
+    uint64_t grid_cap = 0;
 
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -80,18 +133,18 @@ mrg_status upload(T **dst, const std::vector<T> &src, const char *what)
     return MRG_OK;
 }
 
-// Cut the requests into work items under b->cfg and upload the plan.
+// Cut the requests into work items under b->cfg, group them and upload the plan.
 mrg_status build_plan(mrg_batch b)
 {
     free_plan(b);
-    b->breqs.clear();
-    b->prefix.assign(1, 0);
+    b->req_of.clear();
     b->cb_prefix.assign(1, 0);
     b->cb_stream0.clear();
     b->cb_scratch0.clear();
-    b->total_items = b->scratch_slots = b->samples = b->bytes = 0;
-    std::vector<uint64_t> solo;
-    for (const mrg_request &q : b->reqs) {
+    b->scratch_slots = b->samples = b->bytes = 0;
+    std::vector<mrg::BatchReq> in;
+    for (size_t i = 0; i < b->reqs.size(); ++i) {
+        const mrg_request &q = b->reqs[i];
         if (!q.count || !q.n_per_stream) continue;
         const uint64_t es = q.dtype == MRG_F64 ? 8 : 4;
         const uint64_t chunk = 64 * (256 / es);  // values per wave_fill chunk
@@ -104,13 +157,11 @@ mrg_status build_plan(mrg_batch b)
         R.dtype = (uint32_t)q.dtype;
         R.flags = (q.flags & MRG_REQ_SUBSTREAMS) ? mrg::kReqSubstreams : mrg::kReqWriteBack;
         R.vec_ok = ((uintptr_t)q.d_out % 16 == 0) && ((R.n * es) % 16 == 0);
-        uint64_t items;
         if (R.n * es >= b->cfg.wave_min_bytes) {
             uint64_t seg = b->cfg.segment_bytes / es / chunk * chunk;
             if (seg < chunk) seg = chunk;
             R.seg = seg;
             R.segs = (R.n + seg - 1) / seg;
-            items = R.k * R.segs;
             if (R.segs > 1 && (R.flags & mrg::kReqWriteBack)) {
                 R.scratch0 = b->scratch_slots;
                 b->cb_stream0.push_back(R.stream0);
@@ -121,46 +172,42 @@ mrg_status build_plan(mrg_batch b)
         } else {
             R.seg = 0;
             R.segs = 1;
-            items = (R.k + 63) / 64;
         }
-        b->breqs.push_back(R);
-        solo.push_back(0);
-        solo.push_back(items);
-        b->total_items += items;
-        b->prefix.push_back(b->total_items);
+        in.push_back(R);
+        b->req_of.push_back((uint32_t)i);
         b->samples += R.k * R.n;
         b->bytes += R.k * R.n * es;
     }
+    mrg::group_requests(in, &b->plan);
+    std::vector<uint64_t> solo;
+    for (const mrg::BatchReq &R : in) {
+        solo.push_back(0);
+        solo.push_back(mrg::items_of(R));
+    }
     mrg_status st;
-    if ((st = upload(&b->d_reqs, b->breqs, "batch requests"))) return st;
-    if ((st = upload(&b->d_prefix, b->prefix, "batch prefix"))) return st;
+    if ((st = upload(&b->d_reqs, b->plan.reqs, "batch requests"))) return st;
+    if ((st = upload(&b->d_prefix, b->plan.prefix, "batch prefix"))) return st;
     if ((st = upload(&b->d_solo, solo, "batch solo prefix"))) return st;
     std::vector<uint64_t> cb(b->cb_prefix);
     cb.insert(cb.end(), b->cb_stream0.begin(), b->cb_stream0.end());
     cb.insert(cb.end(), b->cb_scratch0.begin(), b->cb_scratch0.end());
     if ((st = upload(&b->d_cb, cb, "batch copy-back"))) return st;
-    hipError_t e = hipMalloc((void **)&b->d_counter, sizeof(unsigned long long));
-    if (e != hipSuccess) return set_error(MRG_ENOMEM, "hipMalloc(counter)");
+    hipError_t e = hipMalloc((void **)&b->d_counter, 6 * sizeof(unsigned long long));
+    if (e != hipSuccess) return set_error(MRG_ENOMEM, "hipMalloc(counters)");
     if (b->scratch_slots) {
         e = hipMalloc((void **)&b->d_scratch, 6 * b->scratch_slots * sizeof(uint32_t));
         if (e != hipSuccess)
             return set_error(MRG_ENOMEM, "hipMalloc(batch scratch, %llu states)",
                              (unsigned long long)b->scratch_slots);
     }
-    const uint64_t cap = (uint64_t)b->tabs.cus * b->cfg.waves_per_cu;
-    b->grid = (unsigned)std::max<uint64_t>(1, std::min<uint64_t>(cap, b->total_items));
+    b->grid_cap = (uint64_t)b->tabs.cus * b->cfg.waves_per_cu;
     return MRG_OK;
 }
 
-mrg::BatchArgs args_of(mrg_batch b)
+mrg::BatchArgs base_args(mrg_batch b)
 {
     mrg::BatchArgs A = {};
-    A.reqs = b->d_reqs;
-    A.prefix = b->d_prefix;
-    A.nreq = (uint32_t)b->breqs.size();
     A.dynamic = b->cfg.schedule == MRG_SCHEDULE_STATIC ? 0u : 1u;
-    A.total_items = b->total_items;
-    A.counter = b->d_counter;
     A.planes = b->ss->d_planes;
     A.plane_stride = b->ss->n;
     A.scratch = b->d_scratch;
@@ -176,16 +223,25 @@ mrg::BatchArgs args_of(mrg_batch b)
     return A;
 }
 
+hipError_t launch_all(mrg_batch b, hipStream_t st)
+{
+    const mrg::BatchArgs A = base_args(b);
+    hipError_t e = mrg::launch_grouped(b->plan, b->d_reqs, b->d_prefix, b->d_counter, A,
+                                       b->grid_cap, b->engine, st);
+    if (e == hipSuccess) e = mrg::launch_copyback(A, st);
+    return e;
+}
+
 mrg_status capture(mrg_batch b)
 {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
     b->exec = nullptr;
     b->graph = nullptr;
-    if (!b->total_items) return MRG_OK;
+    if (!b->plan.total_items) return MRG_OK;
     hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_error(e, "hipStreamBeginCapture");
-    hipError_t le = mrg::launch_batch(args_of(b), b->grid, b->engine, b->cap_stream);
+    hipError_t le = launch_all(b, b->cap_stream);
     e = hipStreamEndCapture(b->cap_stream, &b->graph);
     if (le != hipSuccess) return hip_error(le, "batch kernel capture");
     if (e != hipSuccess) return hip_error(e, "hipStreamEndCapture");
@@ -230,6 +286,18 @@ mrg_status validate(mrg_streamset ss, const mrg_request *reqs, uint64_t n)
             return set_error(MRG_EINVAL, "requests overlap on streams [%llu, %llu)",
                              (unsigned long long)spans[i].first,
                              (unsigned long long)std::min(spans[i].second, spans[i - 1].second));
+    // a substream request reads its stream's state, which a plain request on
+    // that stream would overwrite in the same run
+    for (uint64_t i = 0; i < n; ++i) {
+        const mrg_request &q = reqs[i];
+        if (!q.count || !q.n_per_stream || !(q.flags & MRG_REQ_SUBSTREAMS)) continue;
+        auto it = std::upper_bound(spans.begin(), spans.end(),
+                                   std::make_pair(q.first, UINT64_MAX));
+        if (it != spans.begin() && q.first < std::prev(it)->second)
+            return set_error(MRG_EINVAL, "request %llu: substreams of stream %llu, which a plain "
+                             "request of the batch advances", (unsigned long long)i,
+                             (unsigned long long)q.first);
+    }
     return MRG_OK;
 }
 
@@ -292,37 +360,37 @@ mrg_status mrg_batch_run(mrg_batch b, void *stream)
 mrg_status mrg_batch_run_direct(mrg_batch b, void *stream)
 {
     if (!b) return set_error(MRG_EINVAL, "null batch");
-    if (!b->total_items) return MRG_OK;
-    hipError_t e = mrg::launch_batch(args_of(b), b->grid, b->engine, (hipStream_t)stream);
+    if (!b->plan.total_items) return MRG_OK;
+    hipError_t e = launch_all(b, (hipStream_t)stream);
     return e == hipSuccess ? MRG_OK : hip_error(e, "batch kernel launch");
 }
 
 mrg_status mrg_batch_run_per_request(mrg_batch b, void *stream)
 {
     if (!b) return set_error(MRG_EINVAL, "null batch");
-    size_t r = 0;
-    for (const mrg_request &q : b->reqs) {
-        if (!q.count || !q.n_per_stream) continue;
+    for (size_t r = 0; r < b->req_of.size(); ++r) {
+        const mrg_request &q = b->reqs[b->req_of[r]];
         mrg_status st;
         if (q.flags & MRG_REQ_SUBSTREAMS) {
-            // the batch kernel on this one request
-            mrg::BatchArgs A = args_of(b);
-            A.reqs = b->d_reqs + r;
+            // the batch kernel restricted to this one request
+            const uint32_t p = b->plan.pos[r];
+            const mrg::BatchReq &R = b->plan.reqs[p];
+            mrg::BatchArgs A = base_args(b);
+            A.reqs = b->d_reqs + p;
             A.prefix = b->d_solo + 2 * r;
             A.nreq = 1;
-            A.total_items = b->prefix[r + 1] - b->prefix[r];
-            A.n_cb = 0;
-            A.cb_slots = 0;
-            const uint64_t cap = (uint64_t)b->tabs.cus * b->cfg.waves_per_cu;
-            const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min(cap, A.total_items));
-            hipError_t e = mrg::launch_batch(A, grid, b->engine, (hipStream_t)stream);
+            A.total_items = mrg::items_of(R);
+            A.counter = b->d_counter;
+            const unsigned grid =
+                (unsigned)std::max<uint64_t>(1, std::min(b->grid_cap, A.total_items));
+            hipError_t e = mrg::launch_batch_group(A, (int)R.dtype, mrg::kind_of(R), grid,
+                                                   b->engine, (hipStream_t)stream);
             st = e == hipSuccess ? MRG_OK : hip_error(e, "batch kernel launch");
         } else {
             st = mrg_fill(b->ss, q.first, q.count, q.n_per_stream, (mrg_dtype)q.dtype,
                           MRG_STREAM_MAJOR, q.d_out, stream);
         }
         if (st) return st;
-        ++r;
     }
     return MRG_OK;
 }
@@ -330,11 +398,11 @@ mrg_status mrg_batch_run_per_request(mrg_batch b, void *stream)
 mrg_status mrg_batch_info(mrg_batch b, mrg_batch_info_t *info)
 {
     if (!b || !info) return set_error(MRG_EINVAL, "null argument");
-    info->requests = b->breqs.size();
-    info->items = b->total_items;
+    info->requests = b->req_of.size();
+    info->items = b->plan.total_items;
     info->samples = b->samples;
     info->bytes = b->bytes;
-    info->grid = b->grid;
+    info->grid = (uint32_t)std::max<uint64_t>(1, std::min(b->grid_cap, b->plan.total_items));
     info->scratch_states = b->scratch_slots;
     info->config = b->cfg;
     return MRG_OK;
@@ -360,6 +428,7 @@ mrg_status mrg_batch_autotune(mrg_batch b, const mrg_batch_config *cands, uint32
     float best_ms = 0;
     const mrg_batch_config keep = b->cfg;
     for (uint32_t i = 0; i < n_cands && status == MRG_OK; ++i) {
+        (void)hipStreamSynchronize(st);
         b->cfg = effective(&cands[i]);
         if ((status = build_plan(b)) || (status = capture(b))) break;
         if ((status = mrg_batch_run(b, stream))) break;  // warm-up

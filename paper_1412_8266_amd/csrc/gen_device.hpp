@@ -27,6 +27,7 @@ __device__ __forceinline__ void jump_global(const uint32_t *__restrict__ table, 
                                             uint64_t e1, uint64_t e2, int w_lo, int w_hi,
                                             uint32_t *st)
 {
+#pragma unroll 1
     for (int w = w_lo; w < w_hi; ++w) {
         const uint32_t d = exp_digit(e0, e1, e2, w);
         if (!__any(d != 0u)) continue;
@@ -159,7 +160,7 @@ __device__ __forceinline__ void copy_elem(unsigned char *dst, const unsigned cha
 // at out0 + r * row_stride.  `lds` holds 64 * (TB + 16) bytes; the caller's
 // workgroup is this one wave.
 // ---------------------------------------------------------------------------
-template <int DT, int TB, class G>
+template <int DT, int TB, class G, bool READ_ALL = true>
 __device__ __forceinline__ void rows_fill(G &g, unsigned char *lds, int lane, uint64_t nrows,
                                           unsigned char *out0, uint64_t row_stride, uint64_t n,
                                           bool vec_ok)
@@ -188,7 +189,7 @@ __device__ __forceinline__ void rows_fill(G &g, unsigned char *lds, int lane, ui
         for (int c = 0; c < TB / 16; ++c) *(uint4 *)(my_lds + c * 16) = gen16<DT>(g);
         __syncthreads();
         const uint64_t off = t * TB;
-        if (vec_ok) {
+        if (vec_ok && READ_ALL) {
             // all LDS reads first, one wait, then the stores
             uint4 v[NJ];
 #pragma unroll
@@ -201,6 +202,12 @@ __device__ __forceinline__ void rows_fill(G &g, unsigned char *lds, int lane, ui
 #pragma unroll
                 for (int j = 0; j < NJ; ++j)
                     if (rowa[j]) *(uint4 *)(rowp[j] + off) = v[j];
+            }
+        } else if (vec_ok) {
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const uint4 v = *(const uint4 *)(lds + (lane / LPR + RPI * j) * RS + chunk * 16);
+                if (rowa[j]) *(uint4 *)(rowp[j] + off) = v;
             }
         } else {
             // element stores: lane e covers (row e / TV, col e % TV)
@@ -241,7 +248,7 @@ __device__ __forceinline__ void rows_fill(G &g, unsigned char *lds, int lane, ui
 // left as the last chunk's first state and it returns false.  `lds` holds
 // 64 * 144 bytes.
 // ---------------------------------------------------------------------------
-template <int DT, int L, class G>
+template <int DT, int L, class G, bool READ_ALL = true>
 __device__ __forceinline__ bool wave_fill(uint32_t *w, const uint32_t *m, unsigned char *lds,
                                           int lane, unsigned char *srow, uint64_t v0, uint64_t v1,
                                           bool vec_ok)
@@ -269,13 +276,23 @@ __device__ __forceinline__ bool wave_fill(uint32_t *w, const uint32_t *m, unsign
             for (int q = 0; q < 8; ++q) *(uint4 *)(my_lds + q * 16) = gen16<DT>(g);
             __syncthreads();
             if (full && vec_ok) {
-                uint4 v[8];
+                if constexpr (READ_ALL) {
+                    uint4 v[8];
 #pragma unroll
-                for (int j = 0; j < 8; ++j) v[j] = *(const uint4 *)(lds + (prow + 8 * j) * RS + pcol);
+                    for (int j = 0; j < 8; ++j)
+                        v[j] = *(const uint4 *)(lds + (prow + 8 * j) * RS + pcol);
 #pragma unroll
-                for (int j = 0; j < 8; ++j) {
-                    const uint64_t pos = c0 + (uint64_t)(prow + 8 * j) * L + h * TV;
-                    *(uint4 *)(srow + pos * ES + pcol) = v[j];
+                    for (int j = 0; j < 8; ++j) {
+                        const uint64_t pos = c0 + (uint64_t)(prow + 8 * j) * L + h * TV;
+                        *(uint4 *)(srow + pos * ES + pcol) = v[j];
+                    }
+                } else {
+#pragma unroll
+                    for (int j = 0; j < 8; ++j) {
+                        const uint4 v = *(const uint4 *)(lds + (prow + 8 * j) * RS + pcol);
+                        const uint64_t pos = c0 + (uint64_t)(prow + 8 * j) * L + h * TV;
+                        *(uint4 *)(srow + pos * ES + pcol) = v;
+                    }
                 }
             } else {
                 for (int e = lane; e < 64 * TV; e += 64) {

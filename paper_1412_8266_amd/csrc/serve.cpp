@@ -101,10 +101,11 @@ struct Slot {  // one tick in flight
     hipEvent_t done = nullptr;
     mrg::BatchReq *d_reqs = nullptr;
     uint64_t *d_prefix = nullptr;
-    unsigned long long *d_counter = nullptr;
+    unsigned long long *d_counter = nullptr;  // one per (dtype, kind) group
     mrg::BatchReq *h_reqs = nullptr;  // pinned staging
     uint64_t *h_prefix = nullptr;
     std::vector<Req> reqs;
+    mrg::Grouped plan;
     bool busy = false;
 };
 
@@ -162,39 +163,31 @@ mrg::BatchReq to_batch_req(mrg_server s, const Req &r)
     return R;
 }
 
-uint64_t items_of(const mrg::BatchReq &R) { return R.seg ? R.k * R.segs : (R.k + 63) / 64; }
-
-// Launch the admitted requests of `slot` (scheduler thread).
+// Launch the admitted requests of `slot` (scheduler thread): one persistent
+// kernel per (dtype, kind) group, all on the slot's stream.
 mrg_status launch_tick(mrg_server s, Slot &slot)
 {
-    uint64_t total = 0;
-    slot.h_prefix[0] = 0;
-    for (size_t i = 0; i < slot.reqs.size(); ++i) {
-        slot.h_reqs[i] = to_batch_req(s, slot.reqs[i]);
-        total += items_of(slot.h_reqs[i]);
-        slot.h_prefix[i + 1] = total;
-    }
-    const size_t nr = slot.reqs.size();
+    std::vector<mrg::BatchReq> in(slot.reqs.size());
+    for (size_t i = 0; i < slot.reqs.size(); ++i) in[i] = to_batch_req(s, slot.reqs[i]);
+    mrg::group_requests(in, &slot.plan);
+    const size_t nr = slot.plan.reqs.size(), np = slot.plan.prefix.size();
+    std::memcpy(slot.h_reqs, slot.plan.reqs.data(), nr * sizeof(mrg::BatchReq));
+    std::memcpy(slot.h_prefix, slot.plan.prefix.data(), np * sizeof(uint64_t));
     hipError_t e = hipMemcpyAsync(slot.d_reqs, slot.h_reqs, nr * sizeof(mrg::BatchReq),
                                   hipMemcpyHostToDevice, slot.stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(slot.d_prefix, slot.h_prefix, (nr + 1) * sizeof(uint64_t),
+        e = hipMemcpyAsync(slot.d_prefix, slot.h_prefix, np * sizeof(uint64_t),
                            hipMemcpyHostToDevice, slot.stream);
     if (e != hipSuccess) return hip_error(e, "tick upload");
     mrg::BatchArgs A = {};
-    A.reqs = slot.d_reqs;
-    A.prefix = slot.d_prefix;
-    A.nreq = (uint32_t)nr;
     A.dynamic = 1;
-    A.total_items = total;
-    A.counter = slot.d_counter;
     A.planes = s->clients->d_planes;
     A.plane_stride = s->clients->n;
     A.table = s->tabs.table;
     A.lane_tab = s->tabs.lane_tab;
     const uint64_t cap = (uint64_t)s->tabs.cus * s->cfg.waves_per_cu;
-    const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min(cap, total));
-    e = mrg::launch_batch(A, grid, s->engine, slot.stream);
+    e = mrg::launch_grouped(slot.plan, slot.d_reqs, slot.d_prefix, slot.d_counter, A, cap,
+                            s->engine, slot.stream);
     if (e == hipSuccess) e = hipEventRecord(slot.done, slot.stream);
     if (e != hipSuccess) return hip_error(e, "tick launch");
     slot.busy = true;
@@ -320,12 +313,12 @@ mrg_status mrg_server_create(mrg_server *out, const mrg_server_config *cfg_in)
         e = hipStreamCreateWithFlags(&slot.stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&slot.done, hipEventDisableTiming);
         if (e == hipSuccess) e = hipMalloc(&slot.d_reqs, cfg.max_batch * sizeof(mrg::BatchReq));
-        if (e == hipSuccess) e = hipMalloc(&slot.d_prefix, (cfg.max_batch + 1) * sizeof(uint64_t));
-        if (e == hipSuccess) e = hipMalloc(&slot.d_counter, sizeof(unsigned long long));
+        if (e == hipSuccess) e = hipMalloc(&slot.d_prefix, (cfg.max_batch + 6) * sizeof(uint64_t));
+        if (e == hipSuccess) e = hipMalloc(&slot.d_counter, 6 * sizeof(unsigned long long));
         if (e == hipSuccess)
             e = hipHostMalloc(&slot.h_reqs, cfg.max_batch * sizeof(mrg::BatchReq), 0);
         if (e == hipSuccess)
-            e = hipHostMalloc(&slot.h_prefix, (cfg.max_batch + 1) * sizeof(uint64_t), 0);
+            e = hipHostMalloc(&slot.h_prefix, (cfg.max_batch + 6) * sizeof(uint64_t), 0);
         if (e != hipSuccess) {
             st = hip_error(e, "server slot setup");
             break;

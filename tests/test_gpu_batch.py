@@ -145,6 +145,52 @@ def test_substream_requests(mg):
     ss.close()
 
 
+@pytest.mark.parametrize("engine", [0, 1], ids=["int", "f64"])
+def test_mixed_plain_and_substream_groups(mg, engine):
+    """Plain and substream requests of all three dtypes, rows and waves,
+    in one batch: one persistent kernel per (dtype, kind) group."""
+    import torch
+    say("mixed groups", engine)
+    old = mg.mrg_config_get("engine")
+    mg.mrg_config_set("engine", engine)
+    try:
+        rng = np.random.default_rng(SEED + 11)
+        rows, outs, specs, nplain = make_plain(mg, rng, 30, 120, 50000, 4_000_000)
+        subs = []
+        for i in range(12):
+            s = nplain + int(rng.integers(0, 4))
+            k = int(wl.log_uniform_int(rng, 80, 1)[0])
+            n = int(wl.log_uniform_int(rng, 30000, 1)[0])
+            if k * n > 300_000:
+                n = max(1, 300_000 // k)
+            sub0 = int(rng.integers(0, 1 << 30))
+            dt = i % 3
+            t = torch.empty((k, n), dtype=mg.torch_dtype(dt), device="cuda")
+            rows.append((s, k, n, sub0, t.data_ptr(), dt, mg.REQ_SUBSTREAMS))
+            outs.append(t)
+            subs.append((s, k, n, sub0, dt))
+        order = rng.permutation(len(rows))
+        base = oracle.seed_from_master(SEED + 11)
+        ss = mg.StreamSet(nplain + 4, seed=[int(x) for x in base])
+        st0 = oracle.streams(base, 0, nplain + 4)
+        b = mg.Batch(ss, [rows[i] for i in order], mg.batch_config(segment_bytes=32 * 1024))
+        b.run()
+        check_plain(base, specs, outs[:len(specs)], st0)
+        for (s, k, n, sub0, dt), t in zip(subs, outs[len(specs):]):
+            starts = np.stack([oracle.jump(st0[s], (sub0 + j) << 76) for j in range(k)])
+            want, _ = oracle.fill(starts, n, dt)
+            assert np.array_equal(host(t).view(np.uint8), want.view(np.uint8)), (s, k, n, sub0)
+        st1 = st0.copy()
+        for first, k, n, dt in specs:
+            if k and n:
+                st1[first:first + k] = oracle.jump_many(st0[first:first + k], n)
+        assert np.array_equal(ss.get_states(), st1)
+        b.close()
+        ss.close()
+    finally:
+        mg.mrg_config_set("engine", old)
+
+
 def test_graph_direct_and_per_request_agree(mg):
     import torch
     say("graph vs direct vs per-request")
@@ -207,6 +253,13 @@ def test_batch_validation(mg):
         mg.Batch(ss, [(95, 10, 10, 0, t.data_ptr(), 0, 0)])
     with pytest.raises(mg.MRGError):  # bad dtype
         mg.Batch(ss, [(0, 10, 10, 0, t.data_ptr(), 7, 0)])
+    u = torch.empty((10, 10), dtype=torch.uint32, device="cuda")
+    with pytest.raises(mg.MRGError):  # substreams of a stream that a plain request advances
+        mg.Batch(ss, [(0, 10, 10, 0, t.data_ptr(), 0, 0),
+                      (3, 10, 10, 0, u.data_ptr(), 0, mg.REQ_SUBSTREAMS)])
+    b = mg.Batch(ss, [(0, 10, 10, 0, t.data_ptr(), 0, 0),  # next to it is fine
+                      (10, 10, 10, 0, u.data_ptr(), 0, mg.REQ_SUBSTREAMS)])
+    b.close()
     b = mg.Batch(ss, [])  # empty batch runs as a no-op
     b.run()
     b.close()
