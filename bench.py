@@ -36,7 +36,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
 METRIC = "uint32 Gsamples/s (% HBM write roofline), batched vs plain; p50/p99 latency"
 # HBM bytes per launch read by rocprofv3 (FETCH_SIZE + WRITE_SIZE, scaled by a
 # copy-kernel calibration); None until measured for the current kernel.
-COUNTER_TRAFFIC = 17644557467  # fill_coop_kernel<u32,64>: profiles/fill_coop_u32_2p20x4096.md
+COUNTER_TRAFFIC = None
 
 
 def parse():
@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--tile-bytes", type=int, default=None)
     ap.add_argument("--strategy", type=int, default=None, help="0 auto, 1 lane/stream, 2 wave/stream")
     ap.add_argument("--coop-wgs-per-cu", type=int, default=None)
+    ap.add_argument("--coop-lanes", type=int, default=None, help="lanes per stream: 64, 32 or 16")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched request mix")
     ap.add_argument("--batch-reps", type=int, default=3)
@@ -224,6 +225,8 @@ def main():
         mg.mrg_config_set("strategy", args.strategy)
     if args.coop_wgs_per_cu is not None:
         mg.mrg_config_set("coop_wgs_per_cu", args.coop_wgs_per_cu)
+    if args.coop_lanes is not None:
+        mg.mrg_config_set("coop_lanes", args.coop_lanes)
     engine = mg.mrg_config_get("engine")
     tile = mg.mrg_config_get("tile_bytes")
     stream = torch.cuda.current_stream()
@@ -271,6 +274,7 @@ def main():
             "master_seed": hex(wl.MASTER_SEED),
             "engine": "binary64" if engine == 1 else "int32",
             "tile_bytes": tile,
+            "coop_lanes": mg.mrg_config_get("coop_lanes"),
         },
         "roofline": {
             "bound": "hbm",
@@ -279,7 +283,8 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": COUNTER_TRAFFIC,
-            "kernel": "fill_coop_kernel<u32>" if n >= 2048 and mg.mrg_config_get("strategy") != 1
+            "kernel": ("fill_coop_kernel<u32, %d lanes per stream>" % mg.mrg_config_get("coop_lanes"))
+                      if n >= 2048 and mg.mrg_config_get("strategy") != 1
                       else "fill_sm_kernel<u32>",
             "alg_bytes_per_launch": alg_bytes,
             "avg_launch_ms": round(ms, 4),

@@ -359,8 +359,11 @@ mrg_status mrg_state_check(const uint32_t state6[6]);
  *                else one lane per stream), 1 = always lane per stream,
  *                2 = always wave per stream;
  *   "coop_wgs_per_cu" wave-per-stream fill: one-wave workgroups per compute
- *                unit, each looping over streams (0 = one workgroup per
- *                stream, the default), 0 .. 1024.
+ *                unit, each looping over stream groups (0 = one workgroup
+ *                per group, the default), 0 .. 1024;
+ *   "coop_lanes" wave-per-stream fill: lanes per stream, 64, 32 or 16
+ *                (default 16: 64/coop_lanes streams share a wave; used when
+ *                every row starts on a 128-byte boundary, else 64).
  * Unknown keys or values: MRG_EINVAL.  Takes effect for later launches. */
 mrg_status mrg_config_set(const char *key, int64_t value);
 mrg_status mrg_config_get(const char *key, int64_t *value);

@@ -18,8 +18,9 @@ constexpr int kKindWave = 0;  // one wave per stream segment
 constexpr int kKindRow = 1;   // one lane per stream, 64 streams per item
 
 // One request as the kernel sees it.  seg > 0: wave items, one per segment of
-// seg values of one stream (segs per stream); seg == 0: row items of up to 64
-// streams.
+// seg values of one stream (segs per stream), or, when a stream fits one
+// segment, one per spi consecutive whole streams; seg == 0: row items of up
+// to 64 streams.
 struct BatchReq {
     unsigned char *out;  // [k, n] stream-major output of dtype elements
     uint64_t stream0;    // plane index of stream 0 (substream mode: of the one stream)
@@ -32,7 +33,7 @@ struct BatchReq {
     uint32_t dtype;      // 0 u32, 1 f32, 2 f64
     uint32_t flags;      // kReqSubstreams | kReqWriteBack
     uint32_t vec_ok;     // 16-byte stores allowed (aligned rows)
-    uint32_t pad;
+    uint32_t spi;        // wave items: whole streams per item (segs == 1), else 1
 };
 
 struct BatchArgs {
@@ -47,7 +48,7 @@ struct BatchArgs {
     uint32_t *scratch;           // [6][scratch_stride]
     uint64_t scratch_stride;
     const uint32_t *table;       // windowed jump tables
-    const uint32_t *lane_tab;    // [3][64][18] A^(l*L), L in kLaneSegs
+    const uint32_t *lane_tab;    // [kNumLaneSegs][64][18] A^(l*L), L in kLaneSegs
     const uint64_t *cb_prefix;   // [n_cb + 1] copy-back slot prefix
     const uint64_t *cb_stream0;  // [n_cb] plane index of the entry's first stream
     const uint64_t *cb_scratch0; // [n_cb] scratch slot of the entry's first stream
@@ -57,7 +58,11 @@ struct BatchArgs {
 };
 
 inline int kind_of(const BatchReq &R) { return R.seg ? kKindWave : kKindRow; }
-inline uint64_t items_of(const BatchReq &R) { return R.seg ? R.k * R.segs : (R.k + 63) / 64; }
+inline uint64_t items_of(const BatchReq &R)
+{
+    if (!R.seg) return (R.k + 63) / 64;
+    return R.spi > 1 ? (R.k + R.spi - 1) / R.spi : R.k * R.segs;
+}
 
 // Requests reordered into (dtype, kind) groups, each with its own item
 // prefix; built on the host, uploaded as one request array and one prefix

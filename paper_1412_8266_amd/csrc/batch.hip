@@ -27,16 +27,22 @@ namespace mrg {
 
 __global__ void batch_reset_kernel(unsigned long long *counter) { *counter = 0ull; }
 
+// r with prefix[r] <= item < prefix[r+1] (prefix strictly increasing over
+// [0, nreq], item wave-uniform): a 64-way search, one probe per lane, so a
+// group of up to 4096 requests takes two dependent loads.
 __device__ __forceinline__ uint32_t find_req(const uint64_t *__restrict__ prefix, uint32_t nreq,
-                                             uint64_t item)
+                                             uint64_t item, int lane)
 {
     uint32_t lo = 0, hi = nreq;  // prefix[lo] <= item < prefix[hi]
-    while (hi - lo > 1) {
-        const uint32_t mid = (lo + hi) >> 1;
-        if (prefix[mid] <= item) lo = mid;
-        else hi = mid;
+    for (;;) {
+        const uint32_t step = hi - lo > 64 ? (hi - lo + 63) / 64 : 1;
+        const uint32_t idx = lo + (uint32_t)lane * step;
+        const bool le = idx < hi && prefix[idx] <= item;
+        const uint32_t cnt = (uint32_t)__popcll(__ballot(le));  // le holds on a prefix of lanes
+        lo += (cnt - 1) * step;
+        if (step == 1) return lo;
+        hi = lo + step < hi ? lo + step : hi;
     }
-    return lo;
 }
 
 // Lane 0's value in a scalar register, so that everything derived from it
@@ -50,31 +56,38 @@ __device__ __forceinline__ uint64_t lane0_uniform(uint64_t v)
 }
 
 template <int DT, class G>
-__device__ __forceinline__ void wave_item(const BatchReq &R, uint64_t local, unsigned char *lds, int lane,
-                          const BatchArgs &A)
+__device__ __forceinline__ void wave_item(const BatchReq &R, uint64_t local, unsigned char *lds,
+                                          int lane, const uint32_t *m, const BatchArgs &A)
 {
     constexpr int ES = Elem<DT>::size;
     constexpr int L = ES == 4 ? 64 : 32;  // 256 bytes per lane per chunk
-    constexpr int k = L == 64 ? 2 : 1;    // index into kLaneSegs {16, 32, 64}
-    const uint64_t j = local / R.segs, q = local % R.segs;
+    const bool subs = R.flags & kReqSubstreams;
+    uint64_t j0, j1, q;  // streams [j0, j1), segment q of each
+    if (R.spi > 1) {
+        j0 = local * R.spi;
+        j1 = j0 + R.spi < R.k ? j0 + R.spi : R.k;
+        q = 0;
+    } else {
+        j0 = local / R.segs;
+        j1 = j0 + 1;
+        q = local % R.segs;
+    }
     const uint64_t v0 = q * R.seg;
     const uint64_t v1 = v0 + R.seg < R.n ? v0 + R.seg : R.n;
-    const bool subs = R.flags & kReqSubstreams;
-    uint32_t w[6];
-    load_state(A.planes, A.plane_stride, subs ? R.stream0 : R.stream0 + j, w);
-    const uint64_t sub = subs ? R.sub0 + j : 0;
-    // exponent v0 + sub * 2^76 (v0 < 2^64: no carry between the words)
-    jump_global(A.table, v0, sub << 12, sub >> 52, 0, kTableWindows, w);
-    uint32_t m[18];
-#pragma unroll
-    for (int i = 0; i < 18; ++i) m[i] = A.lane_tab[(k * 64 + lane) * 18 + i];
-    const bool whole = wave_fill<DT, L, G, false>(w, m, lds, lane, R.out + j * R.n * ES, v0, v1,
-                                                  R.vec_ok != 0);
-    if ((R.flags & kReqWriteBack) && v1 == R.n) {
-        if (!whole) jump_global(A.table, (v1 - v0) % ((uint64_t)64 * L), 0, 0, 0, 16, w);
-        if (lane == 0) {
-            if (R.segs == 1) store_state(A.planes, A.plane_stride, R.stream0 + j, w);
-            else store_state(A.scratch, A.scratch_stride, R.scratch0 + j, w);
+    for (uint64_t j = j0; j < j1; ++j) {
+        uint32_t w[6];
+        load_state(A.planes, A.plane_stride, subs ? R.stream0 : R.stream0 + j, w);
+        const uint64_t sub = subs ? R.sub0 + j : 0;
+        // exponent v0 + sub * 2^76 (v0 < 2^64: no carry between the words)
+        jump_global(A.table, v0, sub << 12, sub >> 52, 0, kTableWindows, w);
+        const bool end = (R.flags & kReqWriteBack) && v1 == R.n;
+        wave_fill<DT, L, G, false>(w, m, lds, lane, R.out + j * R.n * ES, 0, 1, v0, v1, A.table,
+                                   A.lane_tab + kHeadTable * 64 * 18, end);
+        if (end) {
+            if (lane == 0) {
+                if (R.segs == 1) store_state(A.planes, A.plane_stride, R.stream0 + j, w);
+                else store_state(A.scratch, A.scratch_stride, R.scratch0 + j, w);
+            }
         }
     }
 }
@@ -115,6 +128,12 @@ __global__ void __launch_bounds__(64) batch_kernel(BatchArgs A)
 {
     __shared__ __attribute__((aligned(16))) unsigned char lds[64 * 144];
     const int lane = threadIdx.x;
+    uint32_t m[18];  // wave items: the lane's A^(lane * L), L = 256 bytes of values
+    if constexpr (KIND == kKindWave) {
+        constexpr int k = Elem<DT>::size == 4 ? 2 : 1;  // kLaneSegs[k] = 64 or 32
+#pragma unroll
+        for (int i = 0; i < 18; ++i) m[i] = A.lane_tab[(k * 64 + lane) * 18 + i];
+    }
     uint64_t next = blockIdx.x;  // static schedule: blockIdx.x + t * gridDim.x
     for (;;) {
         uint64_t item;
@@ -127,12 +146,25 @@ __global__ void __launch_bounds__(64) batch_kernel(BatchArgs A)
             next += gridDim.x;
         }
         if (item >= A.total_items) break;
-        const uint32_t r = find_req(A.prefix, A.nreq, item);
+        const uint32_t r = find_req(A.prefix, A.nreq, item, lane);
         const BatchReq R = A.reqs[r];
         const uint64_t local = item - A.prefix[r];
-        if constexpr (KIND == kKindWave) wave_item<DT, G>(R, local, lds, lane, A);
+        if constexpr (KIND == kKindWave) wave_item<DT, G>(R, local, lds, lane, m, A);
         else row_item<DT, G>(R, local, lds, lane, A);
     }
+}
+
+// Entry e with cb_prefix[e] <= s < cb_prefix[e+1] (per-thread binary search).
+__device__ __forceinline__ uint32_t cb_entry(const uint64_t *__restrict__ prefix, uint32_t n,
+                                             uint64_t s)
+{
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (prefix[mid] <= s) lo = mid;
+        else hi = mid;
+    }
+    return lo;
 }
 
 // Move the end states of multi-segment streams from scratch to the planes.
@@ -143,7 +175,7 @@ __global__ void __launch_bounds__(256) batch_copyback_kernel(BatchArgs A)
 {
     const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= A.cb_slots) return;
-    const uint32_t e = find_req(A.cb_prefix, A.n_cb, s);
+    const uint32_t e = cb_entry(A.cb_prefix, A.n_cb, s);
     const uint64_t off = s - A.cb_prefix[e];
     uint32_t w[6];
     load_state(A.scratch, A.scratch_stride, A.cb_scratch0[e] + off, w);

@@ -162,6 +162,9 @@ mrg_status build_plan(mrg_batch b)
             if (seg < chunk) seg = chunk;
             R.seg = seg;
             R.segs = (R.n + seg - 1) / seg;
+            // streams that fit one segment are packed, about a segment per item
+            R.spi = R.segs == 1 ? (uint32_t)std::min<uint64_t>(seg / R.n, 1u << 20) : 1;
+            if (!R.spi) R.spi = 1;
             if (R.segs > 1 && (R.flags & mrg::kReqWriteBack)) {
                 R.scratch0 = b->scratch_slots;
                 b->cb_stream0.push_back(R.stream0);
@@ -172,6 +175,7 @@ mrg_status build_plan(mrg_batch b)
         } else {
             R.seg = 0;
             R.segs = 1;
+            R.spi = 1;
         }
         in.push_back(R);
         b->req_of.push_back((uint32_t)i);

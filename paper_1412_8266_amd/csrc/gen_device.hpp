@@ -20,15 +20,27 @@ __device__ __forceinline__ uint32_t exp_digit(uint64_t e0, uint64_t e1, uint64_t
     return (uint32_t)(word >> (4 * (w & 15))) & 15u;
 }
 
+// One past the highest window holding a nonzero digit (0 for e = 0).
+__device__ __forceinline__ int top_window(uint64_t e0, uint64_t e1, uint64_t e2)
+{
+    if (e2) return 32 + (67 - __clzll((long long)e2)) / 4;
+    if (e1) return 16 + (67 - __clzll((long long)e1)) / 4;
+    if (e0) return (67 - __clzll((long long)e0)) / 4;
+    return 0;
+}
+
 // st <- A^e st with the tables read from global memory (L2-resident), over
 // windows [w_lo, w_hi).  Windows whose digit is zero in every lane are
-// skipped; when e is the same in every lane the table reads are uniform.
+// skipped, and the loop ends after the wave's highest nonzero digit; when e
+// is the same in every lane the table reads are uniform.
 __device__ __forceinline__ void jump_global(const uint32_t *__restrict__ table, uint64_t e0,
                                             uint64_t e1, uint64_t e2, int w_lo, int w_hi,
                                             uint32_t *st)
 {
+    const int top = top_window(e0, e1, e2);
 #pragma unroll 1
     for (int w = w_lo; w < w_hi; ++w) {
+        if (!__any(w < top)) break;
         const uint32_t d = exp_digit(e0, e1, e2, w);
         if (!__any(d != 0u)) continue;
         if (d == 0u) continue;  // this lane's identity (exec-masked)
@@ -210,12 +222,18 @@ __device__ __forceinline__ void rows_fill(G &g, unsigned char *lds, int lane, ui
                 if (rowa[j]) *(uint4 *)(rowp[j] + off) = v;
             }
         } else {
-            // element stores: lane e covers (row e / TV, col e % TV)
-            for (int e = lane; e < 64 * TV; e += 64) {
-                const int r = e / TV, col = e % TV;
-                if ((uint64_t)r < nrows)
-                    copy_elem<ES>(out0 + (uint64_t)r * row_stride + off + (uint64_t)col * ES,
-                                  lds + r * RS + col * ES);
+            // unaligned rows: dword copies, 64 * 4 / TB rows per instruction,
+            // each row's TB bytes still one contiguous run
+            constexpr int DPR = TB / 4, RPD = 64 / DPR;
+            const int rsub = lane / DPR;
+            unsigned char *p = out0 + off + (lane % DPR) * 4 + (uint64_t)rsub * row_stride;
+            const unsigned char *sp = lds + rsub * RS + (lane % DPR) * 4;
+            const uint64_t step = (uint64_t)RPD * row_stride;
+#pragma unroll 1
+            for (int r = rsub; r < 64; r += RPD) {
+                if ((uint64_t)r < nrows) *(uint32_t *)p = *(const uint32_t *)sp;
+                p += step;
+                sp += RPD * RS;
             }
         }
         __syncthreads();
@@ -237,33 +255,69 @@ __device__ __forceinline__ void rows_fill(G &g, unsigned char *lds, int lane, ui
 }
 
 // ---------------------------------------------------------------------------
-// wave_fill: values [v0, v1) of one stream whose state at v0 is w (the same
-// in every lane), written at srow + v * ES.  The range is cut into chunks of
-// 64*L values; lane l generates the L consecutive values [l*L, l*L + L) of
-// each chunk starting from A^(l*L) applied to the chunk's first state (m: the
-// lane's 18-word matrix pair), and the next chunk starts where lane 63 ended
-// (sequence splitting, sec. 2.3).  Every LDS flush writes 64 pieces of 128
-// bytes that tile contiguous memory.  If v1 - v0 is a whole number of chunks,
-// w receives the state at v1 and the function returns true; otherwise w is
-// left as the last chunk's first state and it returns false.  `lds` holds
-// 64 * 144 bytes.
+// wave_fill: values [v0, v1) of 64/GL streams at once, GL lanes per stream
+// (lane l serves stream l / GL as its member g = l % GL).  Stream t of the
+// wave is written at srow + t * row_stride + v * ES; only streams t < nsv
+// are written.  Each lane's w holds its stream's state at v0 (the same in
+// the GL lanes of a stream) and receives the state at v1.
+//
+// With GL = 64 the values up to the first 128-byte line boundary (the head,
+// fewer than 128 / ES) come first: lane i < head writes value v0 + i from
+// A^i applied to the state (head_tab: the lane's A^lane), and the state moves
+// to lane `head`'s.  With GL < 64 every row must start on a line boundary.
+// The rest is cut into chunks of GL*L values; member g generates the L
+// consecutive values [g*L, g*L + L) of each chunk starting from A^(g*L)
+// applied to the chunk's first state (m: the lane's 18-word matrix pair), and
+// the next chunk starts where member GL-1 ended (sequence splitting, sec.
+// 2.3).  Every LDS flush of a whole chunk writes 64 aligned 128-byte lines;
+// a final partial chunk is written with dword stores and the state is moved
+// over it with the windowed tables (only if want_end).  `lds` holds 64 * 144
+// bytes.  READ_ALL: read all eight LDS pieces of a flush before the first
+// store (else each piece goes straight to memory).
 // ---------------------------------------------------------------------------
-template <int DT, int L, class G, bool READ_ALL = true>
-__device__ __forceinline__ bool wave_fill(uint32_t *w, const uint32_t *m, unsigned char *lds,
-                                          int lane, unsigned char *srow, uint64_t v0, uint64_t v1,
-                                          bool vec_ok)
+template <int DT, int L, class G, bool READ_ALL = true, int GL = 64>
+__device__ __forceinline__ void wave_fill(uint32_t *w, const uint32_t *m, unsigned char *lds,
+                                          int lane, unsigned char *srow, uint64_t row_stride,
+                                          int nsv, uint64_t v0, uint64_t v1,
+                                          const uint32_t *__restrict__ table,
+                                          const uint32_t *__restrict__ head_tab, bool want_end)
 {
     constexpr int ES = Elem<DT>::size;
     constexpr int TV = 128 / ES;   // values per 128-byte piece
     constexpr int NH = L / TV;     // pieces per lane per chunk
     constexpr int RS = 128 + 16;   // LDS row pitch (bytes)
+    constexpr int SPW = 64 / GL;   // streams per wave
+    constexpr int JPS = GL / 8;    // flush instructions per stream
     static_assert(NH >= 1 && L % TV == 0, "chunk must be whole pieces");
-    const uint64_t chunk_vals = (uint64_t)64 * L;
+    static_assert(GL == 64 || GL == 32 || GL == 16, "16, 32 or 64 lanes per stream");
+    const uint64_t chunk_vals = (uint64_t)GL * L;
     unsigned char *my_lds = lds + lane * RS;
     const int prow = lane >> 3;        // flush: 8 lanes per 128-byte piece
     const int pcol = (lane & 7) * 16;  //        8 pieces per instruction
-    bool whole = true;
+    const int last = (lane / GL) * GL + GL - 1;  // the member that ends a chunk
 
+    if constexpr (GL == 64) {
+        const uint32_t mis = (uint32_t)((uintptr_t)(srow + v0 * ES) & 127u);
+        if (mis && v0 < v1) {
+            const uint64_t hv = (128 - mis) / ES < v1 - v0 ? (128 - mis) / ES : v1 - v0;
+            uint32_t hm[18];
+#pragma unroll
+            for (int i = 0; i < 18; ++i) hm[i] = head_tab[lane * 18 + i];
+            uint32_t st[6] = {w[0], w[1], w[2], w[3], w[4], w[5]};
+            matvec3<C1>(hm, st[0], st[1], st[2]);
+            matvec3<C2>(hm + 9, st[3], st[4], st[5]);
+            if ((uint64_t)lane < hv) {
+                G g;
+                g.load(st);
+                put1<DT>(srow + (v0 + lane) * ES, g);
+            }
+#pragma unroll
+            for (int k = 0; k < 6; ++k) w[k] = __shfl(st[k], (int)hv);
+            v0 += hv;
+        }
+    }
+
+    bool whole = true;
     for (uint64_t c0 = v0; c0 < v1; c0 += chunk_vals) {
         uint32_t st[6] = {w[0], w[1], w[2], w[3], w[4], w[5]};
         matvec3<C1>(m, st[0], st[1], st[2]);
@@ -275,7 +329,8 @@ __device__ __forceinline__ bool wave_fill(uint32_t *w, const uint32_t *m, unsign
 #pragma unroll
             for (int q = 0; q < 8; ++q) *(uint4 *)(my_lds + q * 16) = gen16<DT>(g);
             __syncthreads();
-            if (full && vec_ok) {
+            if (full) {
+                // piece row prow + 8j: stream j / JPS, member prow + 8 (j % JPS)
                 if constexpr (READ_ALL) {
                     uint4 v[8];
 #pragma unroll
@@ -283,36 +338,57 @@ __device__ __forceinline__ bool wave_fill(uint32_t *w, const uint32_t *m, unsign
                         v[j] = *(const uint4 *)(lds + (prow + 8 * j) * RS + pcol);
 #pragma unroll
                     for (int j = 0; j < 8; ++j) {
-                        const uint64_t pos = c0 + (uint64_t)(prow + 8 * j) * L + h * TV;
-                        *(uint4 *)(srow + pos * ES + pcol) = v[j];
+                        const int t = j / JPS;
+                        if (SPW > 1 && t >= nsv) continue;
+                        const uint64_t pos = c0 + (uint64_t)(prow + 8 * (j % JPS)) * L + h * TV;
+                        *(uint4 *)(srow + t * row_stride + pos * ES + pcol) = v[j];
                     }
                 } else {
 #pragma unroll
                     for (int j = 0; j < 8; ++j) {
+                        const int t = j / JPS;
+                        if (SPW > 1 && t >= nsv) continue;
                         const uint4 v = *(const uint4 *)(lds + (prow + 8 * j) * RS + pcol);
-                        const uint64_t pos = c0 + (uint64_t)(prow + 8 * j) * L + h * TV;
-                        *(uint4 *)(srow + pos * ES + pcol) = v;
+                        const uint64_t pos = c0 + (uint64_t)(prow + 8 * (j % JPS)) * L + h * TV;
+                        *(uint4 *)(srow + t * row_stride + pos * ES + pcol) = v;
                     }
                 }
             } else {
-                for (int e = lane; e < 64 * TV; e += 64) {
-                    const int r = e / TV, i = e % TV;
-                    const uint64_t pos = c0 + (uint64_t)r * L + h * TV + i;
-                    if (pos < v1) copy_elem<ES>(srow + pos * ES, lds + r * RS + i * ES);
+                // the last, partial chunk: dword copies, two pieces per
+                // instruction (lanes 0-31 row 2q, lanes 32-63 row 2q+1), only
+                // bytes below (v1 - c0) * ES.  Rows 8u .. 8u+7 belong to one
+                // stream (t) and members g0 .. g0+7.
+                const int half = lane >> 5;
+                const uint64_t lim = (v1 - c0) * ES;
+                const uint64_t lane_off = (uint64_t)half * L * ES + (uint64_t)h * 128 + (lane & 31) * 4;
+                unsigned char *base = srow + c0 * ES + lane_off;
+                const unsigned char *src = lds + half * RS + (lane & 31) * 4;
+#pragma unroll 1
+                for (int u = 0; u < 8; ++u) {
+                    const int t = (8 * u) / GL, g0 = (8 * u) % GL;
+                    if (SPW > 1 && t >= nsv) break;
+                    unsigned char *p = base + t * row_stride + (uint64_t)g0 * L * ES;
+                    const unsigned char *sp = src + 8 * u * RS;
+                    const uint64_t o0 = (uint64_t)g0 * L * ES + lane_off;
+#pragma unroll
+                    for (int j = 0; j < 4; ++j)
+                        if (o0 + (uint64_t)(2 * j) * L * ES < lim)
+                            *(uint32_t *)(p + 2 * j * L * ES) = *(const uint32_t *)(sp + 2 * j * RS);
                 }
             }
             __syncthreads();
         }
-        if (full) {  // lane 63 ends at the next chunk's first state
+        if (full) {  // member GL-1 ends at the next chunk's first state
             uint32_t e[6];
             g.store(e);
 #pragma unroll
-            for (int k = 0; k < 6; ++k) w[k] = __shfl(e[k], 63);
+            for (int k = 0; k < 6; ++k) w[k] = __shfl(e[k], last);
         } else {
             whole = false;
         }
     }
-    return whole;
+    // w is the last chunk's first state: move it over the partial chunk
+    if (!whole && want_end) jump_global(table, (v1 - v0) % chunk_vals, 0, 0, 0, 16, w);
 }
 
 }  // namespace mrg

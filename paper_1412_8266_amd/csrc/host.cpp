@@ -123,15 +123,15 @@ const std::vector<uint32_t> &host_tables()
 // ---- per-device context ----------------------------------------------------
 struct DevCtx {
     uint32_t *d_table = nullptr;     // windowed jump tables
-    uint32_t *d_lane_tab = nullptr;  // [3][64][18]: A^(l*L) for L in kLaneSegs
+    uint32_t *d_lane_tab = nullptr;  // [kNumLaneSegs][64][18]: A^(l*L) for L in kLaneSegs
     int cus = 256;                   // compute units of the device
 };
 
 // A^(l*L) for l in [0, 64) and each lane-segment length L, both components.
 std::vector<uint32_t> build_lane_tables()
 {
-    std::vector<uint32_t> t(3 * 64 * 18);
-    for (int k = 0; k < 3; ++k) {
+    std::vector<uint32_t> t(mrg::kNumLaneSegs * 64 * 18);
+    for (int k = 0; k < mrg::kNumLaneSegs; ++k) {
         const uint64_t L = (uint64_t)mrg::kLaneSegs[k];
         for (int l = 0; l < 64; ++l) {
             const uint64_t e[3] = {L * (uint64_t)l, 0, 0};
@@ -465,17 +465,30 @@ mrg_status mrg_fill(mrg_streamset ss, uint64_t first, uint64_t count, uint64_t n
         if (coop) {
             DevCtx *ctx;
             if ((st = device_ctx(ss->device, &ctx))) return st;
-            // 256 bytes per lane per chunk for long streams, 128 otherwise
-            const int L = (int)(128 / es) * (n_per_stream >= 2 * min_chunk ? 2 : 1);
-            const int k = L == 16 ? 0 : (L == 32 ? 1 : 2);
+            // GL lanes per stream, 64/GL streams per wave; each lane takes
+            // 2*64/GL pieces of 128 bytes per chunk when the stream fills such
+            // a chunk, else half as many (a chunk is then 64 x 128 bytes)
+            // several streams per wave only when every row starts on a
+            // 128-byte line (one stream per wave realigns its rows itself)
+            const bool rows_aligned = (uintptr_t)d_out % 128 == 0 && (n_per_stream * es) % 128 == 0;
+            const int GL = rows_aligned ? tune.coop_lanes : 64;
+            const uint64_t tv = 128 / es;
+            const uint64_t nh_min = 64 / GL, nh_max = 2 * nh_min;
+            const uint64_t nh = n_per_stream >= (uint64_t)GL * nh_max * tv ? nh_max : nh_min;
+            const int L = (int)(nh * tv);
+            int k = 0;
+            while (k < mrg::kNumLaneSegs - 1 && mrg::kLaneSegs[k] != L) ++k;
             fl.kernel = 1;
             fl.L = L;
+            fl.lanes = GL;
             fl.lane_tab = ctx->d_lane_tab + k * 64 * 18;
+            fl.head_tab = ctx->d_lane_tab + mrg::kHeadTable * 64 * 18;
             fl.table = ctx->d_table;
-            // resident workgroups stride over the streams, or one per stream
+            // resident workgroups stride over the stream groups, or one per group
+            const uint64_t groups = (count + (64 / GL) - 1) / (64 / GL);
             const uint64_t cap = tune.coop_wgs_per_cu ? (uint64_t)ctx->cus * tune.coop_wgs_per_cu
                                                       : ((uint64_t)1 << 31) - 1;
-            fl.grid = (unsigned)(count < cap ? count : cap);
+            fl.grid = (unsigned)(groups < cap ? groups : cap);
         }
     }
     hipError_t e = mrg::launch_fill(ss->d_planes, ss->n, first, count, n_per_stream, (int)dtype,
@@ -538,6 +551,10 @@ mrg_status mrg_config_set(const char *key, int64_t value)
     } else if (!std::strcmp(key, "coop_wgs_per_cu")) {
         if (value < 0 || value > 1024) return set_error(MRG_EINVAL, "coop_wgs_per_cu must be in [0, 1024]");
         g_tune.coop_wgs_per_cu = (int)value;
+    } else if (!std::strcmp(key, "coop_lanes")) {
+        if (value != 64 && value != 32 && value != 16)
+            return set_error(MRG_EINVAL, "coop_lanes must be 64, 32 or 16");
+        g_tune.coop_lanes = (int)value;
     } else if (!std::strcmp(key, "strategy")) {
         if (value < 0 || value > 2) return set_error(MRG_EINVAL, "strategy must be 0, 1 or 2");
         g_tune.strategy = (int)value;
@@ -558,6 +575,7 @@ mrg_status mrg_config_get(const char *key, int64_t *value)
     else if (!std::strcmp(key, "tile_bytes")) *value = g_tune.tile_bytes;
     else if (!std::strcmp(key, "strategy")) *value = g_tune.strategy;
     else if (!std::strcmp(key, "coop_wgs_per_cu")) *value = g_tune.coop_wgs_per_cu;
+    else if (!std::strcmp(key, "coop_lanes")) *value = g_tune.coop_lanes;
     else return set_error(MRG_EINVAL, "unknown key '%s'", key);
     return MRG_OK;
 }

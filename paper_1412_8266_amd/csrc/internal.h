@@ -23,7 +23,7 @@ mrg_status hip_error(hipError_t e, const char *what);
 // Device-resident tables of one device (created on first use).
 struct DeviceTables {
     const uint32_t *table = nullptr;     // windowed jump tables, kTableWords words
-    const uint32_t *lane_tab = nullptr;  // [3][64][18]
+    const uint32_t *lane_tab = nullptr;  // [kNumLaneSegs][64][18]
     int cus = 256;
 };
 mrg_status device_tables(int dev, DeviceTables *out);

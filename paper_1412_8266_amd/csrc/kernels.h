@@ -29,17 +29,24 @@ struct FillTuning {
     int engine = 1;
     int tile_bytes = 256;
     int strategy = 0;
-    int coop_wgs_per_cu = 0;  // wave per stream: 0 = one workgroup per stream
+    int coop_wgs_per_cu = 0;  // wave per stream: 0 = one workgroup per stream group
+    int coop_lanes = 16;      // wave per stream: lanes per stream (64, 32 or 16)
 };
 
-// Lane-segment lengths of the wave-per-stream fill and their tables.
-constexpr int kLaneSegs[3] = {16, 32, 64};
+// Lane-segment lengths L of the wave-per-stream fill; table k holds A^(l*L)
+// for l < 64, L = kLaneSegs[k].  The last one (L = 1) serves the values
+// before a row's first 128-byte line boundary.
+constexpr int kNumLaneSegs = 6;
+constexpr int kLaneSegs[kNumLaneSegs] = {16, 32, 64, 128, 256, 1};
+constexpr int kHeadTable = 5;
 
 // How one stream-major fill is launched (chosen on the host).
 struct FillLaunch {
     int kernel = 0;                     // 0 lane per stream, 1 wave per stream
     int L = 0;                          // values per lane per chunk (wave per stream)
-    const uint32_t *lane_tab = nullptr; // [64][18]: A^(l*L), component 1 then 2
+    int lanes = 64;                     // lanes per stream (wave per stream)
+    const uint32_t *lane_tab = nullptr; // [64][18]: A^(l*L), component 1 then 2 (lane l % lanes)
+    const uint32_t *head_tab = nullptr; // [64][18]: A^l (values before the first line boundary)
     const uint32_t *table = nullptr;    // windowed jump tables (end state of a partial chunk)
     unsigned grid = 0;                  // workgroups (wave per stream)
 };

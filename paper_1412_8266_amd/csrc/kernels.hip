@@ -160,32 +160,34 @@ fill_il_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t fi
 }
 
 // Wave-per-stream stream-major fill: workgroups (one wave each) stride over
-// the streams; each stream is written by wave_fill, so that every flush tiles
-// contiguous memory and the streams in flight stay adjacent.  The end state
-// is lane 63's after the last whole chunk, advanced by the windowed tables
-// over a final partial chunk.
-template <int DT, int L, class G>
+// groups of 64/GL streams, GL lanes per stream; each group is written by
+// wave_fill, so that every flush writes whole 128-byte lines and the streams
+// in flight stay adjacent.  Lanes of a group past the last stream run on a
+// dummy state and write nothing.
+template <int DT, int L, int GL, class G>
 __global__ void __launch_bounds__(64)
 fill_coop_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t first,
-                 uint64_t count, uint64_t n, unsigned char *__restrict__ out, int vec_ok,
-                 const uint32_t *__restrict__ lane_tab, const uint32_t *__restrict__ table)
+                 uint64_t count, uint64_t n, unsigned char *__restrict__ out,
+                 const uint32_t *__restrict__ lane_tab, const uint32_t *__restrict__ head_tab,
+                 const uint32_t *__restrict__ table)
 {
     constexpr int ES = Elem<DT>::size;
+    constexpr int SPW = 64 / GL;
     __shared__ __attribute__((aligned(16))) unsigned char lds[64 * 144];
     const int lane = threadIdx.x;
+    const int t = lane / GL;  // this lane's stream within the group
     uint32_t m[18];
 #pragma unroll
-    for (int i = 0; i < 18; ++i) m[i] = lane_tab[lane * 18 + i];
-    const uint64_t chunk_vals = (uint64_t)64 * L;
-    const uint64_t rem = n % chunk_vals;
+    for (int i = 0; i < 18; ++i) m[i] = lane_tab[(lane % GL) * 18 + i];
 
-    for (uint64_t s = blockIdx.x; s < count; s += gridDim.x) {
-        const uint64_t idx = first + s;
-        uint32_t w[6];
-        load_state(planes, plane_stride, idx, w);
-        if (!wave_fill<DT, L, G>(w, m, lds, lane, out + s * n * ES, 0, n, vec_ok != 0))
-            jump_global(table, rem, 0, 0, 0, 16, w);
-        if (lane == 0) store_state(planes, plane_stride, idx, w);
+    for (uint64_t s0 = (uint64_t)blockIdx.x * SPW; s0 < count; s0 += (uint64_t)gridDim.x * SPW) {
+        const int nsv = count - s0 < (uint64_t)SPW ? (int)(count - s0) : SPW;
+        const uint64_t idx = first + s0 + t;
+        uint32_t w[6] = {1u, 1u, 1u, 1u, 1u, 1u};
+        if (t < nsv) load_state(planes, plane_stride, idx, w);
+        wave_fill<DT, L, G, true, GL>(w, m, lds, lane, out + s0 * n * ES, n * ES, nsv, 0, n, table,
+                                      head_tab, true);
+        if (lane % GL == 0 && t < nsv) store_state(planes, plane_stride, idx, w);
     }
 }
 
@@ -238,18 +240,21 @@ static hipError_t launch_fill_g(uint32_t *planes, uint64_t plane_stride, uint64_
         hipLaunchKernelGGL((fill_il_kernel<DT, G>), dim3(grid_of(count, 256)), dim3(256), 0, st,
                            planes, plane_stride, first, count, n, o);
     } else if (fl.kernel == 1) {
+        constexpr int TV = 128 / Elem<DT>::size;  // values per 128-byte piece
         const dim3 grid(fl.grid), block(64);
-        if (fl.L == 64 && DT != 2)
-            hipLaunchKernelGGL((fill_coop_kernel<DT, 64, G>), grid, block, 0, st, planes,
-                               plane_stride, first, count, n, o, vec_ok, fl.lane_tab, fl.table);
-        else if (fl.L == 32)
-            hipLaunchKernelGGL((fill_coop_kernel<DT, 32, G>), grid, block, 0, st, planes,
-                               plane_stride, first, count, n, o, vec_ok, fl.lane_tab, fl.table);
-        else if (fl.L == 16 && DT == 2)
-            hipLaunchKernelGGL((fill_coop_kernel<2, 16, G>), grid, block, 0, st, planes,
-                               plane_stride, first, count, n, o, vec_ok, fl.lane_tab, fl.table);
-        else
-            return hipErrorInvalidValue;
+        const int nh = fl.L / TV;
+#define MRG_COOP(GL, NH)                                                                        \
+    hipLaunchKernelGGL((fill_coop_kernel<DT, (NH) * TV, GL, G>), grid, block, 0, st, planes,     \
+                       plane_stride, first, count, n, o, fl.lane_tab, fl.head_tab, fl.table)
+        if (fl.L % TV) return hipErrorInvalidValue;
+        else if (fl.lanes == 64 && nh == 1) MRG_COOP(64, 1);
+        else if (fl.lanes == 64 && nh == 2) MRG_COOP(64, 2);
+        else if (fl.lanes == 32 && nh == 2) MRG_COOP(32, 2);
+        else if (fl.lanes == 32 && nh == 4) MRG_COOP(32, 4);
+        else if (fl.lanes == 16 && nh == 4) MRG_COOP(16, 4);
+        else if (fl.lanes == 16 && nh == 8) MRG_COOP(16, 8);
+        else return hipErrorInvalidValue;
+#undef MRG_COOP
     } else if (tile_bytes >= 256) {
         hipLaunchKernelGGL((fill_sm_kernel<DT, 256, G>), dim3(grid_of(count, 64)), dim3(64), 0, st,
                            planes, plane_stride, first, count, n, o, vec_ok);

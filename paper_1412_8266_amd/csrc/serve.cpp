@@ -156,9 +156,11 @@ mrg::BatchReq to_batch_req(mrg_server s, const Req &r)
         uint64_t seg = (256 * 1024) / es / chunk * chunk;
         R.seg = seg;
         R.segs = (r.n + seg - 1) / seg;
+        R.spi = R.segs == 1 ? (uint32_t)std::max<uint64_t>(1, seg / r.n) : 1;
     } else {
         R.seg = 0;
         R.segs = 1;
+        R.spi = 1;
     }
     return R;
 }

@@ -18,8 +18,10 @@ pytestmark = pytest.mark.gpu
 
 # (engine, stream-major strategy): integer / binary64 arithmetic, lane per
 # stream / wave per stream
-CONFIGS = [(0, 1), (1, 1), (0, 2), (1, 2)]
-CONFIG_IDS = ["int-lane", "f64-lane", "int-wave", "f64-wave"]
+# (engine, strategy, lanes per stream of the wave-per-stream fill)
+CONFIGS = [(0, 1, 64), (1, 1, 64), (0, 2, 64), (1, 2, 64), (1, 2, 32), (0, 2, 16), (1, 2, 16)]
+CONFIG_IDS = ["int-lane", "f64-lane", "int-wave", "f64-wave", "f64-wave32", "int-wave16",
+              "f64-wave16"]
 
 
 def say(*a):
@@ -37,12 +39,13 @@ def mg():
 
 @pytest.fixture(params=CONFIGS, ids=CONFIG_IDS)
 def engine(request, mg):
-    old = (mg.mrg_config_get("engine"), mg.mrg_config_get("strategy"))
-    mg.mrg_config_set("engine", request.param[0])
-    mg.mrg_config_set("strategy", request.param[1])
+    keys = ("engine", "strategy", "coop_lanes")
+    old = [mg.mrg_config_get(k) for k in keys]
+    for k, v in zip(keys, request.param):
+        mg.mrg_config_set(k, v)
     yield request.param
-    mg.mrg_config_set("engine", old[0])
-    mg.mrg_config_set("strategy", old[1])
+    for k, v in zip(keys, old):
+        mg.mrg_config_set(k, v)
 
 
 def host(t):
