@@ -361,7 +361,7 @@ mrg_status mrg_state_check(const uint32_t state6[6]);
  *   "coop_wgs_per_cu" wave-per-stream fill: one-wave workgroups per compute
  *                unit, each looping over stream groups (0 = one workgroup
  *                per group, the default), 0 .. 1024;
- *   "coop_lanes" wave-per-stream fill: lanes per stream, 64, 32 or 16
+ *   "coop_lanes" wave-per-stream fill: lanes per stream, 64, 32, 16 or 8
  *                (default 16: 64/coop_lanes streams share a wave; used when
  *                every row starts on a 128-byte boundary, else 64).
  * Unknown keys or values: MRG_EINVAL.  Takes effect for later launches. */

@@ -289,7 +289,7 @@ __device__ __forceinline__ void wave_fill(uint32_t *w, const uint32_t *m, unsign
     constexpr int SPW = 64 / GL;   // streams per wave
     constexpr int JPS = GL / 8;    // flush instructions per stream
     static_assert(NH >= 1 && L % TV == 0, "chunk must be whole pieces");
-    static_assert(GL == 64 || GL == 32 || GL == 16, "16, 32 or 64 lanes per stream");
+    static_assert(GL == 64 || GL == 32 || GL == 16 || GL == 8, "8, 16, 32 or 64 lanes per stream");
     const uint64_t chunk_vals = (uint64_t)GL * L;
     unsigned char *my_lds = lds + lane * RS;
     const int prow = lane >> 3;        // flush: 8 lanes per 128-byte piece
@@ -330,7 +330,10 @@ __device__ __forceinline__ void wave_fill(uint32_t *w, const uint32_t *m, unsign
             for (int q = 0; q < 8; ++q) *(uint4 *)(my_lds + q * 16) = gen16<DT>(g);
             __syncthreads();
             if (full) {
-                // piece row prow + 8j: stream j / JPS, member prow + 8 (j % JPS)
+                // piece row prow + 8j: stream j / JPS, member prow + 8 (j % JPS).
+                // Address = a wave-uniform base (stream row, chunk, piece) plus
+                // a lane offset below 2^32 that is fixed for the whole call.
+                const uint64_t hoff = (c0 + (uint64_t)h * TV) * ES;
                 if constexpr (READ_ALL) {
                     uint4 v[8];
 #pragma unroll
@@ -340,8 +343,8 @@ __device__ __forceinline__ void wave_fill(uint32_t *w, const uint32_t *m, unsign
                     for (int j = 0; j < 8; ++j) {
                         const int t = j / JPS;
                         if (SPW > 1 && t >= nsv) continue;
-                        const uint64_t pos = c0 + (uint64_t)(prow + 8 * (j % JPS)) * L + h * TV;
-                        *(uint4 *)(srow + t * row_stride + pos * ES + pcol) = v[j];
+                        const uint32_t loff = (uint32_t)((prow + 8 * (j % JPS)) * L * ES + pcol);
+                        *(uint4 *)(srow + t * row_stride + hoff + loff) = v[j];
                     }
                 } else {
 #pragma unroll
@@ -349,8 +352,8 @@ __device__ __forceinline__ void wave_fill(uint32_t *w, const uint32_t *m, unsign
                         const int t = j / JPS;
                         if (SPW > 1 && t >= nsv) continue;
                         const uint4 v = *(const uint4 *)(lds + (prow + 8 * j) * RS + pcol);
-                        const uint64_t pos = c0 + (uint64_t)(prow + 8 * (j % JPS)) * L + h * TV;
-                        *(uint4 *)(srow + t * row_stride + pos * ES + pcol) = v;
+                        const uint32_t loff = (uint32_t)((prow + 8 * (j % JPS)) * L * ES + pcol);
+                        *(uint4 *)(srow + t * row_stride + hoff + loff) = v;
                     }
                 }
             } else {

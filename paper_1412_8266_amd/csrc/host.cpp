@@ -478,6 +478,7 @@ mrg_status mrg_fill(mrg_streamset ss, uint64_t first, uint64_t count, uint64_t n
             const int L = (int)(nh * tv);
             int k = 0;
             while (k < mrg::kNumLaneSegs - 1 && mrg::kLaneSegs[k] != L) ++k;
+            if (mrg::kLaneSegs[k] != L) return set_error(MRG_EINVAL, "no lane table for L = %d", L);
             fl.kernel = 1;
             fl.L = L;
             fl.lanes = GL;
@@ -552,8 +553,8 @@ mrg_status mrg_config_set(const char *key, int64_t value)
         if (value < 0 || value > 1024) return set_error(MRG_EINVAL, "coop_wgs_per_cu must be in [0, 1024]");
         g_tune.coop_wgs_per_cu = (int)value;
     } else if (!std::strcmp(key, "coop_lanes")) {
-        if (value != 64 && value != 32 && value != 16)
-            return set_error(MRG_EINVAL, "coop_lanes must be 64, 32 or 16");
+        if (value != 64 && value != 32 && value != 16 && value != 8)
+            return set_error(MRG_EINVAL, "coop_lanes must be 64, 32, 16 or 8");
         g_tune.coop_lanes = (int)value;
     } else if (!std::strcmp(key, "strategy")) {
         if (value < 0 || value > 2) return set_error(MRG_EINVAL, "strategy must be 0, 1 or 2");

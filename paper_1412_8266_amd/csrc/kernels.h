@@ -30,14 +30,14 @@ struct FillTuning {
     int tile_bytes = 256;
     int strategy = 0;
     int coop_wgs_per_cu = 0;  // wave per stream: 0 = one workgroup per stream group
-    int coop_lanes = 16;      // wave per stream: lanes per stream (64, 32 or 16)
+    int coop_lanes = 16;      // wave per stream: lanes per stream (64, 32, 16 or 8)
 };
 
 // Lane-segment lengths L of the wave-per-stream fill; table k holds A^(l*L)
 // for l < 64, L = kLaneSegs[k].  The last one (L = 1) serves the values
 // before a row's first 128-byte line boundary.
-constexpr int kNumLaneSegs = 6;
-constexpr int kLaneSegs[kNumLaneSegs] = {16, 32, 64, 128, 256, 1};
+constexpr int kNumLaneSegs = 7;
+constexpr int kLaneSegs[kNumLaneSegs] = {16, 32, 64, 128, 256, 1, 512};
 constexpr int kHeadTable = 5;
 
 // How one stream-major fill is launched (chosen on the host).

@@ -253,6 +253,8 @@ static hipError_t launch_fill_g(uint32_t *planes, uint64_t plane_stride, uint64_
         else if (fl.lanes == 32 && nh == 4) MRG_COOP(32, 4);
         else if (fl.lanes == 16 && nh == 4) MRG_COOP(16, 4);
         else if (fl.lanes == 16 && nh == 8) MRG_COOP(16, 8);
+        else if (fl.lanes == 8 && nh == 8) MRG_COOP(8, 8);
+        else if (fl.lanes == 8 && nh == 16) MRG_COOP(8, 16);
         else return hipErrorInvalidValue;
 #undef MRG_COOP
     } else if (tile_bytes >= 256) {

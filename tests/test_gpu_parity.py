@@ -19,9 +19,10 @@ pytestmark = pytest.mark.gpu
 # (engine, stream-major strategy): integer / binary64 arithmetic, lane per
 # stream / wave per stream
 # (engine, strategy, lanes per stream of the wave-per-stream fill)
-CONFIGS = [(0, 1, 64), (1, 1, 64), (0, 2, 64), (1, 2, 64), (1, 2, 32), (0, 2, 16), (1, 2, 16)]
+CONFIGS = [(0, 1, 64), (1, 1, 64), (0, 2, 64), (1, 2, 64), (1, 2, 32), (0, 2, 16), (1, 2, 16),
+           (1, 2, 8)]
 CONFIG_IDS = ["int-lane", "f64-lane", "int-wave", "f64-wave", "f64-wave32", "int-wave16",
-              "f64-wave16"]
+              "f64-wave16", "f64-wave8"]
 
 
 def say(*a):
@@ -101,13 +102,27 @@ def test_unaligned_row_and_pointer(mg, engine):
     import torch
     base = oracle.seed_from_master(7)
     say("unaligned", engine)
-    for n, off in [(37, 1), (40, 1), (64, 3), (2050, 1), (4096, 2)]:
+    for n, off in [(37, 1), (40, 1), (64, 3), (2050, 1), (4096, 2), (4097, 7), (9000, 5),
+                   (8192, 31)]:
         ss = mg.StreamSet(70, seed=[int(x) for x in base])
-        buf = torch.zeros(70 * n + 8, dtype=torch.uint32, device="cuda")
+        buf = torch.zeros(70 * n + 40, dtype=torch.uint32, device="cuda")
         ss.fill_ptr(n, mg.U32, mg.STREAM_MAJOR, buf.data_ptr() + 4 * off)
-        got = host(buf)[off:off + 70 * n].reshape(70, n)
+        h = host(buf)
+        got = h[off:off + 70 * n].reshape(70, n)
         want, _ = oracle_fill(base, 0, 70, n, oracle.U32)
-        assert np.array_equal(got, want)
+        assert np.array_equal(got, want), (n, off)
+        # nothing written outside the rows
+        assert not h[:off].any() and not h[off + 70 * n:].any(), (n, off)
+        ss.close()
+    for n, off in [(1000, 1), (2049, 3), (5000, 5)]:  # f64 rows off the 128-byte lines
+        ss = mg.StreamSet(33, seed=[int(x) for x in base])
+        buf = torch.zeros(33 * n + 24, dtype=torch.float64, device="cuda")
+        ss.fill_ptr(n, mg.F64, mg.STREAM_MAJOR, buf.data_ptr() + 8 * off)
+        h = host(buf)
+        want, _ = oracle_fill(base, 0, 33, n, oracle.F64)
+        assert np.array_equal(h[off:off + 33 * n].reshape(33, n).view(np.uint64),
+                              want.view(np.uint64)), (n, off)
+        assert not h[:off].any() and not h[off + 33 * n:].any(), (n, off)
         ss.close()
 
 
