@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched request mix")
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
+    ap.add_argument("--serve-speeds", type=float, nargs="*", default=[1.1, 1.2],
+                    help="arrival-rate multiples replayed for 4 s each")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the replayed arrival trace (the full trace is 60 s)")
     ap.add_argument("--quick", action="store_true", help="headline only (for profiling)")
@@ -162,7 +164,7 @@ def batched(mg, wl, torch, stream, reps):
     return out
 
 
-def serving(mg, wl, seconds):
+def serving(mg, wl, seconds, speed=1.0):
     """Continuous batching under Poisson arrivals: 20,000 requests/s from
     50,000 clients, request sizes drawn as in the batched mix, a 64 GiB
     output arena as the admission cap, outputs freed on completion.  The
@@ -170,13 +172,13 @@ def serving(mg, wl, seconds):
     latency of a request runs from its submission to its completion event."""
     import numpy as np
     arr = wl.c5_arrivals()
-    keep = arr.t < seconds
+    keep = arr.t < seconds * speed  # replayed `speed` times faster
     t, client = arr.t[keep], arr.client[keep]
     k, n, dt = arr.req.n_streams[keep], arr.req.length[keep], arr.req.dtype[keep]
     es = np.where(dt == 2, 8, 4)
     from paper_1412_8266_amd.serve import Server
     srv = Server(wl.C5_CLIENTS, wl.MASTER_SEED, wl.C5_ARENA_BYTES, auto_release=True)
-    wall = srv.run_trace(t, client, k, n, dt)
+    wall = srv.run_trace(t, client, k, n, dt, time_scale=1.0 / speed)
     res = srv.poll()
     st = srv.stats()
     srv.close()
@@ -188,10 +190,11 @@ def serving(mg, wl, seconds):
         return round(float(a[min(len(a) - 1, int(q * len(a)))]), 3) if len(a) else None
 
     return {
-        "trace_seconds": seconds, "rate_per_s": wl.C5_RATE, "clients": wl.C5_CLIENTS,
+        "trace_seconds": seconds, "rate_per_s": wl.C5_RATE * speed, "clients": wl.C5_CLIENTS,
         "arena_GiB": wl.C5_ARENA_BYTES >> 30, "requests": int(keep.sum()),
         "completed": int(len(res)), "ticks": int(st["ticks"]), "wall_s": round(wall, 3),
         "offered_Gsamples_s": round(samples / seconds / 1e9, 2),
+        "kept_up": bool(wall < seconds * 1.05),
         "served_Gsamples_s": round(samples / wall / 1e9, 2),
         "served_GB_s": round(float((k * n * es).sum()) / wall / 1e9, 1),
         "latency_ms": {"p50": pct(lat, 0.50), "p99": pct(lat, 0.99), "max": pct(lat, 1.0)},
@@ -305,6 +308,14 @@ def main():
         msi = sum(per_i) / len(per_i)
         extra["u32_interleaved"] = {"Gsamples_s": round(samples / msi / 1e6, 2),
                                     "ms": round(msi, 4)}
+        # store-only probes over the same 16 GiB: what the stores alone attain
+        probe = {}
+        for name, pat in (("streaming_16B", 0), ("fill_lines", 1)):
+            per_p, _ = timed(lambda: mg.write_probe(out, pat, stream), args.steps, 1, stream)
+            msp = sum(per_p) / len(per_p)
+            probe[name + "_GBs"] = round(out.numel() * 4 / msp / 1e6, 1)
+        probe["fill_over_fill_lines"] = round(achieved / probe["fill_lines_GBs"], 4)
+        extra["store_probe"] = probe
         del outf
         del out
         # FP64 fill: half the streams so the output stays at 16 GiB
@@ -322,6 +333,14 @@ def main():
         ex = torch.from_numpy(wl.c3_exponents(wl.c3_offsets()).view(np.int64)).cuda()
         per_j, _ = timed(lambda: ss3.jump(ex), 10, 1, stream)
         extra["jump_2^16_streams_ms"] = round(sum(per_j) / len(per_j), 4)
+        # the jumped set's fill: 2^16 streams x 1024 uint32 (each call continues)
+        out3 = torch.empty((wl.C3_STREAMS, wl.C3_N), dtype=torch.uint32, device="cuda")
+        per_3, _ = timed(lambda: ss3.fill_ptr(wl.C3_N, mg.U32, mg.STREAM_MAJOR, out3.data_ptr()),
+                         10, 1, stream)
+        ms3 = sum(per_3) / len(per_3)
+        extra["jumped_2^16x1024_fill"] = {"ms": round(ms3, 4),
+                                           "Gsamples_s": round(wl.C3_STREAMS * wl.C3_N / ms3 / 1e6, 2)}
+        del out3
         ss3.close()
     ss.close()
     torch.cuda.synchronize()
@@ -332,6 +351,14 @@ def main():
         print("[bench] serving trace (%g s)" % args.serve_seconds, file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
         extra["serving"] = serving(mg, wl, args.serve_seconds)
+        # the highest arrival rate served without falling behind (short windows)
+        sweep = []
+        for speed in args.serve_speeds:
+            print("[bench] serving at %g x the arrival rate" % speed, file=sys.stderr, flush=True)
+            r = serving(mg, wl, 4.0, speed)
+            sweep.append({k: r[k] for k in ("rate_per_s", "offered_Gsamples_s", "served_Gsamples_s",
+                                             "kept_up", "latency_ms")})
+        extra["serving_rate_sweep"] = sweep
     res["extra"] = extra
 
     if not args.no_cpu and not args.quick:

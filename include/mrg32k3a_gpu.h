@@ -368,6 +368,18 @@ mrg_status mrg_state_check(const uint32_t state6[6]);
 mrg_status mrg_config_set(const char *key, int64_t value);
 mrg_status mrg_config_get(const char *key, int64_t *value);
 
+/* Store-only bandwidth probe (a measurement aid, not part of the method):
+ * writes `bytes` of filler to device memory d_out on `stream` with the store
+ * pattern of the fills but no generation work, so that a fill's write rate can
+ * be compared with what its stores alone attain.
+ *   pattern 0: streaming 16-byte stores (bytes a multiple of 16, d_out
+ *              16-byte aligned);
+ *   pattern 1: the wave-per-stream fill's geometry at 16 lanes per stream and
+ *              1 KiB per lane: four 16 KiB rows per wave, 128-byte lines staged
+ *              in LDS (bytes a multiple of 65536, d_out 128-byte aligned).
+ * Other patterns or sizes: MRG_EINVAL.  Asynchronous. */
+mrg_status mrg_write_probe(void *d_out, uint64_t bytes, int32_t pattern, void *stream);
+
 /* Static text of a status code. */
 const char *mrg_status_string(mrg_status s);
 

@@ -155,8 +155,16 @@ class StreamSet:
 __all__ = [
     "StreamSet", "MRGError", "U32", "F32", "F64", "STREAM_MAJOR", "INTERLEAVED", "M1", "M2",
     "mrg_seed_from_master", "mrg_jump_matrix", "mrg_state_check", "mrg_config_set",
-    "mrg_config_get", "mrg_version", "torch_dtype",
+    "mrg_config_get", "mrg_version", "torch_dtype", "write_probe",
 ]
+
+
+def write_probe(out, pattern: int = 0, stream=None) -> None:
+    """Store-only bandwidth probe over the whole of `out` (a CUDA tensor):
+    pattern 0 streaming 16-byte stores, 1 the wave-per-stream fill's 128-byte
+    line geometry (mrg_write_probe in the C ABI)."""
+    _abi.mrg_write_probe(out.data_ptr(), out.numel() * out.element_size(), pattern,
+                         _stream_handle(stream))
 
 
 # ---------------------------------------------------------------------------

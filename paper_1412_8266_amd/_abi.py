@@ -140,6 +140,7 @@ _SIGS.update({
                              ctypes.POINTER(ctypes.c_double)],
     "mrg_server_client_state": [_P, _U64, _PU32, ctypes.POINTER(_U64)],
     "mrg_server_destroy": [_P],
+    "mrg_write_probe": [_P, _U64, _I32, _P],
 })
 
 for _name, _args in _SIGS.items():
@@ -271,6 +272,10 @@ def mrg_last_error() -> str:
 
 def mrg_version() -> int:
     return int(lib.mrg_version())
+
+
+def mrg_write_probe(d_out: int, nbytes: int, pattern: int, stream: int = 0) -> None:
+    _call("mrg_write_probe", d_out, nbytes, pattern, stream)
 
 
 def make_requests(rows) -> "ctypes.Array":

@@ -597,6 +597,23 @@ const char *mrg_status_string(mrg_status s)
 
 const char *mrg_last_error(void) { return g_last_error.c_str(); }
 
+mrg_status mrg_write_probe(void *d_out, uint64_t bytes, int32_t pattern, void *stream)
+{
+    if (pattern != 0 && pattern != 1) return set_error(MRG_EINVAL, "unknown probe pattern %d", pattern);
+    if (!d_out) return set_error(MRG_EINVAL, "null output");
+    const uint64_t unit = pattern == 0 ? 16 : 65536, align = pattern == 0 ? 16 : 128;
+    if (bytes % unit) return set_error(MRG_EINVAL, "probe size must be a multiple of %llu bytes",
+                                       (unsigned long long)unit);
+    if ((uintptr_t)d_out % align) return set_error(MRG_EINVAL, "probe output must be %llu-byte aligned",
+                                                   (unsigned long long)align);
+    if (!bytes) return MRG_OK;
+    int dev;
+    mrg_status st = current_device(&dev);
+    if (st) return st;
+    hipError_t e = mrg::launch_write_probe(d_out, bytes, pattern, (hipStream_t)stream);
+    return e == hipSuccess ? MRG_OK : hip_error(e, "probe launch");
+}
+
 int32_t mrg_version(void) { return 100; }
 
 }  // extern "C"

@@ -55,4 +55,8 @@ hipError_t launch_fill(uint32_t *planes, uint64_t plane_stride, uint64_t first, 
                        uint64_t n, int dtype, int layout, void *out, int vec_ok,
                        const FillLaunch &fl, const FillTuning &tune, hipStream_t st);
 
+// Store-only bandwidth probes (probe.hip): pattern 0 streaming, 1 the
+// wave-per-stream fill's line geometry.
+hipError_t launch_write_probe(void *out, uint64_t bytes, int pattern, hipStream_t st);
+
 }  // namespace mrg

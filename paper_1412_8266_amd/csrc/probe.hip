@@ -1,0 +1,69 @@
+// Store-only probes: the write bandwidth HBM grants to a store pattern, with
+// no generation work, so that the fill kernels can be compared with what the
+// same stores alone attain.
+//   pattern 0: streaming 16-byte stores, consecutive lanes on consecutive
+//              addresses (each wave instruction covers 1 KiB);
+//   pattern 1: the wave-per-stream fill's geometry at 16 lanes per stream and
+//              256 uint32 per lane (4 rows of 16 KiB per wave): each flush
+//              stages 64 pieces of 128 bytes in LDS and writes them as 16-byte
+//              stores, 8 lines per instruction, lines 1 KiB apart in a row.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "kernels.h"
+
+namespace mrg {
+
+__global__ void __launch_bounds__(256) probe_stream_kernel(uint4 *__restrict__ out, uint64_t n16)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    const uint32_t tag = threadIdx.x * 0x9E3779B9u;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+        out[i] = make_uint4(tag, (uint32_t)i, tag ^ 1u, (uint32_t)(i >> 32));
+}
+
+__global__ void __launch_bounds__(64) probe_pieces_kernel(unsigned char *__restrict__ out,
+                                                          uint64_t groups)
+{
+    constexpr int RS = 144, L_BYTES = 1024, ROW = 16384;
+    __shared__ __attribute__((aligned(16))) unsigned char lds[64 * RS];
+    const int lane = threadIdx.x;
+    const int prow = lane >> 3, pcol = (lane & 7) * 16;
+    for (uint64_t grp = blockIdx.x; grp < groups; grp += gridDim.x) {
+        unsigned char *base = out + grp * 4 * ROW;
+        for (int h = 0; h < 8; ++h) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                *(uint4 *)(lds + lane * RS + q * 16) =
+                    make_uint4((uint32_t)grp, (uint32_t)h, (uint32_t)lane, (uint32_t)q);
+            __syncthreads();
+            uint4 v[8];
+#pragma unroll
+            for (int j = 0; j < 8; ++j) v[j] = *(const uint4 *)(lds + (prow + 8 * j) * RS + pcol);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const int t = j / 2, g = prow + 8 * (j % 2);
+                *(uint4 *)(base + t * ROW + g * L_BYTES + h * 128 + pcol) = v[j];
+            }
+            __syncthreads();
+        }
+    }
+}
+
+hipError_t launch_write_probe(void *out, uint64_t bytes, int pattern, hipStream_t st)
+{
+    if (pattern == 0) {
+        const uint64_t n16 = bytes / 16;
+        const uint64_t blocks = (n16 + 255) / 256;
+        const unsigned grid = (unsigned)(blocks < (1u << 20) ? blocks : (1u << 20));
+        hipLaunchKernelGGL(probe_stream_kernel, dim3(grid), dim3(256), 0, st, (uint4 *)out, n16);
+    } else {
+        const uint64_t groups = bytes / (4 * 16384);
+        const unsigned grid = (unsigned)(groups < (1u << 30) ? groups : (1u << 30));
+        hipLaunchKernelGGL(probe_pieces_kernel, dim3(grid), dim3(64), 0, st, (unsigned char *)out,
+                           groups);
+    }
+    return hipGetLastError();
+}
+
+}  // namespace mrg

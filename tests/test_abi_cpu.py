@@ -89,7 +89,14 @@ def test_validation_returns_before_any_device_work():
     assert lib.mrg_jump(None, 0, 1, None, None) == _abi.MRG_EINVAL
     assert "null" in _abi.mrg_last_error()
     assert lib.mrg_streamset_destroy(None) == _abi.MRG_OK
-    for s in (0, -1, -2, -3, -4, -5):
+    # store probe: pattern, size unit and alignment are checked first
+    assert lib.mrg_write_probe(None, 16, 0, None) == _abi.MRG_EINVAL
+    assert lib.mrg_write_probe(4096, 16, 2, None) == _abi.MRG_EINVAL
+    assert lib.mrg_write_probe(4096, 24, 0, None) == _abi.MRG_EINVAL
+    assert lib.mrg_write_probe(4096, 65536 + 16, 1, None) == _abi.MRG_EINVAL
+    assert lib.mrg_write_probe(4096 + 16, 65536, 1, None) == _abi.MRG_EINVAL
+    assert lib.mrg_write_probe(4096, 0, 0, None) == _abi.MRG_OK
+    for s in (0, -1, -2, -3, -4, -5, -6):
         assert _abi.mrg_status_string(s).startswith("MRG_")
 
 
@@ -104,6 +111,7 @@ def test_create_without_gpu_reports_no_device():
     h = ctypes.c_void_p()
     good = (ctypes.c_uint32 * 6)(*([12345] * 6))
     assert lib.mrg_streamset_create(ctypes.byref(h), 4, 0, good, None) == _abi.MRG_ENODEV
+    assert lib.mrg_write_probe(4096, 16, 0, None) == _abi.MRG_ENODEV
 
 
 def test_workload_generators_are_deterministic_and_in_range():
