@@ -89,12 +89,14 @@ MRG_HD uint32_t combine(uint32_t x1, uint32_t x2)
 
 MRG_HD double to_f64(uint32_t z) { return (double)z * NORM; }
 
-// (2k + 1) * 2^-24 with k = (z - 1) >> 9, written as k * 2^-23 + 2^-24:
-// both terms and their sum are exact in binary32.
+// (2k + 1) * 2^-24 with k = (z - 1) >> 9 < 2^23: the binary32 number with
+// exponent 0 and mantissa k is 1 + k * 2^-23, and subtracting 1 - 2^-24 from
+// it is exact (the operands are within a factor of two, and the difference
+// (2k + 1) * 2^-24 has at most 24 significant bits).
 MRG_HD float to_f32(uint32_t z)
 {
-    uint32_t k = (z - 1u) >> 9;
-    return (float)k * 0x1p-23f + 0x1p-24f;
+    const uint32_t k = (z - 1u) >> 9;
+    return __builtin_bit_cast(float, 0x3F800000u | k) - 0x1.fffffep-1f;
 }
 
 // ---- matrix-vector product mod m for jumps (entries and x any 32-bit) ----
@@ -169,13 +171,7 @@ MRG_HD uint32_t canonf(double r, double m)
 
 MRG_HD double to_f64f(double z) { return z * NORM; }
 
-// FP32 output from an exact binary64 z: k = floor((z - 1) / 512) is exact
-// ((z-1) * 2^-9 is representable), k * 2^-23 + 2^-24 is exact in binary64
-// and has 24 significant bits, so the conversion to binary32 is exact.
-MRG_HD float to_f32f(double z)
-{
-    const double k = __builtin_floor(__builtin_fma(z, 0x1p-9, -0x1p-9));
-    return (float)__builtin_fma(k, 0x1p-23, 0x1p-24);
-}
+// FP32 output from an exact binary64 z in [1, m1]: through its uint32 value.
+MRG_HD float to_f32f(double z) { return to_f32((uint32_t)z); }
 
 }  // namespace mrg
