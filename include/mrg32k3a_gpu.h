@@ -353,7 +353,8 @@ mrg_status mrg_state_check(const uint32_t state6[6]);
  *   "engine"     0 = 32-bit integer arithmetic with lazy residues,
  *                1 = binary64 arithmetic with centred residues (default);
  *   "tile_bytes" bytes per stream per LDS tile of the lane-per-stream
- *                stream-major fill, 128 or 256 (default);
+ *                stream-major fill, 128 or 256, or 0 (default: 128 for rows
+ *                shorter than 1 KiB, else 256);
  *   "strategy"   stream-major fill: 0 = automatic (default: one wave per
  *                stream when a stream has at least 64 x 128 bytes of output,
  *                else one lane per stream), 1 = always lane per stream,

@@ -32,8 +32,8 @@ struct BatchReq {
     uint64_t scratch0;   // first scratch slot (multi-segment write-back)
     uint32_t dtype;      // 0 u32, 1 f32, 2 f64
     uint32_t flags;      // kReqSubstreams | kReqWriteBack
-    uint32_t vec_ok;     // 16-byte stores allowed (aligned rows)
     uint32_t spi;        // wave items: whole streams per item (segs == 1), else 1
+    uint32_t pad;
 };
 
 struct BatchArgs {

@@ -110,8 +110,7 @@ __device__ __forceinline__ void row_item(const BatchReq &R, uint64_t local, unsi
     }
     G g;
     g.load(w);
-    rows_fill<DT, 128, G, false>(g, lds, lane, nrows, R.out + r0 * R.n * ES, R.n * ES, R.n,
-                                 R.vec_ok != 0);
+    rows_fill<DT, 128, G, false>(g, lds, lane, nrows, R.out + r0 * R.n * ES, R.n * ES, R.n);
     if ((R.flags & kReqWriteBack) && active) {
         g.store(w);
         store_state(A.planes, A.plane_stride, R.stream0 + j, w);

@@ -156,7 +156,6 @@ mrg_status build_plan(mrg_batch b)
         R.sub0 = q.substream0;
         R.dtype = (uint32_t)q.dtype;
         R.flags = (q.flags & MRG_REQ_SUBSTREAMS) ? mrg::kReqSubstreams : mrg::kReqWriteBack;
-        R.vec_ok = ((uintptr_t)q.d_out % 16 == 0) && ((R.n * es) % 16 == 0);
         if (R.n * es >= b->cfg.wave_min_bytes) {
             uint64_t seg = b->cfg.segment_bytes / es / chunk * chunk;
             if (seg < chunk) seg = chunk;

@@ -164,18 +164,48 @@ __device__ __forceinline__ void copy_elem(unsigned char *dst, const unsigned cha
 
 // ---------------------------------------------------------------------------
 // rows_fill: one wave, lane r generates n values of its own stream (rows
-// r < nrows are written).  Each full tile of TB bytes per row goes through the
-// lane's LDS row and is written back as 16-byte chunks, TB/16 lanes per row,
-// so one store instruction covers 64*16/TB rows x TB contiguous bytes.  The
-// row pitch TB+16 keeps both the b128 writes (lanes on different rows) and
-// the reads (lanes along a row) free of bank conflicts.  Row r's output starts
-// at out0 + r * row_stride.  `lds` holds 64 * (TB + 16) bytes; the caller's
-// workgroup is this one wave.
+// r < nrows are written; row r starts at out0 + r * row_stride, which must be
+// ES-aligned).  Each row is cut into a head (the values before its first
+// 128-byte line boundary), full tiles of TB bytes, and a tail.  Every part
+// goes through the lane's LDS row: a full tile is written back as 16-byte
+// chunks, TB/16 lanes per row, so one store instruction covers 64*16/TB rows x
+// TB contiguous, line-aligned bytes; head and tail (fewer than 128 / ES and
+// TB / ES values) are written back as dwords, TB/4 lanes per row.  The row pitch TB+16
+// keeps both the b128 writes (lanes on different rows) and the reads (lanes
+// along a row) free of bank conflicts.  `lds` holds 64 * (TB + 16) bytes; the
+// caller's workgroup is this one wave.
 // ---------------------------------------------------------------------------
+template <int ES>
+__device__ __forceinline__ uint64_t head_values(const unsigned char *row, uint64_t n)
+{
+    const uint64_t h = ((128u - ((uint32_t)(uintptr_t)row & 127u)) & 127u) / ES;
+    return h < n ? h : n;
+}
+
+// Write back a partial part of every row from LDS: row r (< nrows) gets the
+// first bytes_of(r) bytes of its LDS row at row + off_of(r), as dwords, TB/4
+// lanes per row.  part(r, row, &off, &bytes) describes row r.
+template <int TB, class Part>
+__device__ __forceinline__ void rows_flush_part(const unsigned char *lds, int lane, uint64_t nrows,
+                                                unsigned char *out0, uint64_t row_stride,
+                                                const Part &part)
+{
+    constexpr int RS = TB + 16, DPR = TB / 4, RPD = 64 / DPR;
+    const int rsub = lane / DPR;
+    const uint32_t dl = (lane % DPR) * 4;
+#pragma unroll 1
+    for (int r = rsub; r < 64; r += RPD) {
+        if ((uint64_t)r >= nrows) break;
+        unsigned char *row = out0 + (uint64_t)r * row_stride;
+        uint64_t off, bytes;
+        part(row, off, bytes);
+        if (dl < bytes) *(uint32_t *)(row + off + dl) = *(const uint32_t *)(lds + r * RS + dl);
+    }
+}
+
 template <int DT, int TB, class G, bool READ_ALL = true>
 __device__ __forceinline__ void rows_fill(G &g, unsigned char *lds, int lane, uint64_t nrows,
-                                          unsigned char *out0, uint64_t row_stride, uint64_t n,
-                                          bool vec_ok)
+                                          unsigned char *out0, uint64_t row_stride, uint64_t n)
 {
     constexpr int ES = Elem<DT>::size;
     constexpr int TV = TB / ES;      // values per row per tile
@@ -184,72 +214,81 @@ __device__ __forceinline__ void rows_fill(G &g, unsigned char *lds, int lane, ui
     constexpr int RPI = 64 / LPR;    // rows per flush instruction
     constexpr int NJ = 64 / RPI;     // flush instructions per tile
 
+    const bool active = (uint64_t)lane < nrows;
+    unsigned char *myrow = out0 + (uint64_t)lane * row_stride;
+    const uint64_t hd = active ? head_values<ES>(myrow, n) : 0;
+    const uint64_t nfull = (n - hd) / TV;  // n / TV or one less
+
     unsigned char *my_lds = lds + lane * RS;
+    // head (only rows that start off a line boundary have one)
+    if (__any(hd != 0)) {
+        for (uint64_t c = 0; __any(c < hd); ++c)
+            if (c < hd) put1<DT>(my_lds + c * ES, g);
+        __syncthreads();
+        rows_flush_part<TB>(lds, lane, nrows, out0, row_stride,
+                            [n](const unsigned char *row, uint64_t &off, uint64_t &bytes) {
+                                off = 0;
+                                bytes = head_values<ES>(row, n) * ES;
+                            });
+        __syncthreads();
+    }
+
+    // the flush rows of this lane: their aligned tile base and tile count
     const int chunk = lane % LPR;
     unsigned char *rowp[NJ];
+    uint32_t short_mask = 0;  // bit j: row j has n / TV - 1 full tiles
     bool rowa[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
         const int r = lane / LPR + RPI * j;
+        unsigned char *row = out0 + (uint64_t)r * row_stride;
+        const uint64_t h = head_values<ES>(row, n);
         rowa[j] = (uint64_t)r < nrows;
-        rowp[j] = out0 + (uint64_t)r * row_stride + chunk * 16;
+        rowp[j] = row + h * ES + chunk * 16;
+        if ((n - h) / TV < n / TV) short_mask |= 1u << j;
     }
 
-    const uint64_t nfull = n / TV;
-    for (uint64_t t = 0; t < nfull; ++t) {
+    const uint64_t ntiles = n / TV;
+    for (uint64_t t = 0; t < ntiles; ++t) {
+        if (t < nfull) {
 #pragma unroll
-        for (int c = 0; c < TB / 16; ++c) *(uint4 *)(my_lds + c * 16) = gen16<DT>(g);
+            for (int c = 0; c < TB / 16; ++c) *(uint4 *)(my_lds + c * 16) = gen16<DT>(g);
+        }
         __syncthreads();
         const uint64_t off = t * TB;
-        if (vec_ok && READ_ALL) {
+        const bool last = t + 1 == ntiles;
+        if (READ_ALL) {
             // all LDS reads first, one wait, then the stores
             uint4 v[NJ];
 #pragma unroll
             for (int j = 0; j < NJ; ++j)
                 v[j] = *(const uint4 *)(lds + (lane / LPR + RPI * j) * RS + chunk * 16);
-            if (nrows == 64) {
 #pragma unroll
-                for (int j = 0; j < NJ; ++j) *(uint4 *)(rowp[j] + off) = v[j];
-            } else {
-#pragma unroll
-                for (int j = 0; j < NJ; ++j)
-                    if (rowa[j]) *(uint4 *)(rowp[j] + off) = v[j];
-            }
-        } else if (vec_ok) {
+            for (int j = 0; j < NJ; ++j)
+                if (rowa[j] && !(last && ((short_mask >> j) & 1u))) *(uint4 *)(rowp[j] + off) = v[j];
+        } else {
 #pragma unroll
             for (int j = 0; j < NJ; ++j) {
                 const uint4 v = *(const uint4 *)(lds + (lane / LPR + RPI * j) * RS + chunk * 16);
-                if (rowa[j]) *(uint4 *)(rowp[j] + off) = v;
-            }
-        } else {
-            // unaligned rows: dword copies, 64 * 4 / TB rows per instruction,
-            // each row's TB bytes still one contiguous run
-            constexpr int DPR = TB / 4, RPD = 64 / DPR;
-            const int rsub = lane / DPR;
-            unsigned char *p = out0 + off + (lane % DPR) * 4 + (uint64_t)rsub * row_stride;
-            const unsigned char *sp = lds + rsub * RS + (lane % DPR) * 4;
-            const uint64_t step = (uint64_t)RPD * row_stride;
-#pragma unroll 1
-            for (int r = rsub; r < 64; r += RPD) {
-                if ((uint64_t)r < nrows) *(uint32_t *)p = *(const uint32_t *)sp;
-                p += step;
-                sp += RPD * RS;
+                if (rowa[j] && !(last && ((short_mask >> j) & 1u))) *(uint4 *)(rowp[j] + off) = v;
             }
         }
         __syncthreads();
     }
-    // tail: fewer than TV values per row
-    const int tail = (int)(n - nfull * TV);
-    if (tail) {
-        for (int c = 0; c < tail; ++c) put1<DT>(my_lds + c * ES, g);
+
+    // tail
+    const uint64_t tail = active ? n - hd - nfull * TV : 0;
+    if (__any(tail != 0)) {
+        for (uint64_t c = 0; __any(c < tail); ++c)
+            if (c < tail) put1<DT>(my_lds + c * ES, g);
         __syncthreads();
-        const uint64_t off = nfull * TB;
-        for (int e = lane; e < 64 * tail; e += 64) {
-            const int r = e / tail, col = e % tail;
-            if ((uint64_t)r < nrows)
-                copy_elem<ES>(out0 + (uint64_t)r * row_stride + off + (uint64_t)col * ES,
-                              lds + r * RS + col * ES);
-        }
+        rows_flush_part<TB>(lds, lane, nrows, out0, row_stride,
+                            [n](const unsigned char *row, uint64_t &off, uint64_t &bytes) {
+                                const uint64_t h = head_values<ES>(row, n);
+                                const uint64_t t0 = h + (n - h) / TV * TV;
+                                off = t0 * ES;
+                                bytes = (n - t0) * ES;
+                            });
         __syncthreads();
     }
 }

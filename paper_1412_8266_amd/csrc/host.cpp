@@ -454,7 +454,6 @@ mrg_status mrg_fill(mrg_streamset ss, uint64_t first, uint64_t count, uint64_t n
     if ((uintptr_t)d_out % es) return set_error(MRG_EINVAL, "output not aligned to its element size");
     if (n_per_stream > UINT64_MAX / es / count)
         return set_error(MRG_ERANGE, "output size overflows 64 bits");
-    const int vec_ok = ((uintptr_t)d_out % 16 == 0) && ((n_per_stream * es) % 16 == 0);
     const mrg::FillTuning tune = tuning();
     mrg::FillLaunch fl;
     if (layout == MRG_STREAM_MAJOR) {
@@ -493,7 +492,7 @@ mrg_status mrg_fill(mrg_streamset ss, uint64_t first, uint64_t count, uint64_t n
         }
     }
     hipError_t e = mrg::launch_fill(ss->d_planes, ss->n, first, count, n_per_stream, (int)dtype,
-                                    (int)layout, d_out, vec_ok, fl, tune, (hipStream_t)stream);
+                                    (int)layout, d_out, fl, tune, (hipStream_t)stream);
     return e == hipSuccess ? MRG_OK : hip_error(e, "fill kernel launch");
 }
 
@@ -560,7 +559,8 @@ mrg_status mrg_config_set(const char *key, int64_t value)
         if (value < 0 || value > 2) return set_error(MRG_EINVAL, "strategy must be 0, 1 or 2");
         g_tune.strategy = (int)value;
     } else if (!std::strcmp(key, "tile_bytes")) {
-        if (value != 128 && value != 256) return set_error(MRG_EINVAL, "tile_bytes must be 128 or 256");
+        if (value != 0 && value != 128 && value != 256)
+            return set_error(MRG_EINVAL, "tile_bytes must be 0 (automatic), 128 or 256");
         g_tune.tile_bytes = (int)value;
     } else {
         return set_error(MRG_EINVAL, "unknown key '%s'", key);

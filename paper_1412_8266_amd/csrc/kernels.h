@@ -27,7 +27,7 @@ hipError_t launch_jump_uniform(uint32_t *planes, uint64_t plane_stride, uint64_t
 // stream).
 struct FillTuning {
     int engine = 1;
-    int tile_bytes = 256;
+    int tile_bytes = 0;       // lane per stream: 0 = 128 for rows under 1 KiB, else 256
     int strategy = 0;
     int coop_wgs_per_cu = 0;  // wave per stream: 0 = one workgroup per stream group
     int coop_lanes = 16;      // wave per stream: lanes per stream (64, 32, 16 or 8)
@@ -52,7 +52,7 @@ struct FillLaunch {
 };
 
 hipError_t launch_fill(uint32_t *planes, uint64_t plane_stride, uint64_t first, uint64_t count,
-                       uint64_t n, int dtype, int layout, void *out, int vec_ok,
+                       uint64_t n, int dtype, int layout, void *out,
                        const FillLaunch &fl, const FillTuning &tune, hipStream_t st);
 
 // Store-only bandwidth probes (probe.hip): pattern 0 streaming, 1 the

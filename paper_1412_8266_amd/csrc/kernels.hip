@@ -105,7 +105,7 @@ jumpu_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t firs
 template <int DT, int TB, class G>
 __global__ void __launch_bounds__(64)
 fill_sm_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t first,
-               uint64_t count, uint64_t n, unsigned char *__restrict__ out, int vec_ok)
+               uint64_t count, uint64_t n, unsigned char *__restrict__ out)
 {
     constexpr int ES = Elem<DT>::size;
     __shared__ __attribute__((aligned(16))) unsigned char lds[64 * (TB + 16)];
@@ -119,7 +119,7 @@ fill_sm_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t fi
     if (active) load_state(planes, plane_stride, idx, w);
     G g;
     g.load(w);
-    rows_fill<DT, TB, G>(g, lds, lane, nrows, out + s0 * n * ES, n * ES, n, vec_ok != 0);
+    rows_fill<DT, TB, G>(g, lds, lane, nrows, out + s0 * n * ES, n * ES, n);
     if (active) {
         g.store(w);
         store_state(planes, plane_stride, idx, w);
@@ -232,7 +232,7 @@ hipError_t launch_jump_uniform(uint32_t *planes, uint64_t plane_stride, uint64_t
 
 template <int DT, class G>
 static hipError_t launch_fill_g(uint32_t *planes, uint64_t plane_stride, uint64_t first,
-                                uint64_t count, uint64_t n, int layout, void *out, int vec_ok,
+                                uint64_t count, uint64_t n, int layout, void *out,
                                 const FillLaunch &fl, int tile_bytes, hipStream_t st)
 {
     unsigned char *o = (unsigned char *)out;
@@ -257,12 +257,12 @@ static hipError_t launch_fill_g(uint32_t *planes, uint64_t plane_stride, uint64_
         else if (fl.lanes == 8 && nh == 16) MRG_COOP(8, 16);
         else return hipErrorInvalidValue;
 #undef MRG_COOP
-    } else if (tile_bytes >= 256) {
+    } else if (tile_bytes == 256 || (tile_bytes == 0 && n * Elem<DT>::size >= 1024)) {
         hipLaunchKernelGGL((fill_sm_kernel<DT, 256, G>), dim3(grid_of(count, 64)), dim3(64), 0, st,
-                           planes, plane_stride, first, count, n, o, vec_ok);
+                           planes, plane_stride, first, count, n, o);
     } else {
         hipLaunchKernelGGL((fill_sm_kernel<DT, 128, G>), dim3(grid_of(count, 64)), dim3(64), 0, st,
-                           planes, plane_stride, first, count, n, o, vec_ok);
+                           planes, plane_stride, first, count, n, o);
     }
     return hipGetLastError();
 }
@@ -270,24 +270,24 @@ static hipError_t launch_fill_g(uint32_t *planes, uint64_t plane_stride, uint64_
 template <class G>
 static hipError_t launch_fill_d(uint32_t *planes, uint64_t plane_stride, uint64_t first,
                                 uint64_t count, uint64_t n, int dtype, int layout, void *out,
-                                int vec_ok, const FillLaunch &fl, int tile_bytes, hipStream_t st)
+                                const FillLaunch &fl, int tile_bytes, hipStream_t st)
 {
     switch (dtype) {
-    case 0: return launch_fill_g<0, G>(planes, plane_stride, first, count, n, layout, out, vec_ok, fl, tile_bytes, st);
-    case 1: return launch_fill_g<1, G>(planes, plane_stride, first, count, n, layout, out, vec_ok, fl, tile_bytes, st);
-    default: return launch_fill_g<2, G>(planes, plane_stride, first, count, n, layout, out, vec_ok, fl, tile_bytes, st);
+    case 0: return launch_fill_g<0, G>(planes, plane_stride, first, count, n, layout, out, fl, tile_bytes, st);
+    case 1: return launch_fill_g<1, G>(planes, plane_stride, first, count, n, layout, out, fl, tile_bytes, st);
+    default: return launch_fill_g<2, G>(planes, plane_stride, first, count, n, layout, out, fl, tile_bytes, st);
     }
 }
 
 hipError_t launch_fill(uint32_t *planes, uint64_t plane_stride, uint64_t first, uint64_t count,
-                       uint64_t n, int dtype, int layout, void *out, int vec_ok,
+                       uint64_t n, int dtype, int layout, void *out,
                        const FillLaunch &fl, const FillTuning &tune, hipStream_t st)
 {
     if (tune.engine == 1)
-        return launch_fill_d<GenF>(planes, plane_stride, first, count, n, dtype, layout, out,
-                                   vec_ok, fl, tune.tile_bytes, st);
-    return launch_fill_d<GenI>(planes, plane_stride, first, count, n, dtype, layout, out, vec_ok,
-                               fl, tune.tile_bytes, st);
+        return launch_fill_d<GenF>(planes, plane_stride, first, count, n, dtype, layout, out, fl,
+                                   tune.tile_bytes, st);
+    return launch_fill_d<GenI>(planes, plane_stride, first, count, n, dtype, layout, out, fl,
+                               tune.tile_bytes, st);
 }
 
 }  // namespace mrg

@@ -150,7 +150,6 @@ mrg::BatchReq to_batch_req(mrg_server s, const Req &r)
     R.sub0 = r.sub0;
     R.dtype = (uint32_t)r.dtype;
     R.flags = mrg::kReqSubstreams;
-    R.vec_ok = (r.n * es) % 16 == 0;
     if (r.n * es >= 16 * 1024) {
         const uint64_t chunk = 64 * (256 / es);
         uint64_t seg = (256 * 1024) / es / chunk * chunk;
