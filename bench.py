@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched request mix")
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
+    ap.add_argument("--batch-only", action="store_true",
+                    help="only the batched request mix (prints its JSON object; for profiling)")
     ap.add_argument("--serve-speeds", type=float, nargs="*", default=[1.1, 1.2],
                     help="arrival-rate multiples replayed for 4 s each")
     ap.add_argument("--serve-seconds", type=float, default=10.0,
@@ -233,6 +235,11 @@ def main():
     engine = mg.mrg_config_get("engine")
     tile = mg.mrg_config_get("tile_bytes")
     stream = torch.cuda.current_stream()
+
+    if args.batch_only:
+        print("[bench] batched request mix", file=sys.stderr, flush=True)
+        print(json.dumps({"batched": batched(mg, wl, torch, stream, args.batch_reps)}), flush=True)
+        return
 
     S, n = wl.C2_STREAMS, wl.C2_N
     samples = S * n
