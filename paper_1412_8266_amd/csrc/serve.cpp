@@ -7,9 +7,9 @@
 // substreams of 2^76 values), so requests of one client never depend on each
 // other and can run concurrently.  A scheduler thread admits queued requests
 // in arrival order while the output arena has room (first fit), launches each
-// admitted group as one batch-kernel launch ("tick") on the next of several
-// HIP streams -- ticks overlap on the device -- and retires ticks by polling
-// their completion events.  Latency is measured from submission to the
+// admitted group ("tick": one persistent batch kernel per dtype and item kind)
+// on the next of several HIP streams -- ticks overlap on the device -- and
+// retires ticks by polling their completion events.  Latency is measured from submission to the
 // moment the scheduler observes the tick's event complete.
 #include <hip/hip_runtime.h>
 
@@ -22,6 +22,7 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <string>
 #include <thread>
 #include <vector>
 
@@ -126,7 +127,7 @@ struct mrg_server_s {
     std::mutex mu;
     std::condition_variable cv;
     std::deque<Req> pending;
-    std::vector<Req> done;            // finished, not yet taken by poll
+    std::deque<Req> done;             // finished, not yet taken by poll
     std::map<uint64_t, Req> held;     // finished, output held until release
     uint64_t next_ticket = 1;
     uint64_t inflight_reqs = 0;
@@ -253,10 +254,15 @@ void scheduler(mrg_server s)
             if (!free_slot->reqs.empty()) {
                 s->inflight_reqs += free_slot->reqs.size();
                 ++s->ticks;
-                mrg_status st = launch_tick(s, *free_slot);
+                // the slot belongs to this thread alone: launch without the
+                // lock, so that submissions are not held up by the launches
+                lk.unlock();
+                const mrg_status st = launch_tick(s, *free_slot);
+                const std::string err = st ? mrg_last_error() : "";
+                lk.lock();
                 if (st) {
                     s->worker_status = st;
-                    s->worker_error = mrg_last_error();
+                    s->worker_error = err;
                     s->stop = true;
                 }
                 progressed = true;
@@ -280,7 +286,7 @@ mrg_status mrg_server_create(mrg_server *out, const mrg_server_config *cfg_in)
     mrg_server_config cfg = *cfg_in;
     if (!cfg.n_clients) return set_error(MRG_ERANGE, "n_clients must be >= 1");
     if (!cfg.arena_bytes) return set_error(MRG_ERANGE, "arena_bytes must be > 0");
-    if (!cfg.max_inflight) cfg.max_inflight = 4;
+    if (!cfg.max_inflight) cfg.max_inflight = 8;
     if (!cfg.max_batch) cfg.max_batch = 4096;
     if (!cfg.waves_per_cu) cfg.waves_per_cu = 16;
     if (cfg.max_inflight > 64) return set_error(MRG_ERANGE, "max_inflight above 64");
