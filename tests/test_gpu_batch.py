@@ -243,6 +243,49 @@ def test_autotune_restores_states_and_keeps_results(mg):
     ss.close()
 
 
+def test_c4_full_mix_sampled(mg):
+    """The 10,000-request mix at full size in one graph run.  Forty sampled
+    requests (each under 256 MiB) get buffers of their own; every other request
+    writes into one shared scratch region (its contents are not checked).
+    First, middle and last stream of each sampled request against the oracle,
+    and their end states."""
+    import torch
+    say("C4 full mix, sampled")
+    req = wl.c4_requests()
+    nb = req.bytes()
+    rng = np.random.default_rng(44)
+    small = np.flatnonzero(nb <= (256 << 20))
+    sample = sorted(rng.choice(small, 40, replace=False).tolist())
+    scratch = torch.empty(int(nb.max()) // 8 + 32, dtype=torch.float64, device="cuda")
+    outs, rows = {}, []
+    for i in range(len(req)):
+        k, n, dt = int(req.n_streams[i]), int(req.length[i]), int(req.dtype[i])
+        if i in sample:
+            outs[i] = torch.empty((k, n), dtype=mg.torch_dtype(dt), device="cuda")
+            ptr = outs[i].data_ptr()
+        else:
+            ptr = scratch.data_ptr()
+        rows.append((int(req.first_stream[i]), k, n, 0, ptr, dt, 0))
+    S = int(req.n_streams.sum())
+    base = oracle.seed_from_master(wl.MASTER_SEED)
+    ss = mg.StreamSet(S, master_seed=wl.MASTER_SEED)
+    b = mg.Batch(ss, rows)
+    assert b.info()["samples"] == int(req.samples().sum())
+    b.run()
+    for i in sample:
+        first, k, n, dt = int(req.first_stream[i]), int(req.n_streams[i]), int(req.length[i]), \
+            int(req.dtype[i])
+        got = host(outs[i])
+        for j in sorted({0, k // 2, k - 1}):
+            st0 = oracle.stream_start(base, first + j)[None, :]
+            want, st1 = oracle.fill(st0, n, dt)
+            assert np.array_equal(got[j].view(np.uint8), want[0].view(np.uint8)), (i, j)
+            assert np.array_equal(ss.get_states(first + j, 1)[0], st1[0]), (i, j)
+    b.close()
+    ss.close()
+    del scratch
+
+
 def test_batch_validation(mg):
     import torch
     ss = mg.StreamSet(100, master_seed=1)
