@@ -130,9 +130,13 @@ def batched(mg, wl, torch, stream, reps):
     S = int(req.n_streams.sum())
     ss = mg.StreamSet(S, master_seed=wl.MASTER_SEED)
     b = mg.Batch(ss, rows)
-    cands = [mg.batch_config(segment_bytes=sb, waves_per_cu=w, schedule=sc)
-             for sb, w, sc in [(256 << 10, 16, 1), (1 << 20, 16, 1), (256 << 10, 8, 1),
-                               (64 << 10, 16, 1), (256 << 10, 16, 2)]]
+    # segment length (tile), persistent waves, claiming schedule, and the
+    # stream length above which a stream gets a whole wave instead of a lane
+    cands = [mg.batch_config(segment_bytes=sb, waves_per_cu=w, schedule=sc, wave_min_bytes=wm)
+             for sb, w, sc, wm in [(256 << 10, 16, 1, 16 << 10), (1 << 20, 16, 1, 16 << 10),
+                                   (256 << 10, 8, 1, 16 << 10), (64 << 10, 16, 1, 16 << 10),
+                                   (256 << 10, 16, 2, 16 << 10), (1 << 20, 16, 1, 4 << 10),
+                                   (1 << 20, 16, 1, 64 << 10)]]
     t0 = time.perf_counter()
     best, cand_ms = b.autotune(cands, reps=1)
     tune_s = time.perf_counter() - t0
@@ -155,6 +159,7 @@ def batched(mg, wl, torch, stream, reps):
         "batched_over_per_request": round(ms_r / ms_b, 3),
         "batched_hbm_frac": round(info["bytes"] / ms_b / 1e6 / HBM_PEAK_GBS, 4),
         "autotune": {"chosen": {"segment_bytes": info["segment_bytes"],
+                                "wave_min_bytes": info["wave_min_bytes"],
                                 "waves_per_cu": info["waves_per_cu"],
                                 "schedule": "static" if info["schedule"] == 2 else "dynamic"},
                      "candidate_ms": [round(x, 3) for x in cand_ms], "seconds": round(tune_s, 2)},
