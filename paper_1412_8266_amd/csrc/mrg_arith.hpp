@@ -18,11 +18,12 @@
 // residue, with min(x, x + C) (x + C wraps below x exactly when x >= m).
 //
 // A second formulation keeps the state in binary64 (the "F" functions):
-// every product-sum a*s - b*t with |s|, |t| <= m/2 + 8 is below 2^53 in
-// magnitude, so one FMA forms it exactly; r = p - m * rint(p / m) is exact
-// (the quotient only needs to be near the true one) and lies within
-// m/2 + 8 of zero.  Each step is then five binary64 operations per
-// component.  Both formulations give the same residues.
+// words are integer-valued doubles in [-5, m), every product-sum of them is
+// below 2^53 in magnitude, so one FMA forms it exactly, and
+// r = p - m * floor(p / m + bias) is exact (the biased quotient is the true
+// one or one more) and lands back in [-5, m).  Each step is then five
+// binary64 operations per component and five more for the combination.  Both
+// formulations give the same residues.
 #pragma once
 #include <stdint.h>
 
@@ -132,37 +133,44 @@ constexpr double M2D = 4294944443.0;
 constexpr double INV1 = 1.0 / 4294967087.0;  // rounds above 1/m1: m1 * INV1 -> 1.0
 constexpr double INV2 = 1.0 / 4294944443.0;
 
-// Next centred component-1 word from x1[n-3] = s0 and x1[n-2] = s1.
+// The words are near-canonical: integer-valued doubles in [-5, m), each
+// congruent to its residue.  A product-sum of such words stays below 2^53 in
+// magnitude (at most 6.03e15 for component 1, 5.89e15 for component 2), so one
+// FMA forms it exactly.  The quotient t = RN(p * INV + 2^-30) exceeds p/m by
+// between 6.2e-10 and 1.25e-9 (|p/m| < 1.41e6 bounds both roundings by
+// 3.2e-10), so floor(t) is the true quotient, or one more when the residue is
+// within 5.4 of m; r = p - m * floor(t) is then exact and lies in [-5, m).
+constexpr double QBIAS = 0x1p-30;
+
+// Next component-1 word from x1[n-3] = s0 and x1[n-2] = s1.
 MRG_HD double next1f(double s0, double s1)
 {
     const double p = __builtin_fma((double)A12, s1, -((double)A13N * s0));
-    return __builtin_fma(-__builtin_rint(p * INV1), M1D, p);
+    return __builtin_fma(-__builtin_floor(__builtin_fma(p, INV1, QBIAS)), M1D, p);
 }
 
-// Next centred component-2 word from x2[n-3] = s3 and x2[n-1] = s5.
+// Next component-2 word from x2[n-3] = s3 and x2[n-1] = s5.
 MRG_HD double next2f(double s3, double s5)
 {
     const double p = __builtin_fma((double)A21, s5, -((double)A23N * s3));
-    return __builtin_fma(-__builtin_rint(p * INV2), M2D, p);
+    return __builtin_fma(-__builtin_floor(__builtin_fma(p, INV2, QBIAS)), M2D, p);
 }
 
-// Combined output z' in [1, m1] (as an exact binary64 integer) from centred
-// r1, r2.  With x2 the canonical residue of r2,
-//   x1 - x2 = r1 - r2 + 22644 * [r2 < 0]  (mod m1)      (m1 - m2 = 22644),
-// where [r2 < 0] = clamp(-r2, 0, 1) since r2 is an integer.  The sum w lies
-// in (-m1 + 1, 2 m1); z = w - m1 * floor((w - 1) / m1) maps it to [1, m1].
-// The quotient is exact: (w-1)/m1 is at least 1/m1 away from any integer
-// except at w - 1 in {0, m1}, where RN((w-1) * INV1) gives 0 and 1.
+// Combined output z' in [1, m1] (as an exact binary64 integer) from
+// near-canonical r1, r2.  x2 = r2 + m2 * [r2 < 0] is the canonical residue of
+// r2 ([r2 < 0] = clamp(-r2, 0, 1), r2 being an integer); w = r1 - x2 lies in
+// [-m2 - 4, m1 - 1] and is congruent to the combination mod m1, so
+// z = w + m1 * [w <= 0] with [w <= 0] = clamp(1 - w, 0, 1) lands in
+// [m1 - m2 - 4, m1], and w = 0 (equal residues) gives m1.
 MRG_HD double combinef(double r1, double r2)
 {
-    const double w = r1 - r2;
     const double c = __builtin_fmin(__builtin_fmax(-r2, 0.0), 1.0);
-    const double w2 = __builtin_fma(c, 22644.0, w);
-    const double k = __builtin_floor(__builtin_fma(w2, INV1, -INV1));
-    return __builtin_fma(-k, M1D, w2);
+    const double w = r1 - __builtin_fma(c, M2D, r2);
+    const double k = __builtin_fmin(__builtin_fmax(1.0 - w, 0.0), 1.0);
+    return __builtin_fma(k, M1D, w);
 }
 
-// Canonical residue (as uint32) of a centred word.
+// Canonical residue (as uint32) of a near-canonical word.
 MRG_HD uint32_t canonf(double r, double m)
 {
     const double c = __builtin_fmin(__builtin_fmax(-r, 0.0), 1.0);

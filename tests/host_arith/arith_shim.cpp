@@ -42,6 +42,8 @@ void shim_run_f64(uint32_t *w, uint64_t n, uint32_t *out, float *outf, double *o
 
 uint32_t shim_combine(uint32_t x1, uint32_t x2) { return combine(x1, x2); }
 double shim_combinef(double r1, double r2) { return combinef(r1, r2); }
+double shim_next1f(double s0, double s1) { return next1f(s0, s1); }
+double shim_next2f(double s3, double s5) { return next2f(s3, s5); }
 uint32_t shim_canon1(uint32_t x) { return canon1(x); }
 uint32_t shim_canon2(uint32_t x) { return canon2(x); }
 uint32_t shim_canonf(double r, int comp) { return canonf(r, comp ? M2D : M1D); }

@@ -34,6 +34,9 @@ def shim(tmp_path_factory):
     lib.shim_combine.restype = ctypes.c_uint32
     lib.shim_combinef.argtypes = [ctypes.c_double, ctypes.c_double]
     lib.shim_combinef.restype = ctypes.c_double
+    for n in ("shim_next1f", "shim_next2f"):
+        getattr(lib, n).argtypes = [ctypes.c_double, ctypes.c_double]
+        getattr(lib, n).restype = ctypes.c_double
     for n in ("shim_canon1", "shim_canon2"):
         getattr(lib, n).argtypes = [ctypes.c_uint32]
         getattr(lib, n).restype = ctypes.c_uint32
@@ -126,20 +129,41 @@ def test_combine_boundaries(shim):
 
 
 def test_combinef_boundaries(shim):
-    # centred representatives r1 in [-m1/2-2, m1/2+2], r2 likewise
-    h1, h2 = M1 // 2, M2 // 2
-    r1s = [-h1 - 2, -h1, -1, 0, 1, h1, h1 + 2, 22644, -22644, 22643, 12345]
-    r2s = [-h2 - 2, -h2, -1, 0, 1, h2, h2 + 2, 22644, -22645, 12345]
+    # near-canonical representatives: r1 in [-5, m1), r2 in [-5, m2)
+    r1s = [-5, -4, -1, 0, 1, 2, 22643, 22644, 22645, M2 - 1, M2, M1 - 2, M1 - 1, 2**31, 12345]
+    r2s = [-5, -1, 0, 1, 22644, M2 - 2, M2 - 1, 2**31, 12345]
     for r1 in r1s:
         for r2 in r2s:
             z = ((r1 % M1) - (r2 % M2)) % M1 or M1
             assert shim.shim_combinef(float(r1), float(r2)) == float(z), (r1, r2)
-    # equal residues give m1; w - 1 = m1 exactly
+    # equal residues give m1
     assert shim.shim_combinef(0.0, 0.0) == float(M1)
-    for r in (-h1 - 2, -1, 0, 1, h1 + 2):
+    assert shim.shim_combinef(float(M2 - 1), -1.0) == float(M1)
+    for r in (-5, -1, 0, 1, M1 - 1):
         assert shim.shim_canonf(float(r), 0) == r % M1
-    for r in (-h2 - 2, -1, 0, 1, h2 + 2):
+    for r in (-5, -1, 0, 1, M2 - 1):
         assert shim.shim_canonf(float(r), 1) == r % M2
+
+
+def test_binary64_reduction_at_quotient_boundaries(shim):
+    """next1f/next2f on inputs whose product-sum has residue 0, 1, 2 or m-1 ..
+    m-6 (where a rounded quotient can be off by one), at the largest and
+    smallest product-sums the input range allows: the result must be an
+    exact representative in [-5, m)."""
+    rng = random.Random(12)
+    for comp, m, a, b, f in ((0, M1, 1403580, 810728, shim.shim_next1f),
+                             (1, M2, 527612, 1370589, shim.shim_next2f)):
+        ainv = pow(a, -1, m)
+        olds = [-5, -1, 0, 1, m - 1, m - 2, (m - 1) // 2] + [rng.randrange(m) for _ in range(40)]
+        targets = [0, 1, 2, 3, m - 1, m - 2, m - 3, m - 4, m - 5, m - 6, m - 7]
+        for s0 in olds:
+            for tgt in targets:
+                # a*s1 - b*s0 = tgt (mod m); also try s1 shifted to its extremes
+                s1 = (tgt + b * s0) * ainv % m
+                for s1r in {s1, s1 - m if s1 <= 5 else s1}:
+                    r = f(float(s0), float(s1r))
+                    assert r == int(r) and -5 <= r < m, (comp, s0, s1r, r)
+                    assert int(r) % m == (a * s1r - b * s0) % m, (comp, s0, s1r, r)
 
 
 def test_conversions_match_oracle(shim):
