@@ -351,7 +351,7 @@ mrg_status mrg_state_check(const uint32_t state6[6]);
 
 /* Process-wide tuning of the generation kernels (no effect on results):
  *   "engine"     0 = 32-bit integer arithmetic with lazy residues,
- *                1 = binary64 arithmetic with centred residues (default);
+ *                1 = binary64 arithmetic on integer-valued doubles (default);
  *   "tile_bytes" bytes per stream per LDS tile of the lane-per-stream
  *                stream-major fill, 128 or 256, or 0 (default: 128 for rows
  *                shorter than 1 KiB, else 256);

@@ -80,7 +80,7 @@ struct GenI {
     __device__ __forceinline__ double next_f64() { return to_f64(step()); }
 };
 
-// Binary64 generator: centred integer-valued doubles, five FP64 operations
+// Binary64 generator: near-canonical integer-valued doubles, five FP64 operations
 // per component per step.
 struct GenF {
     double a0, a1, a2, b0, b1, b2;

@@ -21,7 +21,7 @@ hipError_t launch_jump(uint32_t *planes, uint64_t plane_stride, uint64_t first, 
                        const uint64_t *d_exp, const uint32_t *table, hipStream_t st);
 hipError_t launch_jump_uniform(uint32_t *planes, uint64_t plane_stride, uint64_t first,
                                uint64_t count, const JumpMatrices &J, hipStream_t st);
-// Generation engine (0: integer lazy words, 1: binary64 centred words),
+// Generation engine (0: integer lazy words, 1: binary64 near-canonical words),
 // bytes per row per LDS tile (128 or 256) of the lane-per-stream fill, and
 // the stream-major strategy (0: automatic, 1: lane per stream, 2: wave per
 // stream).
