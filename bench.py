@@ -37,6 +37,10 @@ METRIC = "uint32 Gsamples/s (% HBM write roofline), batched vs plain; p50/p99 la
 # HBM bytes per launch read by rocprofv3 (FETCH_SIZE + WRITE_SIZE, scaled by a
 # copy-kernel calibration); None until measured for the current kernel.
 COUNTER_TRAFFIC = 17431918387  # fill_coop_kernel<u32,256,16>: profiles/fill_coop_u32_16lanes_2p20x4096.md
+# VALU wave instructions per launch of the same kernel (SQ_INSTS_VALU, same profile);
+# None until measured for the current kernel.
+COUNTER_VALU_INSTS = 1143209984
+SIMDS, PEAK_SCLK_MHZ = 1024, 2400  # MI355X: 256 CUs x 4 SIMDs, 2.4 GHz peak shader clock
 
 
 def parse():
@@ -82,6 +86,17 @@ def timed(fn, steps, warmup, stream):
     return per, wall
 
 
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
 def cpu_baseline(streams: int, n: int):
     import numpy as np
     import oracle
@@ -101,7 +116,7 @@ def cpu_baseline(streams: int, n: int):
                   "single-threaded C oracle, fill only (start states precomputed)"
                   % (streams, n, streams * n),
         "seconds": dt,
-        "cpu": platform.processor() or platform.machine(),
+        "cpu": _cpu_model(),
         "host_cpus": os.cpu_count(),
     }
 
@@ -142,6 +157,9 @@ def batched(mg, wl, torch, stream, reps):
     tune_s = time.perf_counter() - t0
     info = b.info()
     per_b, _ = timed(lambda: b.run(), reps, 1, stream)
+    import numpy as np
+    done = b.request_times()  # of the last graph run
+    done = np.sort(done[req.samples() > 0])
     per_r, _ = timed(lambda: b.run_per_request(), reps, 1, stream)
     ms_b = sum(per_b) / len(per_b)
     ms_r = sum(per_r) / len(per_r)
@@ -157,6 +175,11 @@ def batched(mg, wl, torch, stream, reps):
         "batched_Gsamples_s": round(samples / ms_b / 1e6, 2),
         "per_request_Gsamples_s": round(samples / ms_r / 1e6, 2),
         "batched_over_per_request": round(ms_r / ms_b, 3),
+        # device wall clock from the run's first workgroup start to each
+        # request's last work item, over the 10,000 requests
+        "request_completion_ms": {"p50": round(float(done[len(done) // 2]), 3),
+                                  "p99": round(float(done[int(0.99 * len(done))]), 3),
+                                  "max": round(float(done[-1]), 3)},
         "batched_hbm_frac": round(info["bytes"] / ms_b / 1e6 / HBM_PEAK_GBS, 4),
         "autotune": {"chosen": {"segment_bytes": info["segment_bytes"],
                                 "wave_min_bytes": info["wave_min_bytes"],
@@ -303,6 +326,13 @@ def main():
                       else "fill_sm_kernel<u32>",
             "alg_bytes_per_launch": alg_bytes,
             "avg_launch_ms": round(ms, 4),
+        },
+        "valu": None if COUNTER_VALU_INSTS is None else {
+            # issue cycles at 4 clocks per wave instruction (FP64 rate) over the
+            # cycles the launch would span at the peak clock: VALU use against peak
+            "instr_per_sample": round(COUNTER_VALU_INSTS * 64 / samples, 2),
+            "issue_frac_at_peak_clock": round(COUNTER_VALU_INSTS * 4 / SIMDS
+                                              / (ms * 1e-3 * PEAK_SCLK_MHZ * 1e6), 4),
         },
         "wall_s_timed": round(wall, 3),
     }

@@ -232,6 +232,13 @@ mrg_status mrg_batch_run_per_request(mrg_batch b, void *stream);
 
 mrg_status mrg_batch_info(mrg_batch b, mrg_batch_info_t *info);
 
+/* Completion time of every request in the last mrg_batch_run or
+ * mrg_batch_run_direct: h_ms[i] (n_reqs doubles, host memory, input order)
+ * receives the milliseconds from the earliest workgroup start of that run to
+ * the device wall clock read when request i's last work item ended (0 for
+ * requests with count or n_per_stream 0).  Waits for `stream` first. */
+mrg_status mrg_batch_request_times(mrg_batch b, void *stream, double *h_ms);
+
 /* Time each candidate configuration (reps runs after one warm-up, on
  * `stream`), keep the fastest and re-plan with it.  The stream states are
  * restored afterwards, so autotuning has no visible effect on results.

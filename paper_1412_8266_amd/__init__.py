@@ -202,6 +202,12 @@ class Batch:
     def run_direct(self, stream=None) -> None:
         _abi.mrg_batch_run_direct(self._h, _stream_handle(stream))
 
+    def request_times(self, stream=None) -> np.ndarray:
+        """Milliseconds from the start of the last run to each request's end
+        (input order; 0 for empty requests)."""
+        return np.asarray(_abi.mrg_batch_request_times(self._h, self.n_requests,
+                                                       _stream_handle(stream)))
+
     def run_per_request(self, stream=None) -> None:
         _abi.mrg_batch_run_per_request(self._h, _stream_handle(stream))
 

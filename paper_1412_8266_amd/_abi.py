@@ -96,6 +96,7 @@ _SIGS.update({
     "mrg_batch_run_direct": [_P, _P],
     "mrg_batch_run_per_request": [_P, _P],
     "mrg_batch_info": [_P, ctypes.POINTER(mrg_batch_info_t)],
+    "mrg_batch_request_times": [_P, _P, ctypes.POINTER(ctypes.c_double)],
     "mrg_batch_autotune": [_P, ctypes.POINTER(mrg_batch_config), ctypes.c_uint32, ctypes.c_uint32,
                            _P, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_float)],
     "mrg_batch_destroy": [_P],
@@ -318,6 +319,12 @@ def mrg_batch_info(b: int) -> dict:
             "bytes": info.bytes, "scratch_states": info.scratch_states, "grid": info.grid,
             "segment_bytes": c.segment_bytes, "wave_min_bytes": c.wave_min_bytes,
             "waves_per_cu": c.waves_per_cu, "schedule": c.schedule}
+
+
+def mrg_batch_request_times(b: int, n_reqs: int, stream: int = 0):
+    arr = (ctypes.c_double * max(n_reqs, 1))()
+    _call("mrg_batch_request_times", b, stream, arr)
+    return [arr[i] for i in range(n_reqs)]
 
 
 def mrg_batch_autotune(b: int, configs, reps: int = 1, stream: int = 0):

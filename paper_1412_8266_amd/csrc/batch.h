@@ -55,6 +55,12 @@ struct BatchArgs {
     uint32_t n_cb;
     uint32_t pad;
     uint64_t cb_slots;
+    // completion stamps (all NULL: none): per request of the group, items
+    // finished and the wall clock when its last item ended; the earliest
+    // workgroup start of the run
+    unsigned long long *req_cnt;
+    unsigned long long *req_done;
+    unsigned long long *t_start;
 };
 
 inline int kind_of(const BatchReq &R) { return R.seg ? kKindWave : kKindRow; }
@@ -93,5 +99,8 @@ hipError_t launch_grouped(const Grouped &g, const BatchReq *d_reqs, const uint64
 hipError_t launch_batch_group(const BatchArgs &A, int dtype, int kind, unsigned grid, int engine,
                               hipStream_t st);
 hipError_t launch_copyback(const BatchArgs &A, hipStream_t st);
+// Zero n request counters and set the start stamp to its maximum (before a run).
+hipError_t launch_stamp_reset(unsigned long long *req_cnt, uint64_t n, unsigned long long *t_start,
+                              hipStream_t st);
 
 }  // namespace mrg

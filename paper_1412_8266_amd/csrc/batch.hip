@@ -133,6 +133,7 @@ __global__ void __launch_bounds__(64) batch_kernel(BatchArgs A)
 #pragma unroll
         for (int i = 0; i < 18; ++i) m[i] = A.lane_tab[(k * 64 + lane) * 18 + i];
     }
+    if (A.t_start && lane == 0) atomicMin(A.t_start, (unsigned long long)wall_clock64());
     uint64_t next = blockIdx.x;  // static schedule: blockIdx.x + t * gridDim.x
     for (;;) {
         uint64_t item;
@@ -150,7 +151,21 @@ __global__ void __launch_bounds__(64) batch_kernel(BatchArgs A)
         const uint64_t local = item - A.prefix[r];
         if constexpr (KIND == kKindWave) wave_item<DT, G>(R, local, lds, lane, m, A);
         else row_item<DT, G>(R, local, lds, lane, A);
+        if (A.req_cnt && lane == 0) {
+            const unsigned long long done = atomicAdd(&A.req_cnt[r], 1ull) + 1ull;
+            if (done == A.prefix[r + 1] - A.prefix[r])
+                A.req_done[r] = (unsigned long long)wall_clock64();
+        }
     }
+}
+
+__global__ void __launch_bounds__(256) batch_stamp_reset_kernel(unsigned long long *req_cnt,
+                                                                uint64_t n,
+                                                                unsigned long long *t_start)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) req_cnt[i] = 0ull;
+    if (i == 0) *t_start = ~0ull;
 }
 
 // Entry e with cb_prefix[e] <= s < cb_prefix[e+1] (per-thread binary search).
@@ -202,6 +217,15 @@ hipError_t launch_batch_group(const BatchArgs &A, int dtype, int kind, unsigned 
     if (A.dynamic) hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(1), 0, st, A.counter);
     if (engine == 1) launch_group_g<GenF>(A, dtype, kind, grid, st);
     else launch_group_g<GenI>(A, dtype, kind, grid, st);
+    return hipGetLastError();
+}
+
+hipError_t launch_stamp_reset(unsigned long long *req_cnt, uint64_t n, unsigned long long *t_start,
+                              hipStream_t st)
+{
+    const uint64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(batch_stamp_reset_kernel, dim3((unsigned)(blocks ? blocks : 1)), dim3(256), 0,
+                       st, req_cnt, n, t_start);
     return hipGetLastError();
 }
 

@@ -57,6 +57,10 @@ hipError_t launch_grouped(const Grouped &g, const BatchReq *d_reqs, const uint64
         A.nreq = G.nreq;
         A.total_items = G.items;
         A.counter = d_counters + i;
+        if (base.req_cnt) {
+            A.req_cnt = base.req_cnt + G.req_off;
+            A.req_done = base.req_done + G.req_off;
+        }
         const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min(grid_cap, G.items));
         hipError_t e = launch_batch_group(A, G.dtype, G.kind, grid, engine, st);
         if (e != hipSuccess) return e;
@@ -84,6 +88,7 @@ struct mrg_batch_s {
     uint64_t *d_solo = nullptr;      // [nreq][2]: {0, items of request r}
     uint64_t *d_cb = nullptr;        // cb_prefix | cb_stream0 | cb_scratch0
     unsigned long long *d_counter = nullptr;  // one per group
+    unsigned long long *d_stamps = nullptr;   // [nreq] counts | [nreq] done stamps | start
     uint32_t *d_scratch = nullptr;
     uint64_t grid_cap = 0;
 
@@ -101,11 +106,11 @@ void free_plan(mrg_batch b)
     b->exec = nullptr;
     b->graph = nullptr;
     for (void *p : {(void *)b->d_reqs, (void *)b->d_prefix, (void *)b->d_solo, (void *)b->d_cb,
-                    (void *)b->d_counter, (void *)b->d_scratch})
+                    (void *)b->d_counter, (void *)b->d_stamps, (void *)b->d_scratch})
         if (p) (void)hipFree(p);
     b->d_reqs = nullptr;
     b->d_prefix = b->d_solo = b->d_cb = nullptr;
-    b->d_counter = nullptr;
+    b->d_counter = b->d_stamps = nullptr;
     b->d_scratch = nullptr;
 }
 
@@ -197,6 +202,8 @@ mrg_status build_plan(mrg_batch b)
     if ((st = upload(&b->d_cb, cb, "batch copy-back"))) return st;
     hipError_t e = hipMalloc((void **)&b->d_counter, 6 * sizeof(unsigned long long));
     if (e != hipSuccess) return set_error(MRG_ENOMEM, "hipMalloc(counters)");
+    e = hipMalloc((void **)&b->d_stamps, (2 * b->plan.reqs.size() + 1) * sizeof(unsigned long long));
+    if (e != hipSuccess) return set_error(MRG_ENOMEM, "hipMalloc(completion stamps)");
     if (b->scratch_slots) {
         e = hipMalloc((void **)&b->d_scratch, 6 * b->scratch_slots * sizeof(uint32_t));
         if (e != hipSuccess)
@@ -223,13 +230,19 @@ mrg::BatchArgs base_args(mrg_batch b)
     A.cb_scratch0 = b->d_cb + (ncb + 1) + ncb;
     A.n_cb = ncb;
     A.cb_slots = b->cb_prefix.back();
+    const uint64_t nr = b->plan.reqs.size();
+    A.req_cnt = b->d_stamps;
+    A.req_done = b->d_stamps + nr;
+    A.t_start = b->d_stamps + 2 * nr;
     return A;
 }
 
 hipError_t launch_all(mrg_batch b, hipStream_t st)
 {
     const mrg::BatchArgs A = base_args(b);
-    hipError_t e = mrg::launch_grouped(b->plan, b->d_reqs, b->d_prefix, b->d_counter, A,
+    hipError_t e = mrg::launch_stamp_reset(A.req_cnt, b->plan.reqs.size(), A.t_start, st);
+    if (e != hipSuccess) return e;
+    e = mrg::launch_grouped(b->plan, b->d_reqs, b->d_prefix, b->d_counter, A,
                                        b->grid_cap, b->engine, st);
     if (e == hipSuccess) e = mrg::launch_copyback(A, st);
     return e;
@@ -384,6 +397,7 @@ mrg_status mrg_batch_run_per_request(mrg_batch b, void *stream)
             A.nreq = 1;
             A.total_items = mrg::items_of(R);
             A.counter = b->d_counter;
+            A.req_cnt = A.req_done = A.t_start = nullptr;  // stamps belong to batch runs
             const unsigned grid =
                 (unsigned)std::max<uint64_t>(1, std::min(b->grid_cap, A.total_items));
             hipError_t e = mrg::launch_batch_group(A, (int)R.dtype, mrg::kind_of(R), grid,
@@ -394,6 +408,28 @@ mrg_status mrg_batch_run_per_request(mrg_batch b, void *stream)
                           MRG_STREAM_MAJOR, q.d_out, stream);
         }
         if (st) return st;
+    }
+    return MRG_OK;
+}
+
+mrg_status mrg_batch_request_times(mrg_batch b, void *stream, double *h_ms)
+{
+    if (!b || !h_ms) return set_error(MRG_EINVAL, "null argument");
+    const size_t nr = b->plan.reqs.size();
+    std::vector<unsigned long long> st(2 * nr + 1);
+    hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+    if (e == hipSuccess)
+        e = hipMemcpy(st.data(), b->d_stamps, st.size() * sizeof(unsigned long long),
+                      hipMemcpyDeviceToHost);
+    int khz = 0;
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, b->device);
+    if (e != hipSuccess) return hip_error(e, "reading completion stamps");
+    if (khz <= 0) return set_error(MRG_EHIP, "no wall clock rate");
+    for (size_t i = 0; i < b->reqs.size(); ++i) h_ms[i] = 0.0;
+    const unsigned long long t0 = st[2 * nr];
+    for (size_t r = 0; r < b->req_of.size(); ++r) {
+        const unsigned long long t = st[nr + b->plan.pos[r]];
+        h_ms[b->req_of[r]] = t >= t0 ? (double)(t - t0) / (double)khz : 0.0;
     }
     return MRG_OK;
 }

@@ -223,6 +223,31 @@ def test_graph_direct_and_per_request_agree(mg):
         s.close()
 
 
+def test_request_completion_times(mg):
+    import torch
+    say("request completion stamps")
+    rng = np.random.default_rng(SEED + 9)
+    rows, outs, specs, nstreams = make_plain(mg, rng, 60, 200, 40000, 6_000_000)
+    ss = mg.StreamSet(nstreams, master_seed=SEED + 9)
+    b = mg.Batch(ss, rows, mg.batch_config(segment_bytes=32 * 1024))
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for rep in range(2):
+        e0.record()
+        b.run()
+        e1.record()
+        torch.cuda.synchronize()
+        total = e0.elapsed_time(e1)
+        t = b.request_times()
+        assert t.shape == (len(rows),)
+        for (first, k, n, dt), ti in zip(specs, t):
+            if k and n:
+                assert 0 < ti <= total + 0.05, (ti, total)
+            else:
+                assert ti == 0
+    b.close()
+    ss.close()
+
+
 def test_autotune_restores_states_and_keeps_results(mg):
     say("autotune")
     rng = np.random.default_rng(SEED + 5)
