@@ -1,0 +1,129 @@
+/* Per-thread MRG32k3a streams inside user kernels (HIP, gfx950).
+ *
+ * The paper's generator object is built once per thread and drawn from with
+ * next() inside the user's own kernel (sec. 5, Listing 1), the streams having
+ * been placed on the host beforehand by jump-ahead (sec. 2.3, sec. 4.1).  This
+ * header gives that mode on top of the library's stream sets: create a set
+ * (mrg_streamset_create*), optionally jump it, read its device state planes
+ * with mrg_streamset_states_ptr and its size with mrg_streamset_info, then in
+ * a kernel
+ *
+ *     mrg::Stream<> s;
+ *     s.load(planes, n_streams, i);      // stream i of the set
+ *     float u = s.next_f32();            // ... as many draws as needed
+ *     s.store(planes, n_streams, i);     // continue there next time
+ *
+ * Draws are bit-identical to mrg_fill's: value k of stream i here is value k
+ * of row i of a stream-major fill started from the same state.  State words
+ * live in registers; the planes hold word c of stream i at planes[c * n + i],
+ * so loads and stores of consecutive streams by consecutive lanes coalesce.
+ * The library's own kernels are built on the same types.
+ *
+ * Include path: this directory (the header also pulls in mrg_arith.hpp). */
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "mrg_arith.hpp"
+
+namespace mrg {
+
+// Integer generator: lazy 32-bit words, v_mad_u64_u32 product-sums.  The
+// multipliers live in VGPRs so that each v_mad_u64_u32 can take the constant
+// addend K from an SGPR pair (one scalar operand per VOP3 instruction).
+struct GenI {
+    uint32_t a0, a1, a2, b0, b1, b2;  // lazy words, oldest first
+    uint32_t m13, m12, m23, m21;      // multipliers held in VGPRs
+
+    __device__ __forceinline__ void load(const uint32_t *w)
+    {
+        a0 = w[0]; a1 = w[1]; a2 = w[2]; b0 = w[3]; b1 = w[4]; b2 = w[5];
+        m13 = A13N; m12 = A12; m23 = A23N; m21 = A21;
+        asm volatile("" : "+v"(m13), "+v"(m12), "+v"(m23), "+v"(m21));
+    }
+    __device__ __forceinline__ void store(uint32_t *w) const
+    {
+        w[0] = canon1(a0); w[1] = canon1(a1); w[2] = canon1(a2);
+        w[3] = canon2(b0); w[4] = canon2(b1); w[5] = canon2(b2);
+    }
+    __device__ __forceinline__ uint32_t step()
+    {
+        const uint32_t p1 = next1(a0, a1, m13, m12);
+        const uint32_t p2 = next2(b0, b2, m23, m21);
+        a0 = a1; a1 = a2; a2 = p1;
+        b0 = b1; b1 = b2; b2 = p2;
+        return combine(p1, p2);
+    }
+    __device__ __forceinline__ uint32_t next_u32() { return step(); }
+    __device__ __forceinline__ float next_f32() { return to_f32(step()); }
+    __device__ __forceinline__ double next_f64() { return to_f64(step()); }
+};
+
+// Binary64 generator: near-canonical integer-valued doubles, five FP64 operations
+// per component per step.
+struct GenF {
+    double a0, a1, a2, b0, b1, b2;
+
+    __device__ __forceinline__ void load(const uint32_t *w)
+    {
+        a0 = w[0]; a1 = w[1]; a2 = w[2]; b0 = w[3]; b1 = w[4]; b2 = w[5];
+    }
+    __device__ __forceinline__ void store(uint32_t *w) const
+    {
+        w[0] = canonf(a0, M1D); w[1] = canonf(a1, M1D); w[2] = canonf(a2, M1D);
+        w[3] = canonf(b0, M2D); w[4] = canonf(b1, M2D); w[5] = canonf(b2, M2D);
+    }
+    __device__ __forceinline__ double step()
+    {
+        const double r1 = next1f(a0, a1);
+        const double r2 = next2f(b0, b2);
+        a0 = a1; a1 = a2; a2 = r1;
+        b0 = b1; b1 = b2; b2 = r2;
+        return combinef(r1, r2);
+    }
+    __device__ __forceinline__ uint32_t next_u32() { return (uint32_t)step(); }
+    __device__ __forceinline__ float next_f32() { return to_f32f(step()); }
+    __device__ __forceinline__ double next_f64() { return to_f64f(step()); }
+};
+
+__device__ __forceinline__ void load_state(const uint32_t *planes, uint64_t stride, uint64_t idx,
+                                           uint32_t *w)
+{
+#pragma unroll
+    for (int c = 0; c < 6; ++c) w[c] = planes[c * stride + idx];
+}
+
+__device__ __forceinline__ void store_state(uint32_t *planes, uint64_t stride, uint64_t idx,
+                                            const uint32_t *w)
+{
+#pragma unroll
+    for (int c = 0; c < 6; ++c) planes[c * stride + idx] = w[c];
+}
+
+// One stream drawn by one thread.  G = GenF (binary64 words, the default) or
+// GenI (32-bit integer words).
+template <class G = GenF>
+struct Stream {
+    G g;
+
+    // Stream i of a set whose six state planes of n_streams words start at planes.
+    __device__ __forceinline__ void load(const uint32_t *planes, uint64_t n_streams, uint64_t i)
+    {
+        uint32_t w[6];
+        load_state(planes, n_streams, i, w);
+        g.load(w);
+    }
+    // Write the state back (canonical words), e.g. to continue in a later launch.
+    __device__ __forceinline__ void store(uint32_t *planes, uint64_t n_streams, uint64_t i) const
+    {
+        uint32_t w[6];
+        g.store(w);
+        store_state(planes, n_streams, i, w);
+    }
+    // The next value as uint32 in [1, m1], as binary32 in (0, 1) or as binary64 in (0, 1).
+    __device__ __forceinline__ uint32_t next_u32() { return g.next_u32(); }
+    __device__ __forceinline__ float next_f32() { return g.next_f32(); }
+    __device__ __forceinline__ double next_f64() { return g.next_f64(); }
+};
+
+}  // namespace mrg

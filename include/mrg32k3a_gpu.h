@@ -100,7 +100,8 @@ mrg_status mrg_streamset_info(mrg_streamset ss, uint64_t *n_streams,
                               uint64_t *first_stream, uint32_t seed6[6]);
 
 /* Device pointer of the 6 state planes ([6][n_streams] uint32, plane c holds
- * word c of every stream).  Owned by the stream set; valid until destroy. */
+ * word c of every stream).  Owned by the stream set; valid until destroy.
+ * User kernels draw from these states with mrg::Stream (mrg32k3a_device.h). */
 mrg_status mrg_streamset_states_ptr(mrg_streamset ss, void **d_states);
 
 /* ---------------------------------------------------------------------- */

@@ -9,7 +9,7 @@
 #include <stdint.h>
 
 #include "kernels.h"
-#include "mrg_arith.hpp"
+#include "mrg32k3a_device.h"
 
 namespace mrg {
 
@@ -49,64 +49,6 @@ __device__ __forceinline__ void jump_global(const uint32_t *__restrict__ table, 
     }
 }
 
-// Integer generator: lazy 32-bit words, v_mad_u64_u32 product-sums.  The
-// multipliers live in VGPRs so that each v_mad_u64_u32 can take the constant
-// addend K from an SGPR pair (one scalar operand per VOP3 instruction).
-struct GenI {
-    uint32_t a0, a1, a2, b0, b1, b2;  // lazy words, oldest first
-    uint32_t m13, m12, m23, m21;      // multipliers held in VGPRs
-
-    __device__ __forceinline__ void load(const uint32_t *w)
-    {
-        a0 = w[0]; a1 = w[1]; a2 = w[2]; b0 = w[3]; b1 = w[4]; b2 = w[5];
-        m13 = A13N; m12 = A12; m23 = A23N; m21 = A21;
-        asm volatile("" : "+v"(m13), "+v"(m12), "+v"(m23), "+v"(m21));
-    }
-    __device__ __forceinline__ void store(uint32_t *w) const
-    {
-        w[0] = canon1(a0); w[1] = canon1(a1); w[2] = canon1(a2);
-        w[3] = canon2(b0); w[4] = canon2(b1); w[5] = canon2(b2);
-    }
-    __device__ __forceinline__ uint32_t step()
-    {
-        const uint32_t p1 = next1(a0, a1, m13, m12);
-        const uint32_t p2 = next2(b0, b2, m23, m21);
-        a0 = a1; a1 = a2; a2 = p1;
-        b0 = b1; b1 = b2; b2 = p2;
-        return combine(p1, p2);
-    }
-    __device__ __forceinline__ uint32_t next_u32() { return step(); }
-    __device__ __forceinline__ float next_f32() { return to_f32(step()); }
-    __device__ __forceinline__ double next_f64() { return to_f64(step()); }
-};
-
-// Binary64 generator: near-canonical integer-valued doubles, five FP64 operations
-// per component per step.
-struct GenF {
-    double a0, a1, a2, b0, b1, b2;
-
-    __device__ __forceinline__ void load(const uint32_t *w)
-    {
-        a0 = w[0]; a1 = w[1]; a2 = w[2]; b0 = w[3]; b1 = w[4]; b2 = w[5];
-    }
-    __device__ __forceinline__ void store(uint32_t *w) const
-    {
-        w[0] = canonf(a0, M1D); w[1] = canonf(a1, M1D); w[2] = canonf(a2, M1D);
-        w[3] = canonf(b0, M2D); w[4] = canonf(b1, M2D); w[5] = canonf(b2, M2D);
-    }
-    __device__ __forceinline__ double step()
-    {
-        const double r1 = next1f(a0, a1);
-        const double r2 = next2f(b0, b2);
-        a0 = a1; a1 = a2; a2 = r1;
-        b0 = b1; b1 = b2; b2 = r2;
-        return combinef(r1, r2);
-    }
-    __device__ __forceinline__ uint32_t next_u32() { return (uint32_t)step(); }
-    __device__ __forceinline__ float next_f32() { return to_f32f(step()); }
-    __device__ __forceinline__ double next_f64() { return to_f64f(step()); }
-};
-
 template <int DT> struct Elem;
 template <> struct Elem<0> { static constexpr int size = 4; };
 template <> struct Elem<1> { static constexpr int size = 4; };
@@ -139,20 +81,6 @@ __device__ __forceinline__ void put1(unsigned char *p, G &g)
     if constexpr (DT == 0) *(uint32_t *)p = g.next_u32();
     else if constexpr (DT == 1) *(float *)p = g.next_f32();
     else *(double *)p = g.next_f64();
-}
-
-__device__ __forceinline__ void load_state(const uint32_t *planes, uint64_t stride, uint64_t idx,
-                                           uint32_t *w)
-{
-#pragma unroll
-    for (int c = 0; c < 6; ++c) w[c] = planes[c * stride + idx];
-}
-
-__device__ __forceinline__ void store_state(uint32_t *planes, uint64_t stride, uint64_t idx,
-                                            const uint32_t *w)
-{
-#pragma unroll
-    for (int c = 0; c < 6; ++c) planes[c * stride + idx] = w[c];
 }
 
 template <int ES>

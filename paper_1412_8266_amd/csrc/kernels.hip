@@ -127,7 +127,9 @@ fill_sm_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t fi
 }
 
 // Interleaved output out[k * count + s]: consecutive lanes are consecutive
-// streams, so each step is one coalesced store per wave.
+// streams, so each step is one coalesced store per wave.  Written with the
+// per-thread stream object of the public device header, as a user kernel
+// would draw: one stream per thread, next() per value.
 template <int DT, class G>
 __global__ void __launch_bounds__(256)
 fill_il_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t first,
@@ -136,27 +138,23 @@ fill_il_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t fi
     constexpr int ES = Elem<DT>::size;
     const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= count) return;
-    const uint64_t idx = first + s;
-    uint32_t w[6];
-    load_state(planes, plane_stride, idx, w);
-    G g;
-    g.load(w);
+    Stream<G> rng;
+    rng.load(planes, plane_stride, first + s);
     unsigned char *p = out + s * ES;
     const uint64_t step = count * ES;
     uint64_t k = 0;
     for (; k + 4 <= n; k += 4) {
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            put1<DT>(p, g);
+            put1<DT>(p, rng.g);
             p += step;
         }
     }
     for (; k < n; ++k) {
-        put1<DT>(p, g);
+        put1<DT>(p, rng.g);
         p += step;
     }
-    g.store(w);
-    store_state(planes, plane_stride, idx, w);
+    rng.store(planes, plane_stride, first + s);
 }
 
 // Wave-per-stream stream-major fill: workgroups (one wave each) stride over

@@ -1,0 +1,52 @@
+"""The public device header (include/mrg32k3a_device.h) is self-contained: a
+user kernel that includes only it compiles for gfx950 (compile only, no GPU).
+Its draws are those of the interleaved fill, which is written with the same
+Stream type and checked against the oracle in the GPU parity tests."""
+import os
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HIPCC = "/opt/rocm/bin/hipcc"
+
+USER_KERNEL = r"""
+#include "mrg32k3a_device.h"
+
+// Each thread sums k uniforms of its own stream and continues it next launch.
+__global__ void mean_kernel(uint32_t *planes, uint64_t n_streams, int k, float *out)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_streams) return;
+    mrg::Stream<> s;
+    s.load(planes, n_streams, i);
+    float acc = 0.f;
+    for (int j = 0; j < k; ++j) acc += s.next_f32();
+    s.store(planes, n_streams, i);
+    out[i] = acc / k;
+}
+
+__global__ void int_kernel(uint32_t *planes, uint64_t n_streams, uint32_t *out)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_streams) return;
+    mrg::Stream<mrg::GenI> s;
+    s.load(planes, n_streams, i);
+    out[i] = s.next_u32();
+    out[n_streams + i] = (uint32_t)(s.next_f64() * 4294967296.0);
+    s.store(planes, n_streams, i);
+}
+"""
+
+
+@pytest.mark.skipif(not os.path.exists(HIPCC), reason="no hipcc")
+def test_user_kernel_compiles_with_public_header(tmp_path):
+    src = tmp_path / "user.hip"
+    src.write_text(USER_KERNEL)
+    out = tmp_path / "user.o"
+    subprocess.check_call([HIPCC, "--offload-arch=gfx950", "--offload-device-only", "-O3",
+                           "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
+                           "-packed-fp32-ops", "-Wno-unused-command-line-argument",
+                           "-I", os.path.join(ROOT, "include"), "-c", str(src), "-o", str(out)],
+                          stderr=subprocess.DEVNULL)
+    assert out.stat().st_size > 0

@@ -1,4 +1,4 @@
-"""The library's device arithmetic (csrc/mrg_arith.hpp), compiled for the host
+"""The library's device arithmetic (include/mrg_arith.hpp), compiled for the host
 with g++, against the CPU oracle.  Both formulations (32-bit integer with
 lazy residues, binary64 with centred residues) are stepped from random and
 boundary states and compared output by output; the combination and
@@ -17,7 +17,7 @@ from oracle import ref
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 SRC = os.path.join(ROOT, "tests", "host_arith", "arith_shim.cpp")
-INC = os.path.join(ROOT, "paper_1412_8266_amd", "csrc")
+INC = os.path.join(ROOT, "include")
 M1, M2 = oracle.M1, oracle.M2
 
 
