@@ -100,6 +100,49 @@ __device__ __forceinline__ void store_state(uint32_t *planes, uint64_t stride, u
     for (int c = 0; c < 6; ++c) planes[c * stride + idx] = w[c];
 }
 
+// Windowed jump tables (mrg_streamset_tables_ptr): T[c][w][d] = A_c^(d * 16^w)
+// mod m_c, row-major 3x3 uint32, c in {0,1}, w in [0, 48), d in [0, 16)
+// (d = 0: identity), so any exponent below 2^192 is at most 48 products per
+// component (sec. 2.3 jump-ahead).
+constexpr int kTableWindows = 48;
+constexpr int kTableWindowWords = 16 * 9;
+
+// Digit w (4 bits) of a 192-bit exponent given as 3 little-endian words.
+__device__ __forceinline__ uint32_t exp_digit(uint64_t e0, uint64_t e1, uint64_t e2, int w)
+{
+    const uint64_t word = w < 16 ? e0 : (w < 32 ? e1 : e2);
+    return (uint32_t)(word >> (4 * (w & 15))) & 15u;
+}
+
+// One past the highest window holding a nonzero digit (0 for e = 0).
+__device__ __forceinline__ int top_window(uint64_t e0, uint64_t e1, uint64_t e2)
+{
+    if (e2) return 32 + (67 - __clzll((long long)e2)) / 4;
+    if (e1) return 16 + (67 - __clzll((long long)e1)) / 4;
+    if (e0) return (67 - __clzll((long long)e0)) / 4;
+    return 0;
+}
+
+// st <- A^e st with the tables read from global memory (L2-resident), over
+// windows [w_lo, w_hi).  Windows whose digit is zero in every lane are
+// skipped, and the loop ends after the wave's highest nonzero digit; when e
+// is the same in every lane the table reads are uniform.
+__device__ __forceinline__ void jump_global(const uint32_t *__restrict__ table, uint64_t e0,
+                                            uint64_t e1, uint64_t e2, int w_lo, int w_hi,
+                                            uint32_t *st)
+{
+    const int top = top_window(e0, e1, e2);
+#pragma unroll 1
+    for (int w = w_lo; w < w_hi; ++w) {
+        if (!__any(w < top)) break;
+        const uint32_t d = exp_digit(e0, e1, e2, w);
+        if (!__any(d != 0u)) continue;
+        if (d == 0u) continue;  // this lane's identity (exec-masked)
+        matvec3<C1>(table + ((0 * kTableWindows + w) * 16 + d) * 9, st[0], st[1], st[2]);
+        matvec3<C2>(table + ((1 * kTableWindows + w) * 16 + d) * 9, st[3], st[4], st[5]);
+    }
+}
+
 // One stream drawn by one thread.  G = GenF (binary64 words, the default) or
 // GenI (32-bit integer words).
 template <class G = GenF>
@@ -119,6 +162,21 @@ struct Stream {
         uint32_t w[6];
         g.store(w);
         store_state(planes, n_streams, i, w);
+    }
+    // Move e = e0 + e1 * 2^64 + e2 * 2^128 values ahead (tables: the set's
+    // device jump tables).  Cheapest when e is the same in the whole wave.
+    __device__ __forceinline__ void jump(const uint32_t *tables, uint64_t e0, uint64_t e1 = 0,
+                                         uint64_t e2 = 0)
+    {
+        uint32_t w[6];
+        g.store(w);
+        jump_global(tables, e0, e1, e2, 0, kTableWindows, w);
+        g.load(w);
+    }
+    // Move to substream j of the current position: j * 2^76 values ahead (sec. 4.1).
+    __device__ __forceinline__ void substream(const uint32_t *tables, uint64_t j)
+    {
+        jump(tables, 0, j << 12, j >> 52);
     }
     // The next value as uint32 in [1, m1], as binary32 in (0, 1) or as binary64 in (0, 1).
     __device__ __forceinline__ uint32_t next_u32() { return g.next_u32(); }

@@ -104,6 +104,12 @@ mrg_status mrg_streamset_info(mrg_streamset ss, uint64_t *n_streams,
  * User kernels draw from these states with mrg::Stream (mrg32k3a_device.h). */
 mrg_status mrg_streamset_states_ptr(mrg_streamset ss, void **d_states);
 
+/* Device pointer of the windowed jump tables of the set's device (sec. 2.3
+ * jump-ahead): [2][48][16][9] uint32, entry (c, w, d) = A_c^(d * 16^w) mod m_c
+ * row-major.  Owned by the library; valid until the process ends.  User
+ * kernels pass it to mrg::Stream::jump / substream (mrg32k3a_device.h). */
+mrg_status mrg_streamset_tables_ptr(mrg_streamset ss, const void **d_tables);
+
 /* ---------------------------------------------------------------------- */
 /* Jump ahead (sec. 2.3 sequence splitting; sec. 4.1 substreams of 2^76)   */
 /* Streams [first, first+count) of the set (indices relative to the set).  */

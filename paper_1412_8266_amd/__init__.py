@@ -92,6 +92,17 @@ class StreamSet:
     def base_state(self):
         return _abi.mrg_streamset_info(self._h)[2]
 
+    @property
+    def states_ptr(self) -> int:
+        """Device address of the six state planes ([6][n] uint32), for user
+        kernels built on mrg::Stream (include/mrg32k3a_device.h)."""
+        return _abi.mrg_streamset_states_ptr(self._h)
+
+    @property
+    def tables_ptr(self) -> int:
+        """Device address of the windowed jump tables, for mrg::Stream::jump."""
+        return _abi.mrg_streamset_tables_ptr(self._h)
+
     def _range(self, first, count):
         if count is None:
             count = self.n_streams - first

@@ -55,6 +55,7 @@ _SIGS = {
     "mrg_streamset_destroy": [_P],
     "mrg_streamset_info": [_P, _PU64, _PU64, _PU32],
     "mrg_streamset_states_ptr": [_P, ctypes.POINTER(_P)],
+    "mrg_streamset_tables_ptr": [_P, ctypes.POINTER(_P)],
     "mrg_jump": [_P, _U64, _U64, _P, _P],
     "mrg_jump_uniform": [_P, _U64, _U64, _PU64, _P],
     "mrg_jump_substreams": [_P, _U64, _U64, _U64, _P],
@@ -201,6 +202,12 @@ def mrg_streamset_info(ss: int):
     seed = (ctypes.c_uint32 * 6)()
     _call("mrg_streamset_info", ss, ctypes.byref(n), ctypes.byref(first), seed)
     return n.value, first.value, list(seed)
+
+
+def mrg_streamset_tables_ptr(ss: int) -> int:
+    p = _P()
+    _call("mrg_streamset_tables_ptr", ss, ctypes.byref(p))
+    return int(p.value or 0)
 
 
 def mrg_streamset_states_ptr(ss: int) -> int:

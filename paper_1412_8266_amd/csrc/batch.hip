@@ -102,19 +102,17 @@ __device__ __forceinline__ void row_item(const BatchReq &R, uint64_t local, unsi
     const bool active = (uint64_t)lane < nrows;
     const uint64_t j = r0 + lane;
     const bool subs = R.flags & kReqSubstreams;
-    uint32_t w[6] = {1u, 1u, 1u, 1u, 1u, 1u};
-    if (active) load_state(A.planes, A.plane_stride, subs ? R.stream0 : R.stream0 + j, w);
-    if (subs) {
-        const uint64_t sub = active ? R.sub0 + j : 0;
-        jump_global(A.table, 0, sub << 12, sub >> 52, 19, kTableWindows, w);
+    // one stream per lane, as a user kernel draws (public Stream object)
+    Stream<G> s;
+    if (active) {
+        s.load(A.planes, A.plane_stride, subs ? R.stream0 : R.stream0 + j);
+    } else {
+        const uint32_t dummy[6] = {1u, 1u, 1u, 1u, 1u, 1u};
+        s.g.load(dummy);
     }
-    G g;
-    g.load(w);
-    rows_fill<DT, 128, G, false>(g, lds, lane, nrows, R.out + r0 * R.n * ES, R.n * ES, R.n);
-    if ((R.flags & kReqWriteBack) && active) {
-        g.store(w);
-        store_state(A.planes, A.plane_stride, R.stream0 + j, w);
-    }
+    if (subs) s.substream(A.table, active ? R.sub0 + j : 0);
+    rows_fill<DT, 128, G, false>(s.g, lds, lane, nrows, R.out + r0 * R.n * ES, R.n * ES, R.n);
+    if ((R.flags & kReqWriteBack) && active) s.store(A.planes, A.plane_stride, R.stream0 + j);
 }
 
 // One persistent kernel per (dtype, kind) group keeps each instantiation's

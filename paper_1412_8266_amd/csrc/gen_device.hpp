@@ -13,42 +13,6 @@
 
 namespace mrg {
 
-// Digit w (4 bits) of a 192-bit exponent given as 3 little-endian words.
-__device__ __forceinline__ uint32_t exp_digit(uint64_t e0, uint64_t e1, uint64_t e2, int w)
-{
-    const uint64_t word = w < 16 ? e0 : (w < 32 ? e1 : e2);
-    return (uint32_t)(word >> (4 * (w & 15))) & 15u;
-}
-
-// One past the highest window holding a nonzero digit (0 for e = 0).
-__device__ __forceinline__ int top_window(uint64_t e0, uint64_t e1, uint64_t e2)
-{
-    if (e2) return 32 + (67 - __clzll((long long)e2)) / 4;
-    if (e1) return 16 + (67 - __clzll((long long)e1)) / 4;
-    if (e0) return (67 - __clzll((long long)e0)) / 4;
-    return 0;
-}
-
-// st <- A^e st with the tables read from global memory (L2-resident), over
-// windows [w_lo, w_hi).  Windows whose digit is zero in every lane are
-// skipped, and the loop ends after the wave's highest nonzero digit; when e
-// is the same in every lane the table reads are uniform.
-__device__ __forceinline__ void jump_global(const uint32_t *__restrict__ table, uint64_t e0,
-                                            uint64_t e1, uint64_t e2, int w_lo, int w_hi,
-                                            uint32_t *st)
-{
-    const int top = top_window(e0, e1, e2);
-#pragma unroll 1
-    for (int w = w_lo; w < w_hi; ++w) {
-        if (!__any(w < top)) break;
-        const uint32_t d = exp_digit(e0, e1, e2, w);
-        if (!__any(d != 0u)) continue;
-        if (d == 0u) continue;  // this lane's identity (exec-masked)
-        matvec3<C1>(table + ((0 * kTableWindows + w) * 16 + d) * 9, st[0], st[1], st[2]);
-        matvec3<C2>(table + ((1 * kTableWindows + w) * 16 + d) * 9, st[3], st[4], st[5]);
-    }
-}
-
 template <int DT> struct Elem;
 template <> struct Elem<0> { static constexpr int size = 4; };
 template <> struct Elem<1> { static constexpr int size = 4; };

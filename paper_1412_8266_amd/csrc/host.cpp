@@ -398,6 +398,17 @@ mrg_status mrg_streamset_states_ptr(mrg_streamset ss, void **d_states)
     return MRG_OK;
 }
 
+mrg_status mrg_streamset_tables_ptr(mrg_streamset ss, const void **d_tables)
+{
+    mrg_status st = check_set(ss);
+    if (st) return st;
+    if (!d_tables) return set_error(MRG_EINVAL, "null argument");
+    DevCtx *ctx;
+    if ((st = device_ctx(ss->device, &ctx))) return st;
+    *d_tables = ctx->d_table;
+    return MRG_OK;
+}
+
 mrg_status mrg_jump(mrg_streamset ss, uint64_t first, uint64_t count, const uint64_t *d_exp,
                     void *stream)
 {

@@ -3,12 +3,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "mrg32k3a_device.h"  // table layout (kTableWindows, kTableWindowWords)
+
 namespace mrg {
 
-// Windowed jump tables: T[c][w][d] = A_c^(d * 16^w) mod m_c, row-major 3x3,
-// for c in {0,1}, w in [0, 48), d in [0, 16) (d = 0: identity).
-constexpr int kTableWindows = 48;
-constexpr int kTableWindowWords = 16 * 9;
 constexpr int kTableWords = 2 * kTableWindows * kTableWindowWords;
 
 struct InitSeed { uint32_t w[6]; };

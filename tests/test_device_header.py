@@ -26,15 +26,18 @@ __global__ void mean_kernel(uint32_t *planes, uint64_t n_streams, int k, float *
     out[i] = acc / k;
 }
 
-__global__ void int_kernel(uint32_t *planes, uint64_t n_streams, uint32_t *out)
+// Thread i draws from substream i of stream 0, then jumps 1000 values.
+__global__ void int_kernel(const uint32_t *planes, uint64_t n_streams, const uint32_t *tables,
+                           uint32_t *out)
 {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n_streams) return;
     mrg::Stream<mrg::GenI> s;
-    s.load(planes, n_streams, i);
+    s.load(planes, n_streams, 0);
+    s.substream(tables, i);
+    s.jump(tables, 1000);
     out[i] = s.next_u32();
     out[n_streams + i] = (uint32_t)(s.next_f64() * 4294967296.0);
-    s.store(planes, n_streams, i);
 }
 """
 
