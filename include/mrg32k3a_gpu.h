@@ -279,7 +279,7 @@ typedef struct {
     uint64_t arena_bytes;   /* device output arena: the admission cap */
     uint32_t max_inflight;  /* HIP streams, i.e. groups in flight (0: 8; at most 64) */
     uint32_t max_batch;     /* requests per group (0: 4096) */
-    uint32_t waves_per_cu;  /* persistent workgroups per CU per group (0: 16) */
+    uint32_t waves_per_cu;  /* persistent workgroups per CU per tick kernel (0: 8) */
     uint32_t auto_release;  /* 1: free each output when it completes (throughput runs) */
 } mrg_server_config;
 

@@ -288,7 +288,7 @@ mrg_status mrg_server_create(mrg_server *out, const mrg_server_config *cfg_in)
     if (!cfg.arena_bytes) return set_error(MRG_ERANGE, "arena_bytes must be > 0");
     if (!cfg.max_inflight) cfg.max_inflight = 8;
     if (!cfg.max_batch) cfg.max_batch = 4096;
-    if (!cfg.waves_per_cu) cfg.waves_per_cu = 16;
+    if (!cfg.waves_per_cu) cfg.waves_per_cu = 8;
     if (cfg.max_inflight > 64) return set_error(MRG_ERANGE, "max_inflight above 64");
     auto *s = new (std::nothrow) mrg_server_s;
     if (!s) return set_error(MRG_ENOMEM, "host allocation");
