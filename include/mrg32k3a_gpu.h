@@ -143,8 +143,10 @@ mrg_status mrg_jump_substreams(mrg_streamset ss, uint64_t first, uint64_t count,
  *   layout MRG_STREAM_MAJOR: d_out[s * n_per_stream + k] (a [count, n] array)
  *   layout MRG_INTERLEAVED : d_out[k * count + s]        (a [n, count] array)
  * d_out must hold count * n_per_stream elements of the dtype (4 bytes for
- * MRG_U32/MRG_F32, 8 for MRG_F64) and be aligned to the element size; 16-byte
- * alignment enables the vector store path.  n_per_stream == 0 or count == 0
+ * MRG_U32/MRG_F32, 8 for MRG_F64) and be aligned to the element size.  Any
+ * row start works; when d_out and the row length in bytes are multiples of
+ * 128, several streams share a wave (config "coop_lanes").  n_per_stream == 0
+ * or count == 0
  * is a no-op.  Errors: MRG_EINVAL (null d_out, bad dtype/layout,
  * misaligned), MRG_ERANGE (range outside the set). */
 mrg_status mrg_fill(mrg_streamset ss, uint64_t first, uint64_t count,
@@ -175,10 +177,11 @@ mrg_status mrg_set_states(mrg_streamset ss, uint64_t first, uint64_t count,
  * mrg_fill(set, first, count, n_per_stream, dtype, MRG_STREAM_MAJOR, d_out):
  * streams first .. first+count-1 of the set, advanced by n_per_stream.
  * With MRG_REQ_SUBSTREAMS, `first` names the one stream and count substreams
- * starting at substream0 are generated.  d_out is device memory holding
+ * starting at substream0 are generated (substream0 + count - 1 must fit in
+ * 64 bits, else MRG_ERANGE).  d_out is device memory holding
  * count * n_per_stream elements of dtype, stream-major, aligned to the
- * element size (16 bytes enables vector stores).  Requests with count or
- * n_per_stream equal to 0 are skipped. */
+ * element size (rows starting on 128-byte lines are written fastest).
+ * Requests with count or n_per_stream equal to 0 are skipped. */
 typedef struct {
     uint64_t first;
     uint64_t count;

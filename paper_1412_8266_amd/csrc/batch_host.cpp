@@ -286,7 +286,7 @@ mrg_status validate(mrg_streamset ss, const mrg_request *reqs, uint64_t n)
         if (q.flags & MRG_REQ_SUBSTREAMS) {
             if (q.first >= ss->n)
                 return set_error(MRG_ERANGE, "request %llu: stream outside the set", (unsigned long long)i);
-            if (q.count - 1 > ((uint64_t)1 << 62) - q.substream0)
+            if (q.count - 1 > UINT64_MAX - q.substream0)  // substream0 + count - 1 < 2^64
                 return set_error(MRG_ERANGE, "request %llu: substream index overflow",
                                  (unsigned long long)i);
         } else {
