@@ -267,11 +267,12 @@ mrg_status mrg_batch_destroy(mrg_batch b);
 /* Each client c owns global stream first_stream + c (its state stays on the
  * device and never changes) and a substream cursor: a request of client c
  * for k streams gets the client's next k substreams (sec. 4.1), assigned at
- * admission.  A scheduler thread admits queued requests in arrival order
- * while the output arena has room, launches every admitted group as one
- * persistent batch launch on the next of max_inflight HIP streams (groups
- * overlap on the device), and retires them when their completion events
- * fire.  A request's output is a [k, n] stream-major array of its dtype in
+ * admission.  A scheduler thread admits queued requests in arrival order,
+ * separately for small and large ones (big_request_bytes), while the output
+ * arena has room, launches every admitted group as one persistent batch
+ * launch on the next free HIP stream of its class (max_inflight streams, a
+ * quarter of them for large requests; groups overlap on the device), and
+ * retires them when their completion events fire.  A request's output is a [k, n] stream-major array of its dtype in
  * the arena, identical to generating that request alone. */
 typedef struct mrg_server_s *mrg_server;
 
@@ -284,6 +285,11 @@ typedef struct {
     uint32_t max_batch;     /* requests per group (0: 4096) */
     uint32_t waves_per_cu;  /* persistent workgroups per CU per tick kernel (0: 8) */
     uint32_t auto_release;  /* 1: free each output when it completes (throughput runs) */
+    uint32_t pad;
+    uint64_t big_request_bytes;  /* requests of at least this many output bytes queue
+                                    apart and run on a quarter of the streams, so that
+                                    smaller ones never share a tick with them
+                                    (0: 64 MiB; UINT64_MAX: one class) */
 } mrg_server_config;
 
 typedef struct {

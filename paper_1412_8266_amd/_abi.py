@@ -107,7 +107,8 @@ class mrg_server_config(ctypes.Structure):
     _fields_ = [("n_clients", ctypes.c_uint64), ("first_stream", ctypes.c_uint64),
                 ("master_seed", ctypes.c_uint64), ("arena_bytes", ctypes.c_uint64),
                 ("max_inflight", ctypes.c_uint32), ("max_batch", ctypes.c_uint32),
-                ("waves_per_cu", ctypes.c_uint32), ("auto_release", ctypes.c_uint32)]
+                ("waves_per_cu", ctypes.c_uint32), ("auto_release", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32), ("big_request_bytes", ctypes.c_uint64)]
 
 
 class mrg_server_result(ctypes.Structure):
@@ -348,9 +349,10 @@ def mrg_batch_destroy(b: int) -> None:
 
 
 def mrg_server_create(n_clients, first_stream, master_seed, arena_bytes, max_inflight=0,
-                      max_batch=0, waves_per_cu=0, auto_release=0) -> int:
+                      max_batch=0, waves_per_cu=0, auto_release=0, big_request_bytes=0) -> int:
     cfg = mrg_server_config(n_clients, first_stream, master_seed & ((1 << 64) - 1), arena_bytes,
-                            max_inflight, max_batch, waves_per_cu, auto_release)
+                            max_inflight, max_batch, waves_per_cu, auto_release, 0,
+                            big_request_bytes)
     h = _P()
     _call("mrg_server_create", ctypes.byref(h), ctypes.byref(cfg))
     return h.value

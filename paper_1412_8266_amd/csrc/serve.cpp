@@ -6,7 +6,9 @@
 // for k streams of n values gets the client's next k substreams (sec. 4.1:
 // substreams of 2^76 values), so requests of one client never depend on each
 // other and can run concurrently.  A scheduler thread admits queued requests
-// in arrival order while the output arena has room (first fit), launches each
+// in arrival order within two size classes (large requests queue apart and
+// run on their own quarter of the HIP streams) while the output arena has room
+// (first fit), launches each
 // admitted group ("tick": one persistent batch kernel per dtype and item kind)
 // on the next of several HIP streams -- ticks overlap on the device -- and
 // retires ticks by polling their completion events.  Latency is measured from submission to the
@@ -122,11 +124,12 @@ struct mrg_server_s {
     Arena *arena = nullptr;
     std::vector<uint64_t> cursor;  // next substream of each client
     std::vector<Slot> slots;
-    size_t next_slot = 0;
+    size_t next_slot[2] = {0, 0};  // round robin within each slot pool
+    size_t n_small_slots = 0;      // slots [0, n) serve small requests, the rest large ones
 
     std::mutex mu;
     std::condition_variable cv;
-    std::deque<Req> pending;
+    std::deque<Req> pending[2];    // queued small (0) and large (1) requests
     std::deque<Req> done;             // finished, not yet taken by poll
     std::map<uint64_t, Req> held;     // finished, output held until release
     uint64_t next_ticket = 1;
@@ -229,43 +232,50 @@ void scheduler(mrg_server s)
             progressed = true;
         }
         if (s->stop && s->inflight_reqs == 0) break;
-        // admit into the next free slot
-        Slot *free_slot = nullptr;
-        for (size_t i = 0; i < s->slots.size(); ++i) {
-            Slot &c = s->slots[(s->next_slot + i) % s->slots.size()];
-            if (!c.busy) {
-                free_slot = &c;
-                s->next_slot = (s->next_slot + i + 1) % s->slots.size();
-                break;
-            }
-        }
-        if (free_slot && !s->stop) {
-            while (!s->pending.empty() && free_slot->reqs.size() < s->cfg.max_batch) {
-                Req &r = s->pending.front();
-                uint64_t off;
-                if (!s->arena->alloc(r.bytes, &off)) break;  // head waits for memory
-                r.offset = off;
-                r.sub0 = s->cursor[r.client];
-                s->cursor[r.client] += r.k;
-                r.t_admit = now_s();
-                free_slot->reqs.push_back(r);
-                s->pending.pop_front();
-            }
-            if (!free_slot->reqs.empty()) {
-                s->inflight_reqs += free_slot->reqs.size();
-                ++s->ticks;
-                // the slot belongs to this thread alone: launch without the
-                // lock, so that submissions are not held up by the launches
-                lk.unlock();
-                const mrg_status st = launch_tick(s, *free_slot);
-                const std::string err = st ? mrg_last_error() : "";
-                lk.lock();
-                if (st) {
-                    s->worker_status = st;
-                    s->worker_error = err;
-                    s->stop = true;
+        // admit each size class into the next free slot of its own pool, so
+        // that small requests never wait in a tick behind a large one
+        for (int cls = 0; cls < 2 && !s->stop; ++cls) {
+            const size_t lo = cls ? s->n_small_slots : 0;
+            const size_t pool = cls ? s->slots.size() - s->n_small_slots : s->n_small_slots;
+            Slot *free_slot = nullptr;
+            for (size_t i = 0; i < pool; ++i) {
+                const size_t at = (s->next_slot[cls] + i) % pool;
+                Slot &c = s->slots[lo + at];
+                if (!c.busy) {
+                    free_slot = &c;
+                    s->next_slot[cls] = (at + 1) % pool;
+                    break;
                 }
-                progressed = true;
+            }
+            if (free_slot) {
+                std::deque<Req> &q = s->pending[cls];
+                while (!q.empty() && free_slot->reqs.size() < s->cfg.max_batch) {
+                    Req &r = q.front();
+                    uint64_t off;
+                    if (!s->arena->alloc(r.bytes, &off)) break;  // head waits for memory
+                    r.offset = off;
+                    r.sub0 = s->cursor[r.client];
+                    s->cursor[r.client] += r.k;
+                    r.t_admit = now_s();
+                    free_slot->reqs.push_back(r);
+                    q.pop_front();
+                }
+                if (!free_slot->reqs.empty()) {
+                    s->inflight_reqs += free_slot->reqs.size();
+                    ++s->ticks;
+                    // the slot belongs to this thread alone: launch without the
+                    // lock, so that submissions are not held up by the launches
+                    lk.unlock();
+                    const mrg_status st = launch_tick(s, *free_slot);
+                    const std::string err = st ? mrg_last_error() : "";
+                    lk.lock();
+                    if (st) {
+                        s->worker_status = st;
+                        s->worker_error = err;
+                        s->stop = true;
+                    }
+                    progressed = true;
+                }
             }
         }
         if (!progressed) {
@@ -289,6 +299,7 @@ mrg_status mrg_server_create(mrg_server *out, const mrg_server_config *cfg_in)
     if (!cfg.max_inflight) cfg.max_inflight = 8;
     if (!cfg.max_batch) cfg.max_batch = 4096;
     if (!cfg.waves_per_cu) cfg.waves_per_cu = 8;
+    if (!cfg.big_request_bytes) cfg.big_request_bytes = 64ull << 20;
     if (cfg.max_inflight > 64) return set_error(MRG_ERANGE, "max_inflight above 64");
     auto *s = new (std::nothrow) mrg_server_s;
     if (!s) return set_error(MRG_ENOMEM, "host allocation");
@@ -316,6 +327,10 @@ mrg_status mrg_server_create(mrg_server *out, const mrg_server_config *cfg_in)
     s->arena = new Arena(cfg.arena_bytes);
     s->cursor.assign(cfg.n_clients, 0);
     s->slots.resize(cfg.max_inflight);
+    // a quarter of the slots (at least one) for large requests, unless one class
+    s->n_small_slots = cfg.big_request_bytes == UINT64_MAX || cfg.max_inflight < 2
+                           ? cfg.max_inflight
+                           : cfg.max_inflight - std::max<uint32_t>(1, cfg.max_inflight / 4);
     for (Slot &slot : s->slots) {
         e = hipStreamCreateWithFlags(&slot.stream, hipStreamNonBlocking);
         if (e == hipSuccess) e = hipEventCreateWithFlags(&slot.done, hipEventDisableTiming);
@@ -364,7 +379,8 @@ mrg_status mrg_server_submit(mrg_server s, uint64_t client, uint64_t n_streams,
         std::lock_guard<std::mutex> lk(s->mu);
         if (s->stop) return set_error(MRG_EHIP, "server stopped: %s", s->worker_error.c_str());
         r.ticket = s->next_ticket++;
-        s->pending.push_back(r);
+        s->pending[r.bytes >= s->cfg.big_request_bytes && s->n_small_slots < s->slots.size()]
+            .push_back(r);
     }
     s->cv.notify_one();
     if (ticket) *ticket = r.ticket;
@@ -430,7 +446,7 @@ mrg_status mrg_server_stats(mrg_server s, mrg_server_stats_t *st)
 {
     if (!s || !st) return set_error(MRG_EINVAL, "null argument");
     std::lock_guard<std::mutex> lk(s->mu);
-    st->pending = s->pending.size();
+    st->pending = s->pending[0].size() + s->pending[1].size();
     st->inflight = s->inflight_reqs;
     st->completed = s->completed;
     st->ticks = s->ticks;
@@ -449,7 +465,8 @@ mrg_status mrg_server_drain(mrg_server s, double timeout_s)
         {
             std::lock_guard<std::mutex> lk(s->mu);
             if (s->worker_status) return s->worker_status;
-            if (s->pending.empty() && s->inflight_reqs == 0) return MRG_OK;
+            if (s->pending[0].empty() && s->pending[1].empty() && s->inflight_reqs == 0)
+                return MRG_OK;
             // nothing in flight but the head still queued: its memory is held
             // by outputs that only mrg_server_release can free
             if (s->inflight_reqs == 0 && !s->held.empty() && now_s() > t_end - timeout_s + 0.05)
@@ -501,7 +518,8 @@ mrg_status mrg_server_destroy(mrg_server s)
     {
         std::lock_guard<std::mutex> lk(s->mu);
         s->stop = true;
-        s->pending.clear();
+        s->pending[0].clear();
+        s->pending[1].clear();
     }
     s->cv.notify_one();
     if (s->worker.joinable()) s->worker.join();

@@ -25,10 +25,10 @@ class Server:
 
     def __init__(self, n_clients: int, master_seed: int, arena_bytes: int, first_stream: int = 0,
                  max_inflight: int = 0, max_batch: int = 0, waves_per_cu: int = 0,
-                 auto_release: bool = False):
+                 auto_release: bool = False, big_request_bytes: int = 0):
         self._h = _abi.mrg_server_create(n_clients, first_stream, master_seed, arena_bytes,
                                          max_inflight, max_batch, waves_per_cu,
-                                         1 if auto_release else 0)
+                                         1 if auto_release else 0, big_request_bytes)
         self.auto_release = auto_release
 
     def submit(self, client: int, n_streams: int, n_per_stream: int, dtype: int) -> int:
