@@ -50,14 +50,16 @@ def expected(base, first_stream, rec):
     return oracle.fill(starts, n, int(rec["dtype"]))[0]
 
 
-def test_mix_equals_oracle_and_alone(mg):
+@pytest.mark.parametrize("big", [0, 64 << 10], ids=["one-class", "two-classes"])
+def test_mix_equals_oracle_and_alone(mg, big):
     import torch
     from paper_1412_8266_amd.serve import Server
-    say("serve mix")
+    say("serve mix", big)
     base = oracle.seed_from_master(SEED)
     first = 1000
     rng = np.random.default_rng(SEED)
-    srv = Server(64, SEED, 256 << 20, first_stream=first, max_inflight=3, max_batch=16)
+    srv = Server(64, SEED, 256 << 20, first_stream=first, max_inflight=3, max_batch=16,
+                 big_request_bytes=big)
     subs = []
     for i in range(150):
         c = int(rng.integers(0, 64))
@@ -67,11 +69,15 @@ def test_mix_equals_oracle_and_alone(mg):
         subs.append(srv.submit(c, k, n, dt))
     recs = wait_all(srv, len(subs))
     assert sorted(int(t) for t in recs["ticket"]) == sorted(subs)
-    # cursors: each client's requests take consecutive substreams in ticket order
+    # cursors: each client's requests take consecutive, disjoint runs of
+    # substreams (in admission order, which size classes may reorder)
     for c in np.unique(recs["client"]):
-        r = np.sort(recs[recs["client"] == c], order="ticket")
+        r = np.sort(recs[recs["client"] == c], order="substream0")
         assert int(r["substream0"][0]) == 0
         assert np.array_equal(r["substream0"][1:], np.cumsum(r["n_streams"])[:-1])
+    if big:
+        nb = recs["n_streams"] * recs["n_per_stream"] * np.where(recs["dtype"] == 2, 8, 4)
+        assert (nb >= big).any() and (nb < big).any()  # both classes ran
     # a client set for running single requests alone through the batch kernel
     ss = mg.StreamSet(64, seed=[int(x) for x in base], first_stream=first)
     for rec in recs[:: max(1, len(recs) // 40)]:
