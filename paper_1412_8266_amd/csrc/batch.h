@@ -82,7 +82,7 @@ struct Grouped {
     };
     std::vector<BatchReq> reqs;
     std::vector<uint64_t> prefix;
-    std::vector<Group> groups;   // non-empty groups only
+    std::vector<Group> groups;   // non-empty groups, least output first (launch order)
     std::vector<uint32_t> pos;   // input request i -> index in reqs
     uint64_t total_items = 0;
 };

@@ -43,6 +43,24 @@ void group_requests(const std::vector<BatchReq> &in, Grouped *out)
                 out->prefix.pop_back();
             }
         }
+    // launch the groups with the least output first (shortest-job-first
+    // keeps the completion times of most requests low; the run's end does
+    // not move)
+    std::vector<uint64_t> bytes(out->groups.size(), 0);
+    for (size_t i = 0; i < out->groups.size(); ++i) {
+        const Grouped::Group &G = out->groups[i];
+        for (uint32_t r = G.req_off; r < G.req_off + G.nreq; ++r) {
+            const BatchReq &R = out->reqs[r];
+            bytes[i] += R.k * R.n * (R.dtype == 2 ? 8 : 4);
+        }
+    }
+    std::vector<size_t> order(out->groups.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t a, size_t b) { return bytes[a] < bytes[b]; });
+    std::vector<Grouped::Group> sorted;
+    for (size_t i : order) sorted.push_back(out->groups[i]);
+    out->groups.swap(sorted);
 }
 
 hipError_t launch_grouped(const Grouped &g, const BatchReq *d_reqs, const uint64_t *d_prefix,
