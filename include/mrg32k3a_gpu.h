@@ -282,7 +282,7 @@ typedef struct {
     uint64_t master_seed;   /* base state via mrg_seed_from_master */
     uint64_t arena_bytes;   /* device output arena: the admission cap */
     uint32_t max_inflight;  /* HIP streams, i.e. groups in flight (0: 8; at most 64) */
-    uint32_t max_batch;     /* requests per group (0: 4096) */
+    uint32_t max_batch;     /* requests per group (0: 4096; at most 2^20) */
     uint32_t waves_per_cu;  /* persistent workgroups per CU per tick kernel (0: 8) */
     uint32_t auto_release;  /* 1: free each output when it completes (throughput runs) */
     uint32_t pad;

@@ -301,6 +301,7 @@ mrg_status mrg_server_create(mrg_server *out, const mrg_server_config *cfg_in)
     if (!cfg.waves_per_cu) cfg.waves_per_cu = 8;
     if (!cfg.big_request_bytes) cfg.big_request_bytes = 64ull << 20;
     if (cfg.max_inflight > 64) return set_error(MRG_ERANGE, "max_inflight above 64");
+    if (cfg.max_batch > (1u << 20)) return set_error(MRG_ERANGE, "max_batch above 2^20");
     auto *s = new (std::nothrow) mrg_server_s;
     if (!s) return set_error(MRG_ENOMEM, "host allocation");
     s->cfg = cfg;
