@@ -162,3 +162,44 @@ def test_trace_replay_and_errors(mg):
     with pytest.raises(mg.MRGError):
         srv.submit(0, 1 << 20, 1 << 20, 0)  # larger than the arena
     srv.close()
+
+
+def test_c5_shaped_trace_sampled(mg):
+    """The first 0.2 s of the C5 arrivals (50,000 clients, sizes as C4, 64 GiB
+    arena) submitted at once, outputs held until the poll loop releases them.
+    Every request finishes; sampled requests (first and last substream) equal
+    the oracle; the arena drains to zero."""
+    from paper_1412_8266_amd import workloads as wl
+    from paper_1412_8266_amd.serve import Server
+    say("serve C5-shaped")
+    arr = wl.c5_arrivals()
+    keep = arr.t < 0.2
+    k, n, dt = arr.req.n_streams[keep], arr.req.length[keep], arr.req.dtype[keep]
+    client = arr.client[keep]
+    base = oracle.seed_from_master(wl.MASTER_SEED)
+    srv = Server(wl.C5_CLIENTS, wl.MASTER_SEED, wl.C5_ARENA_BYTES)
+    tickets = [srv.submit(int(c), int(a), int(b), int(d)) for c, a, b, d in zip(client, k, n, dt)]
+    sample = set(tickets[::40])
+    kept, done = [], 0
+    t_end = time.time() + 120
+    while done < len(tickets):
+        for rec in srv.poll():
+            done += 1
+            nbytes = int(rec["n_streams"]) * int(rec["n_per_stream"]) * (8 if rec["dtype"] == 2 else 4)
+            if int(rec["ticket"]) in sample and int(rec["n_per_stream"]) <= (1 << 18) \
+                    and nbytes <= (64 << 20):
+                kept.append((rec.copy(), srv.output(rec)))
+            srv.release(int(rec["ticket"]))
+        assert time.time() < t_end, "requests did not finish"
+        time.sleep(0.001)
+    assert srv.stats()["arena_used"] == 0
+    assert len(kept) >= 20
+    for rec, got in kept:
+        c, kk, nn, d = int(rec["client"]), int(rec["n_streams"]), int(rec["n_per_stream"]), \
+            int(rec["dtype"])
+        s0 = oracle.stream_start(base, c)
+        for j in sorted({0, kk - 1}):
+            st = oracle.jump(s0, (int(rec["substream0"]) + j) << 76)[None, :]
+            want = oracle.fill(st, nn, d)[0][0]
+            assert np.array_equal(got[j].view(np.uint8), want.view(np.uint8)), (rec, j)
+    srv.close()
