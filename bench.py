@@ -232,6 +232,13 @@ def serving(mg, wl, seconds, speed=1.0):
     }
 
 
+def coop_lanes_used(mg, row_bytes):
+    """Lanes per stream of the wave-per-stream fill for rows of row_bytes: the
+    configured value, or the library's automatic choice (16 under 64 KiB)."""
+    cfg = mg.mrg_config_get("coop_lanes")
+    return cfg if cfg else (64 if row_bytes >= 65536 else 16)
+
+
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -321,7 +328,7 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": COUNTER_TRAFFIC,
-            "kernel": ("fill_coop_kernel<u32, %d lanes per stream>" % mg.mrg_config_get("coop_lanes"))
+            "kernel": ("fill_coop_kernel<u32, %d lanes per stream>" % coop_lanes_used(mg, n * 4))
                       if n >= 2048 and mg.mrg_config_get("strategy") != 1
                       else "fill_sm_kernel<u32>",
             "alg_bytes_per_launch": alg_bytes,

@@ -143,10 +143,9 @@ mrg_status mrg_jump_substreams(mrg_streamset ss, uint64_t first, uint64_t count,
  *   layout MRG_STREAM_MAJOR: d_out[s * n_per_stream + k] (a [count, n] array)
  *   layout MRG_INTERLEAVED : d_out[k * count + s]        (a [n, count] array)
  * d_out must hold count * n_per_stream elements of the dtype (4 bytes for
- * MRG_U32/MRG_F32, 8 for MRG_F64) and be aligned to the element size.  Any
- * row start works; when d_out and the row length in bytes are multiples of
- * 128, several streams share a wave (config "coop_lanes").  n_per_stream == 0
- * or count == 0
+ * MRG_U32/MRG_F32, 8 for MRG_F64) and be aligned to the element size (any
+ * row start works: each row is written in whole 128-byte lines after its
+ * first line boundary).  n_per_stream == 0 or count == 0
  * is a no-op.  Errors: MRG_EINVAL (null d_out, bad dtype/layout,
  * misaligned), MRG_ERANGE (range outside the set). */
 mrg_status mrg_fill(mrg_streamset ss, uint64_t first, uint64_t count,
@@ -386,8 +385,8 @@ mrg_status mrg_state_check(const uint32_t state6[6]);
  *                unit, each looping over stream groups (0 = one workgroup
  *                per group, the default), 0 .. 1024;
  *   "coop_lanes" wave-per-stream fill: lanes per stream, 64, 32, 16 or 8
- *                (default 16: 64/coop_lanes streams share a wave; used when
- *                every row starts on a 128-byte boundary, else 64).
+ *                (64/coop_lanes streams share a wave), or 0 (the default:
+ *                16 for rows under 64 KiB, else 64).
  * Unknown keys or values: MRG_EINVAL.  Takes effect for later launches. */
 mrg_status mrg_config_set(const char *key, int64_t value);
 mrg_status mrg_config_get(const char *key, int64_t *value);

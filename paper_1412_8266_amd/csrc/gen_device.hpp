@@ -190,21 +190,23 @@ __device__ __forceinline__ void rows_fill(G &g, unsigned char *lds, int lane, ui
 // (lane l serves stream l / GL as its member g = l % GL).  Stream t of the
 // wave is written at srow + t * row_stride + v * ES; only streams t < nsv
 // are written.  Each lane's w holds its stream's state at v0 (the same in
-// the GL lanes of a stream) and receives the state at v1.
+// the GL lanes of a stream) and receives the state at v1 (want_end), else
+// some state the caller must not use.
 //
-// With GL = 64 the values up to the first 128-byte line boundary (the head,
-// fewer than 128 / ES) come first: lane i < head writes value v0 + i from
-// A^i applied to the state (head_tab: the lane's A^lane), and the state moves
-// to lane `head`'s.  With GL < 64 every row must start on a line boundary.
-// The rest is cut into chunks of GL*L values; member g generates the L
-// consecutive values [g*L, g*L + L) of each chunk starting from A^(g*L)
-// applied to the chunk's first state (m: the lane's 18-word matrix pair), and
-// the next chunk starts where member GL-1 ended (sequence splitting, sec.
-// 2.3).  Every LDS flush of a whole chunk writes 64 aligned 128-byte lines;
-// a final partial chunk is written with dword stores and the state is moved
-// over it with the windowed tables (only if want_end).  `lds` holds 64 * 144
-// bytes.  READ_ALL: read all eight LDS pieces of a flush before the first
-// store (else each piece goes straight to memory).
+// Each stream first writes its head, the values before its row's first
+// 128-byte line boundary (fewer than 128 / ES): value i of the head comes
+// from A^i applied to the state (head_tab: entry l is A^l), members taking
+// i = g, GL + g, ..., and the stream moves on to the state A^head w.  The rest
+// is cut into chunks of GL*L values; member g generates the L consecutive
+// values [g*L, g*L + L) of each chunk starting from A^(g*L) applied to the
+// chunk's first state (m: the lane's 18-word matrix pair), and the next chunk
+// starts where member GL-1 ended (sequence splitting, sec. 2.3).  Every LDS
+// flush of whole chunks writes aligned 128-byte lines; a stream's last,
+// partial chunk writes the same lines up to its end (16-byte stores, dwords
+// for the last group), and its state is then moved over that chunk with the
+// windowed tables.  `lds` holds 64 * 144 bytes.
+// READ_ALL: read all eight LDS pieces of a flush before the first store (else
+// each piece goes straight to memory).
 // ---------------------------------------------------------------------------
 template <int DT, int L, class G, bool READ_ALL = true, int GL = 64>
 __device__ __forceinline__ void wave_fill(uint32_t *w, const uint32_t *m, unsigned char *lds,
@@ -219,52 +221,85 @@ __device__ __forceinline__ void wave_fill(uint32_t *w, const uint32_t *m, unsign
     constexpr int RS = 128 + 16;   // LDS row pitch (bytes)
     constexpr int SPW = 64 / GL;   // streams per wave
     constexpr int JPS = GL / 8;    // flush instructions per stream
+    constexpr int ROUNDS = (TV + GL - 1) / GL;  // head rounds (heads are < TV values)
     static_assert(NH >= 1 && L % TV == 0, "chunk must be whole pieces");
     static_assert(GL == 64 || GL == 32 || GL == 16 || GL == 8, "8, 16, 32 or 64 lanes per stream");
+    static_assert(ROUNDS * GL <= 64, "head table has 64 entries");
     const uint64_t chunk_vals = (uint64_t)GL * L;
+    const uint64_t len = v1 > v0 ? v1 - v0 : 0;
     unsigned char *my_lds = lds + lane * RS;
     const int prow = lane >> 3;        // flush: 8 lanes per 128-byte piece
     const int pcol = (lane & 7) * 16;  //        8 pieces per instruction
-    const int last = (lane / GL) * GL + GL - 1;  // the member that ends a chunk
+    const int tl = lane / GL, gl = lane % GL;
+    const int last = tl * GL + GL - 1;  // the member that ends a chunk
 
-    if constexpr (GL == 64) {
-        const uint32_t mis = (uint32_t)((uintptr_t)(srow + v0 * ES) & 127u);
-        if (mis && v0 < v1) {
-            const uint64_t hv = (128 - mis) / ES < v1 - v0 ? (128 - mis) / ES : v1 - v0;
+    // head of every stream (wave-uniform values, one per stream)
+    uint32_t hvt[SPW];
+#pragma unroll
+    for (int t = 0; t < SPW; ++t)
+        hvt[t] = (uint32_t)head_values<ES>(srow + t * row_stride + v0 * ES, len);
+    uint32_t hv = hvt[0];
+#pragma unroll
+    for (int t = 1; t < SPW; ++t)
+        if (tl == t) hv = hvt[t];
+    if (__any(hv != 0u)) {
+        uint32_t sel[6] = {w[0], w[1], w[2], w[3], w[4], w[5]};
+        for (int k = 0; k < ROUNDS; ++k) {
+            const uint32_t i = (uint32_t)(k * GL + gl);
             uint32_t hm[18];
 #pragma unroll
-            for (int i = 0; i < 18; ++i) hm[i] = head_tab[lane * 18 + i];
+            for (int q = 0; q < 18; ++q) hm[q] = head_tab[i * 18 + q];
             uint32_t st[6] = {w[0], w[1], w[2], w[3], w[4], w[5]};
             matvec3<C1>(hm, st[0], st[1], st[2]);
             matvec3<C2>(hm + 9, st[3], st[4], st[5]);
-            if ((uint64_t)lane < hv) {
+            if (tl < nsv && i < hv) {
                 G g;
                 g.load(st);
-                put1<DT>(srow + (v0 + lane) * ES, g);
+                put1<DT>(srow + tl * row_stride + (v0 + i) * ES, g);
             }
+            if (i == hv) {
 #pragma unroll
-            for (int k = 0; k < 6; ++k) w[k] = __shfl(st[k], (int)hv);
-            v0 += hv;
+                for (int q = 0; q < 6; ++q) sel[q] = st[q];
+            }
         }
+        // the state at v0 + hv sits with member hv % GL of this stream
+#pragma unroll
+        for (int q = 0; q < 6; ++q) w[q] = __shfl(sel[q], tl * GL + (int)(hv % GL));
     }
+    const uint64_t start = v0 + hv;  // this lane's stream: first line-aligned value
 
     bool whole = true;
-    for (uint64_t c0 = v0; c0 < v1; c0 += chunk_vals) {
+    for (uint64_t c = 0;; ++c) {
+        const uint64_t c0 = start + c * chunk_vals;
+        if (!__any(c0 < v1)) break;
         uint32_t st[6] = {w[0], w[1], w[2], w[3], w[4], w[5]};
         matvec3<C1>(m, st[0], st[1], st[2]);
         matvec3<C2>(m + 9, st[3], st[4], st[5]);
         G g;
         g.load(st);
+        const bool active = c0 < v1;
         const bool full = c0 + chunk_vals <= v1;
-        for (int h = 0; h < NH; ++h) {
+        const bool cut = __any(tl < nsv && active && !full);  // a row ends in this chunk
+        // a chunk where every row ends before member 0's last piece needs
+        // only the flushes up to the longest of them
+        int h_end = NH;
+        if (cut) {
+            uint64_t rmax = 0;
+#pragma unroll
+            for (int t = 0; t < SPW; ++t) {
+                const uint64_t ct = v0 + hvt[t] + c * chunk_vals;
+                const uint64_t r = (SPW > 1 && t >= nsv) || ct >= v1 ? 0 : v1 - ct;
+                rmax = r > rmax ? r : rmax;
+            }
+            if (rmax < (uint64_t)L) h_end = (int)((rmax + TV - 1) / TV);
+        }
+        for (int h = 0; h < h_end; ++h) {
 #pragma unroll
             for (int q = 0; q < 8; ++q) *(uint4 *)(my_lds + q * 16) = gen16<DT>(g);
             __syncthreads();
-            if (full) {
-                // piece row prow + 8j: stream j / JPS, member prow + 8 (j % JPS).
-                // Address = a wave-uniform base (stream row, chunk, piece) plus
-                // a lane offset below 2^32 that is fixed for the whole call.
-                const uint64_t hoff = (c0 + (uint64_t)h * TV) * ES;
+            // piece row prow + 8j is stream j / JPS, member prow + 8 (j % JPS);
+            // each piece is one aligned 128-byte line of the row
+            if (!cut) {
                 if constexpr (READ_ALL) {
                     uint4 v[8];
 #pragma unroll
@@ -273,41 +308,45 @@ __device__ __forceinline__ void wave_fill(uint32_t *w, const uint32_t *m, unsign
 #pragma unroll
                     for (int j = 0; j < 8; ++j) {
                         const int t = j / JPS;
-                        if (SPW > 1 && t >= nsv) continue;
+                        const uint64_t ct = v0 + hvt[t] + c * chunk_vals;
+                        if ((SPW > 1 && t >= nsv) || ct + chunk_vals > v1) continue;
                         const uint32_t loff = (uint32_t)((prow + 8 * (j % JPS)) * L * ES + pcol);
-                        *(uint4 *)(srow + t * row_stride + hoff + loff) = v[j];
+                        *(uint4 *)(srow + t * row_stride + (ct + (uint64_t)h * TV) * ES + loff) = v[j];
                     }
                 } else {
 #pragma unroll
                     for (int j = 0; j < 8; ++j) {
                         const int t = j / JPS;
-                        if (SPW > 1 && t >= nsv) continue;
+                        const uint64_t ct = v0 + hvt[t] + c * chunk_vals;
+                        if ((SPW > 1 && t >= nsv) || ct + chunk_vals > v1) continue;
                         const uint4 v = *(const uint4 *)(lds + (prow + 8 * j) * RS + pcol);
                         const uint32_t loff = (uint32_t)((prow + 8 * (j % JPS)) * L * ES + pcol);
-                        *(uint4 *)(srow + t * row_stride + hoff + loff) = v;
+                        *(uint4 *)(srow + t * row_stride + (ct + (uint64_t)h * TV) * ES + loff) = v;
                     }
                 }
             } else {
-                // the last, partial chunk: dword copies, two pieces per
-                // instruction (lanes 0-31 row 2q, lanes 32-63 row 2q+1), only
-                // bytes below (v1 - c0) * ES.  Rows 8u .. 8u+7 belong to one
-                // stream (t) and members g0 .. g0+7.
-                const int half = lane >> 5;
-                const uint64_t lim = (v1 - c0) * ES;
-                const uint64_t lane_off = (uint64_t)half * L * ES + (uint64_t)h * 128 + (lane & 31) * 4;
-                unsigned char *base = srow + c0 * ES + lane_off;
-                const unsigned char *src = lds + half * RS + (lane & 31) * 4;
+                // some row ends here: the same pieces, 16-byte stores below
+                // the end and dword stores for the group that straddles it
 #pragma unroll 1
-                for (int u = 0; u < 8; ++u) {
-                    const int t = (8 * u) / GL, g0 = (8 * u) % GL;
+                for (int j = 0; j < 8; ++j) {
+                    const int t = j / JPS;
                     if (SPW > 1 && t >= nsv) break;
-                    unsigned char *p = base + t * row_stride + (uint64_t)g0 * L * ES;
-                    const unsigned char *sp = src + 8 * u * RS;
-                    const uint64_t o0 = (uint64_t)g0 * L * ES + lane_off;
-#pragma unroll
-                    for (int j = 0; j < 4; ++j)
-                        if (o0 + (uint64_t)(2 * j) * L * ES < lim)
-                            *(uint32_t *)(p + 2 * j * L * ES) = *(const uint32_t *)(sp + 2 * j * RS);
+                    // stream t's head count sits in its first lane
+                    const uint32_t ht = (uint32_t)__builtin_amdgcn_readlane((int)hv, t * GL);
+                    const uint64_t ct = v0 + ht + c * chunk_vals;
+                    if (ct >= v1) continue;
+                    const uint64_t rem = (v1 - ct < chunk_vals ? v1 - ct : chunk_vals) * ES;
+                    const uint32_t o = (uint32_t)((prow + 8 * (j % JPS)) * L * ES + pcol + h * 128);
+                    if (o >= rem) continue;
+                    const uint4 v = *(const uint4 *)(lds + (prow + 8 * j) * RS + pcol);
+                    unsigned char *p = srow + t * row_stride + ct * ES + o;
+                    if (o + 16 <= rem) {
+                        *(uint4 *)p = v;
+                    } else {
+                        *(uint32_t *)p = v.x;
+                        if (o + 4 < rem) *(uint32_t *)(p + 4) = v.y;
+                        if (o + 8 < rem) *(uint32_t *)(p + 8) = v.z;
+                    }
                 }
             }
             __syncthreads();
@@ -317,12 +356,12 @@ __device__ __forceinline__ void wave_fill(uint32_t *w, const uint32_t *m, unsign
             g.store(e);
 #pragma unroll
             for (int k = 0; k < 6; ++k) w[k] = __shfl(e[k], last);
-        } else {
+        } else if (active) {
             whole = false;
         }
     }
     // w is the last chunk's first state: move it over the partial chunk
-    if (!whole && want_end) jump_global(table, (v1 - v0) % chunk_vals, 0, 0, 0, 16, w);
+    if (!whole && want_end) jump_global(table, (v1 - start) % chunk_vals, 0, 0, 0, 16, w);
 }
 
 }  // namespace mrg

@@ -476,15 +476,21 @@ mrg_status mrg_fill(mrg_streamset ss, uint64_t first, uint64_t count, uint64_t n
             DevCtx *ctx;
             if ((st = device_ctx(ss->device, &ctx))) return st;
             // GL lanes per stream, 64/GL streams per wave; each lane takes
-            // 2*64/GL pieces of 128 bytes per chunk when the stream fills such
-            // a chunk, else half as many (a chunk is then 64 x 128 bytes)
-            // several streams per wave only when every row starts on a
-            // 128-byte line (one stream per wave realigns its rows itself)
-            const bool rows_aligned = (uintptr_t)d_out % 128 == 0 && (n_per_stream * es) % 128 == 0;
-            const int GL = rows_aligned ? tune.coop_lanes : 64;
+            // 64/GL or 2*64/GL pieces of 128 bytes per chunk (a chunk is then
+            // 64 or 128 lines), whichever generates fewer values past the end
+            // of a row (the longer chunk on a tie).  A row's line-aligned
+            // part is n values, or about n - tv/2 when rows start anywhere.
+            // automatic: 16 lanes for rows under 64 KiB, else 64 (measured
+            // faster for rows of 64 KiB and more)
+            const int GL = tune.coop_lanes ? tune.coop_lanes : n_per_stream * es >= 65536 ? 64 : 16;
             const uint64_t tv = 128 / es;
             const uint64_t nh_min = 64 / GL, nh_max = 2 * nh_min;
-            const uint64_t nh = n_per_stream >= (uint64_t)GL * nh_max * tv ? nh_max : nh_min;
+            const bool rows_aligned = (uintptr_t)d_out % 128 == 0 && (n_per_stream * es) % 128 == 0;
+            const uint64_t body = rows_aligned || n_per_stream <= tv ? n_per_stream : n_per_stream - tv / 2;
+            const uint64_t ch_min = (uint64_t)GL * nh_min * tv, ch_max = 2 * ch_min;
+            const uint64_t gen_min = (body + ch_min - 1) / ch_min * ch_min;
+            const uint64_t gen_max = (body + ch_max - 1) / ch_max * ch_max;
+            const uint64_t nh = gen_max <= gen_min ? nh_max : nh_min;
             const int L = (int)(nh * tv);
             int k = 0;
             while (k < mrg::kNumLaneSegs - 1 && mrg::kLaneSegs[k] != L) ++k;
@@ -563,8 +569,8 @@ mrg_status mrg_config_set(const char *key, int64_t value)
         if (value < 0 || value > 1024) return set_error(MRG_EINVAL, "coop_wgs_per_cu must be in [0, 1024]");
         g_tune.coop_wgs_per_cu = (int)value;
     } else if (!std::strcmp(key, "coop_lanes")) {
-        if (value != 64 && value != 32 && value != 16 && value != 8)
-            return set_error(MRG_EINVAL, "coop_lanes must be 64, 32, 16 or 8");
+        if (value != 64 && value != 32 && value != 16 && value != 8 && value != 0)
+            return set_error(MRG_EINVAL, "coop_lanes must be 0, 64, 32, 16 or 8");
         g_tune.coop_lanes = (int)value;
     } else if (!std::strcmp(key, "strategy")) {
         if (value < 0 || value > 2) return set_error(MRG_EINVAL, "strategy must be 0, 1 or 2");

@@ -28,7 +28,7 @@ struct FillTuning {
     int tile_bytes = 0;       // lane per stream: 0 = 128 for rows under 1 KiB, else 256
     int strategy = 0;
     int coop_wgs_per_cu = 0;  // wave per stream: 0 = one workgroup per stream group
-    int coop_lanes = 16;      // wave per stream: lanes per stream (64, 32, 16 or 8)
+    int coop_lanes = 0;       // wave per stream: lanes per stream (64, 32, 16, 8; 0 automatic)
 };
 
 // Lane-segment lengths L of the wave-per-stream fill; table k holds A^(l*L)

@@ -162,6 +162,20 @@ fill_il_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t fi
 // wave_fill, so that every flush writes whole 128-byte lines and the streams
 // in flight stay adjacent.  Lanes of a group past the last stream run on a
 // dummy state and write nothing.
+// Workgroups are dispatched to the 8 XCDs in turn (workgroup b on XCD b % 8).
+// xcd_range gives the workgroups of each XCD a contiguous range of the items,
+// so that work which varies with the item index in a period dividing 8 still
+// spreads evenly over the XCDs, and neighbouring rows meet in one L2.
+struct XcdRange { uint64_t first, end, step; };
+__device__ __forceinline__ XcdRange xcd_range(uint64_t items)
+{
+    const uint64_t nb = gridDim.x, b = blockIdx.x;
+    if (nb < 8) return {b, items, nb};
+    const uint64_t x = b % 8, q = items / 8, r = items % 8;
+    const uint64_t lo = x * q + (x < r ? x : r);
+    return {lo + b / 8, lo + q + (x < r ? 1 : 0), (nb - x + 7) / 8};
+}
+
 template <int DT, int L, int GL, class G>
 __global__ void __launch_bounds__(64)
 fill_coop_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t first,
@@ -178,7 +192,9 @@ fill_coop_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t 
 #pragma unroll
     for (int i = 0; i < 18; ++i) m[i] = lane_tab[(lane % GL) * 18 + i];
 
-    for (uint64_t s0 = (uint64_t)blockIdx.x * SPW; s0 < count; s0 += (uint64_t)gridDim.x * SPW) {
+    const XcdRange R = xcd_range((count + SPW - 1) / SPW);
+    for (uint64_t grp = R.first; grp < R.end; grp += R.step) {
+        const uint64_t s0 = grp * SPW;
         const int nsv = count - s0 < (uint64_t)SPW ? (int)(count - s0) : SPW;
         const uint64_t idx = first + s0 + t;
         uint32_t w[6] = {1u, 1u, 1u, 1u, 1u, 1u};

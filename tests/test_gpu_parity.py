@@ -19,10 +19,10 @@ pytestmark = pytest.mark.gpu
 # (engine, stream-major strategy): integer / binary64 arithmetic, lane per
 # stream / wave per stream
 # (engine, strategy, lanes per stream of the wave-per-stream fill)
-CONFIGS = [(0, 1, 64), (1, 1, 64), (0, 2, 64), (1, 2, 64), (1, 2, 32), (0, 2, 16), (1, 2, 16),
-           (1, 2, 8)]
-CONFIG_IDS = ["int-lane", "f64-lane", "int-wave", "f64-wave", "f64-wave32", "int-wave16",
-              "f64-wave16", "f64-wave8"]
+CONFIGS = [(1, 0, 0), (0, 1, 64), (1, 1, 64), (0, 2, 64), (1, 2, 64), (1, 2, 32), (0, 2, 16),
+           (1, 2, 16), (1, 2, 8)]
+CONFIG_IDS = ["default", "int-lane", "f64-lane", "int-wave", "f64-wave", "f64-wave32",
+              "int-wave16", "f64-wave16", "f64-wave8"]
 
 
 def say(*a):
