@@ -80,6 +80,10 @@ def _load():
         lib.orc_splitmix64_next.argtypes = [P]
         lib.orc_splitmix64_next.restype = u64
         lib.orc_seed_from_master.argtypes = [u64, P]
+        lib.orc_splitmix64_at.argtypes = [u64, u64]
+        lib.orc_splitmix64_at.restype = u64
+        lib.orc_random_spacing.argtypes = [u64, u64, u64, P]
+        lib.orc_random_spacing.restype = None
         lib.orc_state_valid.argtypes = [P]
         lib.orc_state_valid.restype = ctypes.c_int
         _lib = lib
@@ -208,6 +212,36 @@ def seed_from_master(master: int) -> np.ndarray:
     out = np.zeros(6, dtype=np.uint32)
     _load().orc_seed_from_master(int(master), _ptr(out))
     return out
+
+
+def splitmix64_at(seed: int, k: int) -> int:
+    """Output number k of SplitMix64 seeded with ``seed``."""
+    return int(_load().orc_splitmix64_at(int(seed), int(k)))
+
+
+def random_spacing_states(master: int, first: int, count: int) -> np.ndarray:
+    """Random spacing (sec. 2.3): [count, 6] start states of streams
+    first .. first+count-1, stream g started from the state expanded from
+    SplitMix64 output g of ``master`` (as ``seed_from_master`` expands a
+    seed)."""
+    out = np.zeros((count, 6), dtype=np.uint32)
+    if count:
+        _load().orc_random_spacing(int(master), int(first), int(count), _ptr(out))
+    return out
+
+
+def leapfrog(state, players: int, per_player: int, dtype: int = U32,
+             layout: int = STREAM_MAJOR):
+    """Leapfrog (sec. 2.3): the outputs of one stream dealt to ``players``
+    players like cards, ``per_player`` each: card k of player t is output
+    t + k * players of the stream.  Returns (out, advanced_state): out is
+    [players, per_player] (STREAM_MAJOR: each player's cards in a row) or
+    [per_player, players] (INTERLEAVED: the stream's outputs in order)."""
+    seq, end = fill(_state(state), players * per_player, dtype, STREAM_MAJOR)
+    dealt = seq.reshape(per_player, players)  # row k: card k of every player
+    if layout == STREAM_MAJOR:
+        dealt = np.ascontiguousarray(dealt.T)
+    return dealt, end.reshape(6)
 
 
 def state_valid(state) -> bool:

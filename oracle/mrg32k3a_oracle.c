@@ -245,6 +245,24 @@ void orc_seed_from_master(uint64_t master, uint32_t out[6])
     }
 }
 
+/* Output number k (k = 0, 1, ...) of SplitMix64 seeded with `seed`: the
+ * generator's state after k+1 increments is seed + (k+1) * gamma, so the
+ * state before the call that returns output k is seed + k * gamma. */
+uint64_t orc_splitmix64_at(uint64_t seed, uint64_t k)
+{
+    uint64_t x = seed + k * 0x9e3779b97f4a7c15ULL;
+    return orc_splitmix64_next(&x);
+}
+
+/* Random spacing (sec. 2.3: the same generator started from different
+ * random states).  Stream g of the set starts at the state expanded, as for
+ * a master seed, from output g of SplitMix64 seeded with `master`. */
+void orc_random_spacing(uint64_t master, uint64_t first, uint64_t count, uint32_t *out)
+{
+    for (uint64_t i = 0; i < count; ++i)
+        orc_seed_from_master(orc_splitmix64_at(master, first + i), out + 6 * i);
+}
+
 /* 1 when the state is a valid MRG32k3a state: each word below its modulus
  * and neither triple all zero (the all-zero triple is a fixed point). */
 int orc_state_valid(const uint32_t s[6])

@@ -14,7 +14,12 @@ Nothing here compares the oracle with a retyped copy of itself.  The pins are:
 * stream and substream spacing of sec. 4.1: 2^64 streams of 2^127 numbers,
   substreams of 2^76 (2^51 substreams per stream);
 * the floating-point conversions, evaluated in exact rational arithmetic;
-* the SplitMix64 known-answer value used by the master-seed expansion.
+* the SplitMix64 known-answer value used by the master-seed expansion, and
+  its random access (output k) against the sequential generator;
+* the two partitions of one sequence in sec. 2.3 beside sequence splitting:
+  random spacing (each stream from its own expanded SplitMix64 draw) and the
+  leapfrog deal (every card checked against the big-integer jump of
+  ``oracle/ref.py``).
 """
 import math
 import os
@@ -383,6 +388,56 @@ def test_seed_from_master_is_valid_and_defined():
         w = oracle.splitmix64(seed, 6)
         want = [w[i] % M1 for i in range(3)] + [w[i] % M2 for i in range(3, 6)]
         assert [int(x) for x in s] == want
+
+
+def test_splitmix64_random_access_matches_sequential():
+    for seed in (0, 1, 0x0123456789ABCDEF, 2**64 - 1):
+        seq = oracle.splitmix64(seed, 1500)
+        for k in list(range(40)) + [777, 1499]:
+            assert oracle.splitmix64_at(seed, k) == seq[k]
+    assert oracle.splitmix64_at(0, 0) == 0xE220A8397B1DCDAF
+
+
+# --------------------------------------------------------------------------
+# random spacing and leapfrog (sec. 2.3)
+# --------------------------------------------------------------------------
+def test_random_spacing_states_are_expanded_draws():
+    master = 0x0123456789ABCDEF
+    seq = oracle.splitmix64(master, 64)
+    st = oracle.random_spacing_states(master, 0, 64)
+    assert st.shape == (64, 6)
+    for g in range(64):
+        assert np.array_equal(st[g], oracle.seed_from_master(seq[g]))
+        assert oracle.state_valid(st[g])
+    assert len({tuple(r) for r in st.tolist()}) == 64
+    # a window of the set is the same streams
+    assert np.array_equal(oracle.random_spacing_states(master, 17, 9), st[17:26])
+    far = oracle.random_spacing_states(master, 2**40 + 3, 2)
+    assert np.array_equal(far[1], oracle.seed_from_master(oracle.splitmix64_at(master, 2**40 + 4)))
+
+
+@pytest.mark.parametrize("players,per_player", [(1, 9), (7, 1), (5, 6), (64, 3), (3, 70)])
+def test_leapfrog_cards_are_every_pth_output(players, per_player):
+    seed = oracle.seed_from_master(99)
+    pm, end = oracle.leapfrog(seed, players, per_player, oracle.U32, oracle.STREAM_MAJOR)
+    il, end2 = oracle.leapfrog(seed, players, per_player, oracle.U32, oracle.INTERLEAVED)
+    assert pm.shape == (players, per_player) and il.shape == (per_player, players)
+    assert np.array_equal(pm, il.T) and np.array_equal(end, end2)
+    for t in range(players):
+        for k in range(per_player):
+            # card k of player t: one step from the state t + k*players
+            # steps on, computed with big-integer matrix powers
+            assert int(pm[t, k]) == ref.outputs(ref.jump(seed, t + k * players), 1)[0]
+    assert [int(v) for v in end] == ref.jump(seed, players * per_player)
+
+
+def test_leapfrog_floats_follow_the_integers():
+    seed = oracle.seed_from_master(5)
+    u, _ = oracle.leapfrog(seed, 11, 4, oracle.U32)
+    f, _ = oracle.leapfrog(seed, 11, 4, oracle.F32)
+    d, _ = oracle.leapfrog(seed, 11, 4, oracle.F64, oracle.INTERLEAVED)
+    assert np.array_equal(f, np.vectorize(oracle.to_f32)(u).astype(np.float32))
+    assert np.array_equal(d, np.vectorize(oracle.to_f64)(u.T))
 
 
 # --------------------------------------------------------------------------
