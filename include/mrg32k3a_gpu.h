@@ -89,6 +89,18 @@ mrg_status mrg_streamset_create_seed64(mrg_streamset *out, uint64_t n_streams,
                                        uint64_t first_stream, uint64_t master_seed,
                                        void *stream);
 
+/* Random spacing (sec. 2.3: the same generator started from different random
+ * states): stream g (global index) starts at the state that
+ * mrg_seed_from_master expands from output g (g = 0, 1, ...) of SplitMix64
+ * seeded with master_seed, i.e. mix(master_seed + (g+1) * gamma).  Streams
+ * are not spaced by a jump, so two of them may overlap after an unknown
+ * number of outputs (for 2^20 streams of 2^40 outputs each the chance is
+ * about 2^-90 of a period of 2^191).  Sizes, errors and ownership as
+ * mrg_streamset_create; mrg_streamset_info reports an all-zero seed6. */
+mrg_status mrg_streamset_create_random(mrg_streamset *out, uint64_t n_streams,
+                                       uint64_t first_stream, uint64_t master_seed,
+                                       void *stream);
+
 /* Release the stream set and its device memory (sec. 5.1 release()).
  * Synchronises the device work the library enqueued on the set first.
  * NULL is accepted and ignored. */
@@ -151,6 +163,24 @@ mrg_status mrg_jump_substreams(mrg_streamset ss, uint64_t first, uint64_t count,
 mrg_status mrg_fill(mrg_streamset ss, uint64_t first, uint64_t count,
                     uint64_t n_per_stream, mrg_dtype dtype, mrg_layout layout,
                     void *d_out, void *stream);
+
+/* Leapfrog (sec. 2.3): the outputs of stream s of the set dealt to
+ * `players` players like cards, `per_player` each: card k of player t is
+ * output t + k * players of the stream.  With P = players, K = per_player:
+ *   layout MRG_STREAM_MAJOR: d_out[t * K + k] (a [P, K] array: each
+ *                            player's cards in a row; full speed needs
+ *                            K >= 64, since 64 adjacent cards of one player
+ *                            make one store)
+ *   layout MRG_INTERLEAVED : d_out[k * P + t] (a [K, P] array: the stream's
+ *                            outputs in order, generated by sequence
+ *                            splitting over the whole device)
+ * Advances stream s by P * K.  d_out holds P * K elements of the dtype,
+ * aligned to the element size.  P == 0 or K == 0 is a no-op.  Errors:
+ * MRG_EINVAL (null d_out, bad dtype/layout, misaligned), MRG_ERANGE (s
+ * outside the set, P * K * element size above 2^64 - 1). */
+mrg_status mrg_fill_leapfrog(mrg_streamset ss, uint64_t s, uint64_t players,
+                             uint64_t per_player, mrg_dtype dtype, mrg_layout layout,
+                             void *d_out, void *stream);
 
 /* Copy the states of streams [first, first+count) to host memory h_out
  * ([count][6] uint32).  Synchronous with respect to `stream` (waits for it). */

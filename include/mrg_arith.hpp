@@ -182,4 +182,40 @@ MRG_HD double to_f64f(double z) { return z * NORM; }
 // FP32 output from an exact binary64 z in [1, m1]: through its uint32 value.
 MRG_HD float to_f32f(double z) { return to_f32((uint32_t)z); }
 
+// ---------------------------------------------------------------------------
+// SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): the state advances by a fixed
+// odd gamma and each output is a bijective mix of the new state, so output k
+// of a generator seeded with s is mix(s + (k+1) * gamma).
+// ---------------------------------------------------------------------------
+constexpr uint64_t kSplitMixGamma = 0x9e3779b97f4a7c15ull;
+
+MRG_HD uint64_t splitmix64_mix(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+MRG_HD uint64_t splitmix64_next(uint64_t &x)
+{
+    x += kSplitMixGamma;
+    return splitmix64_mix(x);
+}
+
+// A 64-bit seed expanded into a valid state (random spacing, sec. 2.3):
+// successive SplitMix64 outputs mod m1 for words 0-2 and mod m2 for words
+// 3-5; a triple that comes out all zero (probability below 2^-95) is drawn
+// again, at most 16 times in all.
+MRG_HD void expand_seed(uint64_t seed, uint32_t out[6])
+{
+    uint64_t x = seed;
+    for (int c = 0; c < 2; ++c) {
+        const uint64_t m = c ? M2 : M1;
+        for (int attempt = 0; attempt < 16; ++attempt) {
+            for (int i = 0; i < 3; ++i) out[3 * c + i] = (uint32_t)(splitmix64_next(x) % m);
+            if (out[3 * c] | out[3 * c + 1] | out[3 * c + 2]) break;
+        }
+    }
+}
+
 }  // namespace mrg

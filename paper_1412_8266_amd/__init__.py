@@ -51,16 +51,25 @@ class StreamSet:
 
     Global stream g starts at A^(g * 2^127) * base; the stream set holds
     streams [first_stream, first_stream + n_streams).  The base state is
-    ``seed`` (6 words) or is expanded from ``master_seed`` (64 bits).
+    ``seed`` (6 words) or is expanded from ``master_seed`` (64 bits).  With
+    ``spacing="random"`` (and a master seed) stream g instead starts at its
+    own random state, expanded from SplitMix64 output g of the master seed
+    (random spacing, sec. 2.3).
     """
 
     def __init__(self, n_streams: int, seed=None, master_seed: Optional[int] = None,
-                 first_stream: int = 0, stream=None):
+                 first_stream: int = 0, stream=None, spacing: str = "jump"):
         if (seed is None) == (master_seed is None):
             raise ValueError("give exactly one of seed (6 words) or master_seed")
+        if spacing not in ("jump", "random"):
+            raise ValueError("spacing must be 'jump' or 'random'")
+        if spacing == "random" and master_seed is None:
+            raise ValueError("random spacing draws its states from a master_seed")
         h = _stream_handle(stream)
         if seed is not None:
             self._h = _abi.mrg_streamset_create(n_streams, first_stream, seed, h)
+        elif spacing == "random":
+            self._h = _abi.mrg_streamset_create_random(n_streams, first_stream, master_seed, h)
         else:
             self._h = _abi.mrg_streamset_create_seed64(n_streams, first_stream, master_seed, h)
         self.n_streams = int(n_streams)
@@ -131,6 +140,23 @@ class StreamSet:
                  count: Optional[int] = None, stream=None) -> None:
         first, count = self._range(first, count)
         _abi.mrg_fill(self._h, first, count, n, dtype, layout, d_out, _stream_handle(stream))
+
+    def fill_leapfrog(self, s: int, players: int, per_player: int, dtype: int = U32,
+                      layout: int = STREAM_MAJOR, out=None, stream=None):
+        """Leapfrog (sec. 2.3): stream s dealt to ``players`` players, card k of
+        player t being output t + k*players; advances stream s by
+        players*per_player.  Returns a [players, per_player] (STREAM_MAJOR) or
+        [per_player, players] (INTERLEAVED: the stream in order) tensor."""
+        torch = _torch()
+        shape = (players, per_player) if layout == STREAM_MAJOR else (per_player, players)
+        if out is None:
+            out = torch.empty(shape, dtype=torch_dtype(dtype), device="cuda")
+        elif (out.numel() < players * per_player or out.element_size() != _ESIZE[dtype]
+              or not out.is_contiguous()):
+            raise ValueError("output tensor too small, of the wrong element size or not contiguous")
+        _abi.mrg_fill_leapfrog(self._h, s, players, per_player, dtype, layout,
+                               out.data_ptr() if out.numel() else 0, _stream_handle(stream))
+        return out
 
     # -- jumps ------------------------------------------------------------------
     def jump(self, exps, first: int = 0, count: Optional[int] = None, stream=None) -> None:

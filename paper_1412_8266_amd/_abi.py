@@ -52,6 +52,7 @@ _PU64 = ctypes.POINTER(ctypes.c_uint64)
 _SIGS = {
     "mrg_streamset_create": [ctypes.POINTER(_P), _U64, _U64, _PU32, _P],
     "mrg_streamset_create_seed64": [ctypes.POINTER(_P), _U64, _U64, _U64, _P],
+    "mrg_streamset_create_random": [ctypes.POINTER(_P), _U64, _U64, _U64, _P],
     "mrg_streamset_destroy": [_P],
     "mrg_streamset_info": [_P, _PU64, _PU64, _PU32],
     "mrg_streamset_states_ptr": [_P, ctypes.POINTER(_P)],
@@ -60,6 +61,7 @@ _SIGS = {
     "mrg_jump_uniform": [_P, _U64, _U64, _PU64, _P],
     "mrg_jump_substreams": [_P, _U64, _U64, _U64, _P],
     "mrg_fill": [_P, _U64, _U64, _U64, _I32, _I32, _P, _P],
+    "mrg_fill_leapfrog": [_P, _U64, _U64, _U64, _I32, _I32, _P, _P],
     "mrg_get_states": [_P, _U64, _U64, _PU32, _P],
     "mrg_set_states": [_P, _U64, _U64, _PU32, _P],
     "mrg_seed_from_master": [_U64, _PU32],
@@ -194,6 +196,14 @@ def mrg_streamset_create_seed64(n_streams: int, first_stream: int, master_seed: 
     return h.value
 
 
+def mrg_streamset_create_random(n_streams: int, first_stream: int, master_seed: int,
+                                stream: int = 0) -> int:
+    h = _P()
+    _call("mrg_streamset_create_random", ctypes.byref(h), n_streams, first_stream,
+          master_seed & ((1 << 64) - 1), stream)
+    return h.value
+
+
 def mrg_streamset_destroy(ss: int) -> None:
     _call("mrg_streamset_destroy", ss)
 
@@ -232,6 +242,11 @@ def mrg_jump_substreams(ss: int, first: int, count: int, k: int, stream: int = 0
 def mrg_fill(ss: int, first: int, count: int, n_per_stream: int, dtype: int, layout: int,
              d_out: int, stream: int = 0) -> None:
     _call("mrg_fill", ss, first, count, n_per_stream, dtype, layout, d_out, stream)
+
+
+def mrg_fill_leapfrog(ss: int, s: int, players: int, per_player: int, dtype: int, layout: int,
+                      d_out: int, stream: int = 0) -> None:
+    _call("mrg_fill_leapfrog", ss, s, players, per_player, dtype, layout, d_out, stream)
 
 
 def mrg_get_states(ss: int, first: int, count: int, stream: int = 0):

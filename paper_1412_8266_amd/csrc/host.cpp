@@ -254,20 +254,49 @@ namespace {
 using mrg::check_range;
 mrg_status check_set(mrg_streamset ss) { return mrg::check_streamset(ss); }
 
-uint64_t splitmix64_next(uint64_t &x)
-{
-    x += 0x9e3779b97f4a7c15ULL;
-    uint64_t z = x;
-    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
-    z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
-    return z ^ (z >> 31);
-}
-
 int bit_length(uint64_t v)
 {
     int b = 0;
     while (v) { ++b; v >>= 1; }
     return b;
+}
+
+// Validated size, device context and state planes of a new stream set.
+mrg_status new_streamset(uint64_t n_streams, uint64_t first_stream, mrg_streamset *out,
+                         DevCtx **ctx_out)
+{
+    if (n_streams == 0) return set_error(MRG_ERANGE, "n_streams must be >= 1");
+    if (n_streams - 1 > UINT64_MAX - first_stream)
+        return set_error(MRG_ERANGE, "first_stream + n_streams exceeds 2^64");
+    if (n_streams > ((uint64_t)1 << 36))
+        return set_error(MRG_ERANGE, "n_streams above the limit 2^36");
+    int dev;
+    mrg_status st = current_device(&dev);
+    if (st) return st;
+    if ((st = device_ctx(dev, ctx_out))) return st;
+    auto *ss = new (std::nothrow) mrg_streamset_s;
+    if (!ss) return set_error(MRG_ENOMEM, "host allocation");
+    ss->device = dev;
+    ss->n = n_streams;
+    ss->first = first_stream;
+    hipError_t e = hipMalloc(&ss->d_planes, 6 * n_streams * sizeof(uint32_t));
+    if (e != hipSuccess) {
+        delete ss;
+        return set_error(MRG_ENOMEM, "hipMalloc(%llu states): %s", (unsigned long long)n_streams,
+                         hipGetErrorString(e));
+    }
+    *out = ss;
+    return MRG_OK;
+}
+
+// A^e for both components as kernel arguments.
+mrg::JumpMatrices jump_matrices(const uint64_t e[3])
+{
+    mrg::JumpMatrices J;
+    const Mat P1 = power(0, e), P2 = power(1, e);
+    std::memcpy(J.m, P1.data(), 36);
+    std::memcpy(J.m + 9, P2.data(), 36);
+    return J;
 }
 
 }  // namespace
@@ -277,18 +306,7 @@ extern "C" {
 mrg_status mrg_seed_from_master(uint64_t master_seed, uint32_t out6[6])
 {
     if (!out6) return set_error(MRG_EINVAL, "null output");
-    uint64_t x = master_seed;
-    for (int c = 0; c < 2; ++c) {
-        const uint64_t m = modulus(c);
-        for (;;) {
-            uint32_t t[3];
-            for (int i = 0; i < 3; ++i) t[i] = (uint32_t)(splitmix64_next(x) % m);
-            if (t[0] | t[1] | t[2]) {
-                std::memcpy(out6 + 3 * c, t, sizeof t);
-                break;
-            }
-        }
-    }
+    mrg::expand_seed(master_seed, out6);
     return MRG_OK;
 }
 
@@ -314,37 +332,19 @@ mrg_status mrg_streamset_create(mrg_streamset *out, uint64_t n_streams, uint64_t
     if (!out || !seed6) return set_error(MRG_EINVAL, "null argument");
     *out = nullptr;
     if (!state_ok(seed6)) return set_error(MRG_EINVAL, "invalid seed state");
-    if (n_streams == 0) return set_error(MRG_ERANGE, "n_streams must be >= 1");
-    if (n_streams - 1 > UINT64_MAX - first_stream)
-        return set_error(MRG_ERANGE, "first_stream + n_streams exceeds 2^64");
-    if (n_streams > ((uint64_t)1 << 36))
-        return set_error(MRG_ERANGE, "n_streams above the limit 2^36");
-    int dev;
-    mrg_status st = current_device(&dev);
-    if (st) return st;
+    mrg_streamset ss;
     DevCtx *ctx;
-    if ((st = device_ctx(dev, &ctx))) return st;
-
-    auto *ss = new (std::nothrow) mrg_streamset_s;
-    if (!ss) return set_error(MRG_ENOMEM, "host allocation");
-    ss->device = dev;
-    ss->n = n_streams;
-    ss->first = first_stream;
+    mrg_status st = new_streamset(n_streams, first_stream, &ss, &ctx);
+    if (st) return st;
     std::memcpy(ss->seed, seed6, sizeof ss->seed);
-    hipError_t e = hipMalloc(&ss->d_planes, 6 * n_streams * sizeof(uint32_t));
-    if (e != hipSuccess) {
-        delete ss;
-        return set_error(MRG_ENOMEM, "hipMalloc(%llu states): %s", (unsigned long long)n_streams,
-                    hipGetErrorString(e));
-    }
     // exponent g * 2^127 uses bits 127 .. 126 + bit_length(g): windows 31 ..
     const uint64_t g_max = first_stream + (n_streams - 1);
     const int top_bit = 126 + bit_length(g_max);  // highest set bit of g_max * 2^127
     const int w_lo = 31, w_hi = g_max ? top_bit / 4 + 1 : 31;
     mrg::InitSeed sd;
     std::memcpy(sd.w, seed6, sizeof sd.w);
-    e = mrg::launch_init(ss->d_planes, n_streams, n_streams, first_stream, sd, ctx->d_table,
-                         w_lo, w_hi, (hipStream_t)stream);
+    hipError_t e = mrg::launch_init(ss->d_planes, n_streams, n_streams, first_stream, sd,
+                                    ctx->d_table, w_lo, w_hi, (hipStream_t)stream);
     if (e != hipSuccess) {
         (void)hipFree(ss->d_planes);
         delete ss;
@@ -361,6 +361,27 @@ mrg_status mrg_streamset_create_seed64(mrg_streamset *out, uint64_t n_streams,
     mrg_status st = mrg_seed_from_master(master_seed, s);
     if (st) return st;
     return mrg_streamset_create(out, n_streams, first_stream, s, stream);
+}
+
+mrg_status mrg_streamset_create_random(mrg_streamset *out, uint64_t n_streams,
+                                       uint64_t first_stream, uint64_t master_seed, void *stream)
+{
+    if (!out) return set_error(MRG_EINVAL, "null argument");
+    *out = nullptr;
+    mrg_streamset ss;
+    DevCtx *ctx;
+    mrg_status st = new_streamset(n_streams, first_stream, &ss, &ctx);
+    if (st) return st;
+    // no common base state: info reports all zeros
+    hipError_t e = mrg::launch_random_init(ss->d_planes, n_streams, n_streams, first_stream,
+                                           master_seed, (hipStream_t)stream);
+    if (e != hipSuccess) {
+        (void)hipFree(ss->d_planes);
+        delete ss;
+        return hip_error(e, "random init kernel launch");
+    }
+    *out = ss;
+    return MRG_OK;
 }
 
 mrg_status mrg_streamset_destroy(mrg_streamset ss)
@@ -432,12 +453,8 @@ mrg_status mrg_jump_uniform(mrg_streamset ss, uint64_t first, uint64_t count,
     if ((st = check_range(ss, first, count))) return st;
     if (!h_exp) return set_error(MRG_EINVAL, "null exponent");
     if (count == 0) return MRG_OK;
-    mrg::JumpMatrices J;
-    const Mat P1 = power(0, h_exp), P2 = power(1, h_exp);
-    std::memcpy(J.m, P1.data(), 36);
-    std::memcpy(J.m + 9, P2.data(), 36);
-    hipError_t e = mrg::launch_jump_uniform(ss->d_planes, ss->n, first, count, J,
-                                            (hipStream_t)stream);
+    hipError_t e = mrg::launch_jump_uniform(ss->d_planes, ss->n, first, count,
+                                            jump_matrices(h_exp), (hipStream_t)stream);
     return e == hipSuccess ? MRG_OK : hip_error(e, "jump kernel launch");
 }
 
@@ -511,6 +528,83 @@ mrg_status mrg_fill(mrg_streamset ss, uint64_t first, uint64_t count, uint64_t n
     hipError_t e = mrg::launch_fill(ss->d_planes, ss->n, first, count, n_per_stream, (int)dtype,
                                     (int)layout, d_out, fl, tune, (hipStream_t)stream);
     return e == hipSuccess ? MRG_OK : hip_error(e, "fill kernel launch");
+}
+
+mrg_status mrg_fill_leapfrog(mrg_streamset ss, uint64_t s, uint64_t players,
+                             uint64_t per_player, mrg_dtype dtype, mrg_layout layout,
+                             void *d_out, void *stream)
+{
+    mrg_status st = check_set(ss);
+    if (st) return st;
+    if ((st = check_range(ss, s, 1))) return st;
+    if (dtype != MRG_U32 && dtype != MRG_F32 && dtype != MRG_F64)
+        return set_error(MRG_EINVAL, "unknown dtype %d", (int)dtype);
+    if (layout != MRG_STREAM_MAJOR && layout != MRG_INTERLEAVED)
+        return set_error(MRG_EINVAL, "unknown layout %d", (int)layout);
+    if (players == 0 || per_player == 0) return MRG_OK;
+    if (!d_out) return set_error(MRG_EINVAL, "null output");
+    const uint64_t es = dtype == MRG_F64 ? 8 : 4;
+    if ((uintptr_t)d_out % es) return set_error(MRG_EINVAL, "output not aligned to its element size");
+    if (players > UINT64_MAX / per_player || players * per_player > UINT64_MAX / es)
+        return set_error(MRG_ERANGE, "players * per_player * element size overflows 64 bits");
+    const uint64_t N = players * per_player;
+    DevCtx *ctx;
+    if ((st = device_ctx(ss->device, &ctx))) return st;
+    const mrg::FillTuning tune = tuning();
+    mrg::PartitionLaunch pl;
+    pl.table = ctx->d_table;
+    const uint64_t slots = (uint64_t)ctx->cus * 16;  // resident one-wave workgroups
+    if (layout == MRG_INTERLEAVED) {
+        // the stream's outputs in order: blocks of 16-256 KiB (at least 4096
+        // of them when the output allows), each a whole number of 128-line
+        // chunks, one 64-lane wave per block
+        const uint64_t tv = 128 / es;
+        uint64_t bb = 16384;
+        while (bb < 262144 && N * es / (2 * bb) >= 4096) bb *= 2;
+        pl.kind = 0;
+        pl.B = bb / es;
+        pl.nfull = N / pl.B;
+        pl.rem = N % pl.B;
+        const bool one_chunk = N < 128 * tv;  // short: 64-line chunks
+        pl.L = (int)(one_chunk ? tv : 2 * tv);
+        int k = 0;
+        while (k < mrg::kNumLaneSegs - 1 && mrg::kLaneSegs[k] != pl.L) ++k;
+        if (mrg::kLaneSegs[k] != pl.L) return set_error(MRG_EINVAL, "no lane table for L = %d", pl.L);
+        pl.lane_tab = ctx->d_lane_tab + k * 64 * 18;
+        pl.head_tab = ctx->d_lane_tab + mrg::kHeadTable * 64 * 18;
+        const uint64_t blocks = pl.nfull + (pl.rem ? 1 : 0);
+        pl.grid = (unsigned)(blocks < ((uint64_t)1 << 31) - 1 ? blocks : ((uint64_t)1 << 31) - 1);
+    } else {
+        // each player's cards in a row: items of 64 card columns x T players,
+        // T chosen for about 4 items per resident workgroup (at least 256)
+        pl.kind = 1;
+        pl.P = players;
+        pl.K = per_player;
+        const uint64_t nkb = (per_player + 63) / 64;
+        const uint64_t target = 4 * slots;
+        uint64_t T = players;
+        if (nkb < target) {
+            const uint64_t segs = (target + nkb - 1) / nkb;
+            T = (players + segs - 1) / segs;
+            if (T < 256) T = 256;
+            if (T > players) T = players;
+        }
+        pl.T = T;
+        pl.nseg = (players + T - 1) / T;
+        pl.items = nkb * pl.nseg;
+        pl.grid = (unsigned)(pl.items < slots ? pl.items : slots);
+        // 63 * players as a 192-bit exponent
+        const unsigned __int128 e63 = (unsigned __int128)players * 63u;
+        const uint64_t ew[3] = {(uint64_t)e63, (uint64_t)(e63 >> 64), 0};
+        pl.J63 = jump_matrices(ew);
+    }
+    hipError_t e = mrg::launch_partition(ss->d_planes, ss->n, s, (int)dtype, pl, d_out,
+                                         tune.engine, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_error(e, "leapfrog kernel launch");
+    // the stream moves past the N outputs dealt
+    const uint64_t en[3] = {N, 0, 0};
+    e = mrg::launch_jump_uniform(ss->d_planes, ss->n, s, 1, jump_matrices(en), (hipStream_t)stream);
+    return e == hipSuccess ? MRG_OK : hip_error(e, "jump kernel launch");
 }
 
 mrg_status mrg_get_states(mrg_streamset ss, uint64_t first, uint64_t count, uint32_t *h_out,

@@ -53,6 +53,30 @@ hipError_t launch_fill(uint32_t *planes, uint64_t plane_stride, uint64_t first, 
                        uint64_t n, int dtype, int layout, void *out,
                        const FillLaunch &fl, const FillTuning &tune, hipStream_t st);
 
+// Random spacing: stream g0 + s of a set starts at the state expanded from
+// SplitMix64 output g0 + s of the master seed.
+hipError_t launch_random_init(uint32_t *planes, uint64_t plane_stride, uint64_t count,
+                              uint64_t g0, uint64_t master, hipStream_t st);
+
+// One stream partitioned (chosen on the host): kind 0 writes its outputs
+// [0, nfull*B + rem) in order, in blocks of B values (64 lanes per block, L
+// values per lane per chunk); kind 1 deals them to P players, K cards each,
+// each player's cards in a row (work items of 64 card columns x T players).
+struct PartitionLaunch {
+    int kind = 0;
+    int L = 0;
+    uint64_t nfull = 0, B = 0, rem = 0;            // kind 0
+    uint64_t P = 0, K = 0, T = 0, nseg = 0, items = 0;  // kind 1
+    const uint32_t *lane_tab = nullptr;  // kind 0: [64][18] A^(l*L)
+    const uint32_t *head_tab = nullptr;  // kind 0: [64][18] A^l
+    const uint32_t *table = nullptr;     // windowed jump tables
+    JumpMatrices J63 = {};               // kind 1: A^(63*P)
+    unsigned grid = 0;
+};
+hipError_t launch_partition(const uint32_t *planes, uint64_t plane_stride, uint64_t sidx,
+                            int dtype, const PartitionLaunch &pl, void *out, int engine,
+                            hipStream_t st);
+
 // Store-only bandwidth probes (probe.hip): pattern 0 streaming, 1 the
 // wave-per-stream fill's line geometry.
 hipError_t launch_write_probe(void *out, uint64_t bytes, int pattern, hipStream_t st);

@@ -9,6 +9,13 @@
 //                    row-segment stores                                  (sec. 5.2, Listing 1)
 //   fill_il_kernel   bulk generation, interleaved output (lane = stream,
 //                    consecutive lanes write consecutive elements)
+//   fill_coop_kernel bulk generation, stream-major output, GL lanes per
+//                    stream (sequence splitting inside each stream)
+//   random_init_kernel  random spacing: each stream from its own expanded
+//                    SplitMix64 draw                                     (sec. 2.3)
+//   fill_split_kernel   one stream's outputs in order, split into blocks
+//   fill_leap_kernel    leapfrog: one stream dealt to P players, each
+//                    player's cards in a row                            (sec. 2.3)
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -95,6 +102,19 @@ jumpu_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t firs
     planes[3 * plane_stride + idx] = b0;
     planes[4 * plane_stride + idx] = b1;
     planes[5 * plane_stride + idx] = b2;
+}
+
+// Random spacing (sec. 2.3): stream g = g0 + s starts at the state expanded
+// from SplitMix64 output g of the master seed.
+__global__ void __launch_bounds__(256)
+random_init_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t count,
+                   uint64_t g0, uint64_t master)
+{
+    const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= count) return;
+    uint32_t w[6];
+    expand_seed(splitmix64_mix(master + (g0 + s + 1) * kSplitMixGamma), w);
+    store_state(planes, plane_stride, s, w);
 }
 
 // ---------------------------------------------------------------------------
@@ -205,6 +225,102 @@ fill_coop_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t 
     }
 }
 
+// Sequence splitting of one stream (sec. 2.3): its outputs [0, N) in order as
+// blocks of B values (the last one rem values when rem > 0), block r starting
+// from A^(r*B) applied to the stream state (stream sidx of the planes) and
+// written by one wave with wave_fill (64 lanes, L values per lane per chunk).
+// Blocks are laid out XCD by XCD.  The stream state is not advanced here.
+template <int DT, int L, class G>
+__global__ void __launch_bounds__(64)
+fill_split_kernel(const uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t sidx,
+                  uint64_t nfull, uint64_t B, uint64_t rem, unsigned char *__restrict__ out,
+                  const uint32_t *__restrict__ lane_tab, const uint32_t *__restrict__ head_tab,
+                  const uint32_t *__restrict__ table)
+{
+    constexpr int ES = Elem<DT>::size;
+    __shared__ __attribute__((aligned(16))) unsigned char lds[64 * 144];
+    const int lane = threadIdx.x;
+    uint32_t m[18];
+#pragma unroll
+    for (int i = 0; i < 18; ++i) m[i] = lane_tab[lane * 18 + i];
+    uint32_t s0[6];
+    load_state(planes, plane_stride, sidx, s0);
+    const XcdRange R = xcd_range(nfull + (rem ? 1 : 0));
+    for (uint64_t r = R.first; r < R.end; r += R.step) {
+        uint32_t w[6] = {s0[0], s0[1], s0[2], s0[3], s0[4], s0[5]};
+        jump_global(table, r * B, 0, 0, 0, 16, w);
+        wave_fill<DT, L, G, true, 64>(w, m, lds, lane, out + r * B * ES, B * ES, 1, 0,
+                                      r < nfull ? B : rem, table, head_tab, false);
+    }
+}
+
+// Leapfrog (sec. 2.3) with each player's cards in a row: card k of player t
+// is output t + k*P of the stream (stream sidx of the planes) and goes to
+// out[t*K + k].  Lane j of a wave takes card column k = 64*kb + j, i.e. the
+// stream's outputs [k*P, k*P + P) in order, and writes them down its column,
+// so each store instruction covers 64 adjacent cards of one player.  Work
+// items are (column block kb, segment of T players); each workgroup takes a
+// contiguous run of the nkb * nseg items, jumps its lanes once
+// (A^(k*P + t0)) and from then on only continues: to the next segment by
+// stepping on, to the next column block by A^(63*P) (J63).  The stream state
+// is not advanced here.
+template <int DT, class G>
+__global__ void __launch_bounds__(64)
+fill_leap_kernel(const uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t sidx,
+                 uint64_t P, uint64_t K, uint64_t T, uint64_t nseg, uint64_t items,
+                 unsigned char *__restrict__ out, const uint32_t *__restrict__ table,
+                 JumpMatrices J63)
+{
+    constexpr int ES = Elem<DT>::size;
+    const uint64_t lane = threadIdx.x;
+    const uint64_t nb = gridDim.x, b = blockIdx.x;
+    const uint64_t q = items / nb, r = items % nb;
+    const uint64_t i0 = b * q + (b < r ? b : r);
+    const uint64_t i1 = i0 + q + (b < r ? 1 : 0);
+    if (i0 >= i1) return;
+    uint64_t kb = i0 / nseg, seg = i0 % nseg;
+    uint32_t w[6];
+    load_state(planes, plane_stride, sidx, w);
+    {
+        // lanes past the last column start anywhere in range and write nothing
+        const uint64_t k = kb * 64 + lane < K ? kb * 64 + lane : K - 1;
+        jump_global(table, k * P + seg * T, 0, 0, 0, 16, w);
+    }
+    G g;
+    g.load(w);
+    const uint64_t row = K * ES;
+    for (uint64_t it = i0; it < i1; ++it) {
+        if (it != i0 && seg == 0) {
+            // column k ended at output (k+1)*P; column k+64 starts at (k+64)*P
+            g.store(w);
+            matvec3<C1>(J63.m, w[0], w[1], w[2]);
+            matvec3<C2>(J63.m + 9, w[3], w[4], w[5]);
+            g.load(w);
+        }
+        const uint64_t k = kb * 64 + lane;
+        const uint64_t t0 = seg * T, t1 = t0 + T < P ? t0 + T : P;
+        if (k < K) {
+            unsigned char *p = out + (t0 * K + k) * ES;
+            uint64_t t = t0;
+            for (; t + 4 <= t1; t += 4) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    put1<DT>(p, g);
+                    p += row;
+                }
+            }
+            for (; t < t1; ++t) {
+                put1<DT>(p, g);
+                p += row;
+            }
+        }
+        if (++seg == nseg) {
+            seg = 0;
+            ++kb;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // launchers (host side)
 // ---------------------------------------------------------------------------
@@ -302,6 +418,59 @@ hipError_t launch_fill(uint32_t *planes, uint64_t plane_stride, uint64_t first, 
                                    tune.tile_bytes, st);
     return launch_fill_d<GenI>(planes, plane_stride, first, count, n, dtype, layout, out, fl,
                                tune.tile_bytes, st);
+}
+
+hipError_t launch_random_init(uint32_t *planes, uint64_t plane_stride, uint64_t count,
+                              uint64_t g0, uint64_t master, hipStream_t st)
+{
+    hipLaunchKernelGGL(random_init_kernel, dim3(grid_of(count, 256)), dim3(256), 0, st, planes,
+                       plane_stride, count, g0, master);
+    return hipGetLastError();
+}
+
+template <int DT, class G>
+static hipError_t launch_partition_g(const uint32_t *planes, uint64_t plane_stride, uint64_t sidx,
+                                     const PartitionLaunch &pl, void *out, hipStream_t st)
+{
+    unsigned char *o = (unsigned char *)out;
+    constexpr int TV = 128 / Elem<DT>::size;
+    if (pl.kind == 0) {
+        if (pl.L == TV)
+            hipLaunchKernelGGL((fill_split_kernel<DT, TV, G>), dim3(pl.grid), dim3(64), 0, st, planes,
+                               plane_stride, sidx, pl.nfull, pl.B, pl.rem, o, pl.lane_tab,
+                               pl.head_tab, pl.table);
+        else if (pl.L == 2 * TV)
+            hipLaunchKernelGGL((fill_split_kernel<DT, 2 * TV, G>), dim3(pl.grid), dim3(64), 0, st,
+                               planes, plane_stride, sidx, pl.nfull, pl.B, pl.rem, o, pl.lane_tab,
+                               pl.head_tab, pl.table);
+        else
+            return hipErrorInvalidValue;
+    } else {
+        hipLaunchKernelGGL((fill_leap_kernel<DT, G>), dim3(pl.grid), dim3(64), 0, st, planes,
+                           plane_stride, sidx, pl.P, pl.K, pl.T, pl.nseg, pl.items, o, pl.table,
+                           pl.J63);
+    }
+    return hipGetLastError();
+}
+
+template <class G>
+static hipError_t launch_partition_d(const uint32_t *planes, uint64_t plane_stride, uint64_t sidx,
+                                     int dtype, const PartitionLaunch &pl, void *out,
+                                     hipStream_t st)
+{
+    switch (dtype) {
+    case 0: return launch_partition_g<0, G>(planes, plane_stride, sidx, pl, out, st);
+    case 1: return launch_partition_g<1, G>(planes, plane_stride, sidx, pl, out, st);
+    default: return launch_partition_g<2, G>(planes, plane_stride, sidx, pl, out, st);
+    }
+}
+
+hipError_t launch_partition(const uint32_t *planes, uint64_t plane_stride, uint64_t sidx,
+                            int dtype, const PartitionLaunch &pl, void *out, int engine,
+                            hipStream_t st)
+{
+    if (engine == 1) return launch_partition_d<GenF>(planes, plane_stride, sidx, dtype, pl, out, st);
+    return launch_partition_d<GenI>(planes, plane_stride, sidx, dtype, pl, out, st);
 }
 
 }  // namespace mrg
