@@ -391,6 +391,26 @@ def main():
                                            "Gsamples_s": round(wl.C3_STREAMS * wl.C3_N / ms3 / 1e6, 2)}
         del out3
         ss3.close()
+        # the other partitions of sec. 2.3 over the same 2^32 uint32: one
+        # stream dealt to 2^16 players x 2^16 cards (in order, and each
+        # player's cards in a row), and random-spacing set creation
+        ssl = mg.StreamSet(1, master_seed=wl.MASTER_SEED)
+        outl = torch.empty(samples, dtype=torch.uint32, device="cuda")
+        for name, lay in (("leapfrog_in_order_2^16x2^16", mg.INTERLEAVED),
+                          ("leapfrog_player_rows_2^16x2^16", mg.STREAM_MAJOR)):
+            per_l, _ = timed(lambda: ssl.fill_leapfrog(0, 1 << 16, 1 << 16, mg.U32, lay, out=outl),
+                             10, 2, stream)
+            msl = sum(per_l) / len(per_l)
+            extra[name] = {"ms": round(msl, 4), "Gsamples_s": round(samples / msl / 1e6, 2),
+                           "hbm_frac": round(samples * 4 / msl / 1e6 / HBM_PEAK_GBS, 4)}
+        del outl
+        ssl.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ssr = mg.StreamSet(S, master_seed=wl.MASTER_SEED, spacing="random")
+        torch.cuda.synchronize()
+        extra["random_spacing_create_2^20_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
+        ssr.close()
     ss.close()
     torch.cuda.synchronize()
     if not args.quick and not args.no_batch:

@@ -554,7 +554,8 @@ mrg_status mrg_fill_leapfrog(mrg_streamset ss, uint64_t s, uint64_t players,
     mrg::PartitionLaunch pl;
     pl.table = ctx->d_table;
     const uint64_t slots = (uint64_t)ctx->cus * 16;  // resident one-wave workgroups
-    if (layout == MRG_INTERLEAVED) {
+    // with one player or one card per player both layouts are the stream in order
+    if (layout == MRG_INTERLEAVED || players == 1 || per_player == 1) {
         // the stream's outputs in order: blocks of 16-256 KiB (at least 4096
         // of them when the output allows), each a whole number of 128-line
         // chunks, one 64-lane wave per block
@@ -575,28 +576,37 @@ mrg_status mrg_fill_leapfrog(mrg_streamset ss, uint64_t s, uint64_t players,
         const uint64_t blocks = pl.nfull + (pl.rem ? 1 : 0);
         pl.grid = (unsigned)(blocks < ((uint64_t)1 << 31) - 1 ? blocks : ((uint64_t)1 << 31) - 1);
     } else {
-        // each player's cards in a row: items of 64 card columns x T players,
-        // T chosen for about 4 items per resident workgroup (at least 256)
+        // each player's cards in a row: items of KB = min(K, 64) card columns
+        // x T players (R = 64 / KB lanes per column, Ts = T / R players
+        // each), T chosen for about 4 items per resident workgroup (at least
+        // 256 players per lane)
+        mrg::LeapArgs &A = pl.leap;
         pl.kind = 1;
-        pl.P = players;
-        pl.K = per_player;
-        const uint64_t nkb = (per_player + 63) / 64;
+        A.P = players;
+        A.K = per_player;
+        A.KB = (int)(per_player < 64 ? per_player : 64);
+        A.R = 64 / A.KB;
+        const uint64_t nkb = (per_player + A.KB - 1) / A.KB;
         const uint64_t target = 4 * slots;
-        uint64_t T = players;
+        uint64_t Ts = (players + A.R - 1) / A.R;
         if (nkb < target) {
             const uint64_t segs = (target + nkb - 1) / nkb;
-            T = (players + segs - 1) / segs;
-            if (T < 256) T = 256;
-            if (T > players) T = players;
+            Ts = (players + segs * A.R - 1) / (segs * A.R);
+            if (Ts < 256) Ts = 256;
         }
-        pl.T = T;
-        pl.nseg = (players + T - 1) / T;
-        pl.items = nkb * pl.nseg;
-        pl.grid = (unsigned)(pl.items < slots ? pl.items : slots);
-        // 63 * players as a 192-bit exponent
+        const uint64_t ts_max = (players + A.R - 1) / A.R;
+        if (Ts > ts_max) Ts = ts_max;
+        A.Ts = Ts;
+        A.T = Ts * A.R;
+        A.nseg = (players + A.T - 1) / A.T;
+        A.items = nkb * A.nseg;
+        pl.grid = (unsigned)(A.items < slots ? A.items : slots);
+        // 63 * players and T - Ts as 192-bit exponents
         const unsigned __int128 e63 = (unsigned __int128)players * 63u;
         const uint64_t ew[3] = {(uint64_t)e63, (uint64_t)(e63 >> 64), 0};
-        pl.J63 = jump_matrices(ew);
+        A.J63 = jump_matrices(ew);
+        const uint64_t es_[3] = {A.T - A.Ts, 0, 0};
+        A.Jseg = jump_matrices(es_);
     }
     hipError_t e = mrg::launch_partition(ss->d_planes, ss->n, s, (int)dtype, pl, d_out,
                                          tune.engine, (hipStream_t)stream);

@@ -58,19 +58,28 @@ hipError_t launch_fill(uint32_t *planes, uint64_t plane_stride, uint64_t first, 
 hipError_t launch_random_init(uint32_t *planes, uint64_t plane_stride, uint64_t count,
                               uint64_t g0, uint64_t master, hipStream_t st);
 
+// Leapfrog with each player's cards in a row: P players, K cards each; work
+// items of KB = min(K, 64) card columns x T = R*Ts players (R = 64 / KB lanes
+// per column), nseg segments per column block, items = column blocks x nseg.
+struct LeapArgs {
+    uint64_t P = 0, K = 0, T = 0, Ts = 0, nseg = 0, items = 0;
+    int KB = 64, R = 1;
+    JumpMatrices J63 = {};   // A^(63*P): to the next column block (R = 1)
+    JumpMatrices Jseg = {};  // A^(T - Ts): to the next segment (R > 1)
+};
+
 // One stream partitioned (chosen on the host): kind 0 writes its outputs
 // [0, nfull*B + rem) in order, in blocks of B values (64 lanes per block, L
-// values per lane per chunk); kind 1 deals them to P players, K cards each,
-// each player's cards in a row (work items of 64 card columns x T players).
+// values per lane per chunk); kind 1 deals them to players, each player's
+// cards in a row.
 struct PartitionLaunch {
     int kind = 0;
     int L = 0;
-    uint64_t nfull = 0, B = 0, rem = 0;            // kind 0
-    uint64_t P = 0, K = 0, T = 0, nseg = 0, items = 0;  // kind 1
+    uint64_t nfull = 0, B = 0, rem = 0;  // kind 0
+    LeapArgs leap;                       // kind 1
     const uint32_t *lane_tab = nullptr;  // kind 0: [64][18] A^(l*L)
     const uint32_t *head_tab = nullptr;  // kind 0: [64][18] A^l
     const uint32_t *table = nullptr;     // windowed jump tables
-    JumpMatrices J63 = {};               // kind 1: A^(63*P)
     unsigned grid = 0;
 };
 hipError_t launch_partition(const uint32_t *planes, uint64_t plane_stride, uint64_t sidx,

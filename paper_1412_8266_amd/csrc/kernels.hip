@@ -256,51 +256,63 @@ fill_split_kernel(const uint32_t *__restrict__ planes, uint64_t plane_stride, ui
 
 // Leapfrog (sec. 2.3) with each player's cards in a row: card k of player t
 // is output t + k*P of the stream (stream sidx of the planes) and goes to
-// out[t*K + k].  Lane j of a wave takes card column k = 64*kb + j, i.e. the
-// stream's outputs [k*P, k*P + P) in order, and writes them down its column,
-// so each store instruction covers 64 adjacent cards of one player.  Work
-// items are (column block kb, segment of T players); each workgroup takes a
-// contiguous run of the nkb * nseg items, jumps its lanes once
-// (A^(k*P + t0)) and from then on only continues: to the next segment by
-// stepping on, to the next column block by A^(63*P) (J63).  The stream state
-// is not advanced here.
+// out[t*K + k].  A column block is KB = min(K, 64) card columns; lane
+// l < R*KB (R = 64 / KB) takes column k = KB*kb + l % KB and sub-segment
+// r = l / KB of each segment of T = R*Ts players, i.e. the stream's outputs
+// [k*P + t0 + r*Ts, ... + Ts) in order, written down its column: a store
+// instruction covers R runs of KB adjacent cards (64 adjacent cards when
+// K >= 64).  Work items are (column block kb, segment); each workgroup takes
+// a contiguous run of the nkb * nseg items, jumps its lanes once (A^(k*P +
+// t0 + r*Ts)) and from then on only continues: to the next segment by
+// A^(T - Ts) (Jseg; stepping on when R = 1), to the next column block by
+// A^(63*P) (J63; only with R = 1, since K < 64 leaves one column block).  The
+// stream state is not advanced here.
 template <int DT, class G>
 __global__ void __launch_bounds__(64)
 fill_leap_kernel(const uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t sidx,
-                 uint64_t P, uint64_t K, uint64_t T, uint64_t nseg, uint64_t items,
-                 unsigned char *__restrict__ out, const uint32_t *__restrict__ table,
-                 JumpMatrices J63)
+                 LeapArgs A, unsigned char *__restrict__ out, const uint32_t *__restrict__ table)
 {
     constexpr int ES = Elem<DT>::size;
     const uint64_t lane = threadIdx.x;
     const uint64_t nb = gridDim.x, b = blockIdx.x;
-    const uint64_t q = items / nb, r = items % nb;
-    const uint64_t i0 = b * q + (b < r ? b : r);
-    const uint64_t i1 = i0 + q + (b < r ? 1 : 0);
-    if (i0 >= i1) return;
-    uint64_t kb = i0 / nseg, seg = i0 % nseg;
+    const uint64_t q = A.items / nb, rr = A.items % nb;
+    const uint64_t i0 = b * q + (b < rr ? b : rr);
+    const uint64_t i1 = i0 + q + (b < rr ? 1 : 0);
+    if (i0 >= i1 || lane >= (uint64_t)A.R * A.KB) return;
+    const uint64_t kl = lane % A.KB, r = lane / A.KB;
+    uint64_t kb = i0 / A.nseg, seg = i0 % A.nseg;
     uint32_t w[6];
     load_state(planes, plane_stride, sidx, w);
     {
         // lanes past the last column start anywhere in range and write nothing
-        const uint64_t k = kb * 64 + lane < K ? kb * 64 + lane : K - 1;
-        jump_global(table, k * P + seg * T, 0, 0, 0, 16, w);
+        const uint64_t k = kb * A.KB + kl < A.K ? kb * A.KB + kl : A.K - 1;
+        const uint64_t t = seg * A.T + r * A.Ts < A.P ? seg * A.T + r * A.Ts : A.P - 1;
+        jump_global(table, k * A.P + t, 0, 0, 0, 16, w);
     }
     G g;
     g.load(w);
-    const uint64_t row = K * ES;
+    const uint64_t row = A.K * ES;
     for (uint64_t it = i0; it < i1; ++it) {
-        if (it != i0 && seg == 0) {
-            // column k ended at output (k+1)*P; column k+64 starts at (k+64)*P
-            g.store(w);
-            matvec3<C1>(J63.m, w[0], w[1], w[2]);
-            matvec3<C2>(J63.m + 9, w[3], w[4], w[5]);
-            g.load(w);
+        if (it != i0) {
+            if (seg == 0) {
+                // column k ended at output (k+1)*P; column k+64 starts at (k+64)*P
+                g.store(w);
+                matvec3<C1>(A.J63.m, w[0], w[1], w[2]);
+                matvec3<C2>(A.J63.m + 9, w[3], w[4], w[5]);
+                g.load(w);
+            } else if (A.R > 1) {
+                // sub-segment r ended at t0 + (r+1)*Ts; the next one starts T - Ts on
+                g.store(w);
+                matvec3<C1>(A.Jseg.m, w[0], w[1], w[2]);
+                matvec3<C2>(A.Jseg.m + 9, w[3], w[4], w[5]);
+                g.load(w);
+            }
         }
-        const uint64_t k = kb * 64 + lane;
-        const uint64_t t0 = seg * T, t1 = t0 + T < P ? t0 + T : P;
-        if (k < K) {
-            unsigned char *p = out + (t0 * K + k) * ES;
+        const uint64_t k = kb * A.KB + kl;
+        const uint64_t t0 = seg * A.T + r * A.Ts;
+        const uint64_t t1 = t0 + A.Ts < A.P ? t0 + A.Ts : A.P;
+        if (k < A.K && t0 < t1) {
+            unsigned char *p = out + (t0 * A.K + k) * ES;
             uint64_t t = t0;
             for (; t + 4 <= t1; t += 4) {
 #pragma unroll
@@ -314,7 +326,7 @@ fill_leap_kernel(const uint32_t *__restrict__ planes, uint64_t plane_stride, uin
                 p += row;
             }
         }
-        if (++seg == nseg) {
+        if (++seg == A.nseg) {
             seg = 0;
             ++kb;
         }
@@ -447,8 +459,7 @@ static hipError_t launch_partition_g(const uint32_t *planes, uint64_t plane_stri
             return hipErrorInvalidValue;
     } else {
         hipLaunchKernelGGL((fill_leap_kernel<DT, G>), dim3(pl.grid), dim3(64), 0, st, planes,
-                           plane_stride, sidx, pl.P, pl.K, pl.T, pl.nseg, pl.items, o, pl.table,
-                           pl.J63);
+                           plane_stride, sidx, pl.leap, o, pl.table);
     }
     return hipGetLastError();
 }

@@ -77,7 +77,8 @@ def test_random_spacing_fill(mg, engine):
 # leapfrog
 # --------------------------------------------------------------------------
 DEALS = [(1, 1), (1, 5000), (5000, 1), (64, 64), (100, 77), (3, 7000), (1000, 1000),
-         (257, 130), (70000, 3)]
+         (257, 130), (70000, 3), (1000, 5), (4097, 63), (10000, 2), (777, 32), (123457, 17),
+         (65, 33)]
 
 
 @pytest.mark.parametrize("players,per_player", DEALS, ids=["%dx%d" % d for d in DEALS])
@@ -138,9 +139,10 @@ def card(state, players, t, k, dtype):
 
 @pytest.mark.parametrize("players,per_player,layout,dtype",
                          [(1 << 14, 1 << 14, 0, 0), (1 << 10, 1 << 18, 1, 0),
-                          (12345, 6789, 0, 1), (1 << 20, 100, 1, 2)],
+                          (12345, 6789, 0, 1), (1 << 20, 100, 1, 2), (1 << 24, 5, 0, 0),
+                          ((1 << 22) + 3, 48, 0, 2)],
                          ids=["rows-2^28-u32", "in-order-2^28-u32", "rows-ragged-f32",
-                              "in-order-f64"])
+                              "in-order-f64", "rows-5-cards-u32", "rows-48-cards-f64"])
 def test_leapfrog_large_sampled(mg, players, per_player, layout, dtype):
     say("leapfrog large", players, per_player, layout, dtype)
     rng = np.random.default_rng(17)
