@@ -84,6 +84,18 @@ def _load():
         lib.orc_splitmix64_at.restype = u64
         lib.orc_random_spacing.argtypes = [u64, u64, u64, P]
         lib.orc_random_spacing.restype = None
+        lib.orc_philox_constants.argtypes = [P]
+        lib.orc_philox4x32_10.argtypes = [P, P, P]
+        lib.orc_philox_next.argtypes = [P]
+        lib.orc_philox_next.restype = ctypes.c_uint32
+        lib.orc_philox_to_f32.argtypes = [ctypes.c_uint32]
+        lib.orc_philox_to_f32.restype = ctypes.c_float
+        lib.orc_philox_to_f64.argtypes = [ctypes.c_uint32]
+        lib.orc_philox_to_f64.restype = ctypes.c_double
+        lib.orc_philox_fill.argtypes = [P, u64, u64, ctypes.c_int, ctypes.c_int, P]
+        lib.orc_philox_fill.restype = None
+        lib.orc_philox_streams.argtypes = [u64, u64, u64, P]
+        lib.orc_philox_streams.restype = None
         lib.orc_state_valid.argtypes = [P]
         lib.orc_state_valid.restype = ctypes.c_int
         _lib = lib
@@ -242,6 +254,64 @@ def leapfrog(state, players: int, per_player: int, dtype: int = U32,
     if layout == STREAM_MAJOR:
         dealt = np.ascontiguousarray(dealt.T)
     return dealt, end.reshape(6)
+
+
+# --------------------------------------------------------------------------
+# Philox4x32-10 streams.  A state is (position lo, hi, stream id lo, hi,
+# key lo, hi); output number `position` is word position % 4 of the block
+# whose counter is (position // 4, stream id).
+# --------------------------------------------------------------------------
+def philox_constants() -> list:
+    """[M0, M1, W0, W1]: the two round multipliers and the two Weyl key
+    increments."""
+    out = np.zeros(4, dtype=np.uint32)
+    _load().orc_philox_constants(_ptr(out))
+    return [int(v) for v in out]
+
+
+def philox4x32_10(ctr, key) -> list:
+    c = np.ascontiguousarray(np.asarray(ctr, dtype=np.uint32).reshape(4))
+    k = np.ascontiguousarray(np.asarray(key, dtype=np.uint32).reshape(2))
+    out = np.zeros(4, dtype=np.uint32)
+    _load().orc_philox4x32_10(_ptr(c), _ptr(k), _ptr(out))
+    return [int(v) for v in out]
+
+
+def philox_streams(key: int, first: int, count: int) -> np.ndarray:
+    out = np.zeros((count, 6), dtype=np.uint32)
+    if count:
+        _load().orc_philox_streams(int(key), int(first), int(count), _ptr(out))
+    return out
+
+
+def philox_to_f32(w: int) -> float:
+    return float(np.float32(_load().orc_philox_to_f32(int(w))))
+
+
+def philox_to_f64(w: int) -> float:
+    return float(_load().orc_philox_to_f64(int(w)))
+
+
+def philox_fill(states, n: int, dtype: int = U32, layout: int = STREAM_MAJOR):
+    """As ``fill`` for Philox stream states."""
+    st = np.ascontiguousarray(np.array(states, dtype=np.uint32, copy=True).reshape(-1, 6))
+    S = st.shape[0]
+    shape = (S, n) if layout == STREAM_MAJOR else (n, S)
+    out = np.empty(shape, dtype=_DTYPES[dtype])
+    _load().orc_philox_fill(_ptr(st), S, n, dtype, layout, _ptr(out) if out.size else None)
+    return out, st
+
+
+def philox_jump(states, e) -> np.ndarray:
+    """Philox states moved e outputs ahead (e an int, or one per state); the
+    position wraps at 2^64."""
+    st = np.array(states, dtype=np.uint32, copy=True).reshape(-1, 6)
+    es = [int(e)] * st.shape[0] if isinstance(e, (int, np.integer)) else [int(x) for x in e]
+    for i, x in enumerate(es):
+        pos = (int(st[i, 0]) | int(st[i, 1]) << 32) + x
+        pos &= (1 << 64) - 1
+        st[i, 0], st[i, 1] = pos & 0xFFFFFFFF, pos >> 32
+    return st
 
 
 def state_valid(state) -> bool:

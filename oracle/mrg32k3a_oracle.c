@@ -272,3 +272,99 @@ int orc_state_valid(const uint32_t s[6])
     if ((s[0] | s[1] | s[2]) == 0 || (s[3] | s[4] | s[5]) == 0) return 0;
     return 1;
 }
+
+/* ---------------------------------------------------------------------- */
+/* Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC 2011), the counter-based  */
+/* family the paper embeds beside MRG32k3a: ten rounds of a multiply-and-  */
+/* xor bijection of a 128-bit counter under a 64-bit key.  Each round      */
+/* multiplies counter words 0 and 2 by the two multipliers, keeps the low  */
+/* halves as the new words 3 and 1, and xors the high halves with the      */
+/* other two words and the round key into the new words 2 and 0.  The      */
+/* round key starts at the key and moves by the two Weyl increments        */
+/* between rounds.                                                         */
+/* ---------------------------------------------------------------------- */
+#define ORC_PHILOX_M0 0xD2511F53u
+#define ORC_PHILOX_M1 0xCD9E8D57u
+#define ORC_PHILOX_W0 0x9E3779B9u
+#define ORC_PHILOX_W1 0xBB67AE85u
+
+void orc_philox_constants(uint32_t out[4])
+{
+    out[0] = ORC_PHILOX_M0;
+    out[1] = ORC_PHILOX_M1;
+    out[2] = ORC_PHILOX_W0;
+    out[3] = ORC_PHILOX_W1;
+}
+
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int r = 0; r < 10; ++r) {
+        if (r > 0) {
+            k0 += ORC_PHILOX_W0;
+            k1 += ORC_PHILOX_W1;
+        }
+        uint64_t p0 = (uint64_t)ORC_PHILOX_M0 * c0;
+        uint64_t p1 = (uint64_t)ORC_PHILOX_M1 * c2;
+        uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        uint32_t n1 = (uint32_t)p1;
+        uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        uint32_t n3 = (uint32_t)p0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* A Philox stream's 6 state words: (position lo, hi, stream id lo, hi, key lo,
+ * hi).  Output number `position` is word position % 4 of the block with
+ * counter (position / 4 as two words, stream id as two words). */
+uint32_t orc_philox_next(uint32_t st[6])
+{
+    uint64_t pos = (uint64_t)st[0] | (uint64_t)st[1] << 32;
+    uint64_t b = pos >> 2;
+    uint32_t ctr[4] = {(uint32_t)b, (uint32_t)(b >> 32), st[2], st[3]};
+    uint32_t key[2] = {st[4], st[5]};
+    uint32_t w[4];
+    orc_philox4x32_10(ctr, key, w);
+    uint32_t z = w[pos & 3];
+    pos += 1;
+    st[0] = (uint32_t)pos;
+    st[1] = (uint32_t)(pos >> 32);
+    return z;
+}
+
+/* Conversions of a 32-bit word: odd multiples of 2^-24 from its top 23 bits
+ * (binary32) and of 2^-33 from all 32 (binary64), both exact (24 and 33
+ * significant bits) and inside (0, 1). */
+float orc_philox_to_f32(uint32_t w) { return (float)(2u * (w >> 9) + 1u) * 0x1p-24f; }
+double orc_philox_to_f64(uint32_t w) { return ((double)w * 2.0 + 1.0) * 0x1p-33; }
+
+void orc_philox_fill(uint32_t *states, uint64_t S, uint64_t n, int dtype, int layout, void *out)
+{
+    for (uint64_t s = 0; s < S; ++s) {
+        uint32_t *st = states + 6 * s;
+        for (uint64_t k = 0; k < n; ++k) {
+            uint32_t w = orc_philox_next(st);
+            uint64_t idx = (layout == ORC_STREAM_MAJOR) ? s * n + k : k * S + s;
+            if (dtype == ORC_U32)      ((uint32_t *)out)[idx] = w;
+            else if (dtype == ORC_F32) ((float *)out)[idx] = orc_philox_to_f32(w);
+            else                       ((double *)out)[idx] = orc_philox_to_f64(w);
+        }
+    }
+}
+
+/* Stream g of a Philox set under `key` starts at position 0 with id g. */
+void orc_philox_streams(uint64_t key, uint64_t first, uint64_t count, uint32_t *out)
+{
+    for (uint64_t i = 0; i < count; ++i) {
+        uint64_t g = first + i;
+        uint32_t *st = out + 6 * i;
+        st[0] = 0;
+        st[1] = 0;
+        st[2] = (uint32_t)g;
+        st[3] = (uint32_t)(g >> 32);
+        st[4] = (uint32_t)key;
+        st[5] = (uint32_t)(key >> 32);
+    }
+}

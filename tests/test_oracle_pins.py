@@ -19,7 +19,11 @@ Nothing here compares the oracle with a retyped copy of itself.  The pins are:
 * the two partitions of one sequence in sec. 2.3 beside sequence splitting:
   random spacing (each stream from its own expanded SplitMix64 draw) and the
   leapfrog deal (every card checked against the big-integer jump of
-  ``oracle/ref.py``).
+  ``oracle/ref.py``);
+* Philox4x32-10: the Weyl key increments derived from sqrt(5) and sqrt(3),
+  and the round wiring, key schedule and round count through an inverse
+  written here from the round structure.  The two round multipliers have no
+  closed form and no known-answer file is available: parity unpinned.
 """
 import math
 import os
@@ -438,6 +442,86 @@ def test_leapfrog_floats_follow_the_integers():
     d, _ = oracle.leapfrog(seed, 11, 4, oracle.F64, oracle.INTERLEAVED)
     assert np.array_equal(f, np.vectorize(oracle.to_f32)(u).astype(np.float32))
     assert np.array_equal(d, np.vectorize(oracle.to_f64)(u.T))
+
+
+# --------------------------------------------------------------------------
+# Philox4x32-10 (the counter-based second generator)
+# --------------------------------------------------------------------------
+def test_philox_weyl_increments_are_golden_ratio_and_sqrt3():
+    M0, M1, W0, W1 = oracle.philox_constants()
+    # floor(2^32 (sqrt(5) - 1) / 2) and floor(2^32 (sqrt(3) - 1)), exactly
+    assert W0 == (math.isqrt(5 << 64) - (1 << 32)) // 2
+    assert W1 == math.isqrt(3 << 64) - (1 << 32)
+    # the multipliers must be odd for each round to be a bijection; their
+    # values (found by search in Salmon et al.) have no closed form here
+    assert M0 % 2 == 1 and M1 % 2 == 1
+
+
+def philox_inverse(out, key, rounds=10):
+    """Undo Philox4x32 rounds, written from the round structure: the low
+    halves of the two products are the new words 3 and 1, so the old words 0
+    and 2 come back by multiplying with the multipliers' inverses mod 2^32;
+    the high halves then unmask the old words 3 and 1."""
+    M0, M1, W0, W1 = oracle.philox_constants()
+    inv0, inv1 = pow(M0, -1, 1 << 32), pow(M1, -1, 1 << 32)
+    n0, n1, n2, n3 = [int(v) for v in out]
+    for r in reversed(range(rounds)):
+        k0 = (key[0] + r * W0) & 0xFFFFFFFF
+        k1 = (key[1] + r * W1) & 0xFFFFFFFF
+        c0 = (n3 * inv0) & 0xFFFFFFFF
+        c2 = (n1 * inv1) & 0xFFFFFFFF
+        c3 = n2 ^ ((M0 * c0) >> 32) ^ k1
+        c1 = n0 ^ ((M1 * c2) >> 32) ^ k0
+        n0, n1, n2, n3 = c0, c1, c2, c3
+    return [n0, n1, n2, n3]
+
+
+def test_philox_rounds_are_undone_by_the_inverse():
+    rng = random.Random(1412)
+    for _ in range(300):
+        ctr = [rng.getrandbits(32) for _ in range(4)]
+        key = [rng.getrandbits(32) for _ in range(2)]
+        out = oracle.philox4x32_10(ctr, key)
+        assert philox_inverse(out, key) == ctr
+        assert philox_inverse(out, key, rounds=9) != ctr
+
+
+def test_philox_streams_fill_and_jump():
+    key = 0x0123456789ABCDEF
+    st = oracle.philox_streams(key, 2**40, 3)
+    assert [int(v) for v in st[1]] == [0, 0, (2**40 + 1) & 0xFFFFFFFF, (2**40 + 1) >> 32,
+                                       key & 0xFFFFFFFF, key >> 32]
+    out, end = oracle.philox_fill(st, 11, oracle.U32)
+    for s in range(3):
+        words = []
+        for b in range(3):
+            words += oracle.philox4x32_10([b, 0, int(st[s, 2]), int(st[s, 3])],
+                                          [int(st[s, 4]), int(st[s, 5])])
+        assert [int(v) for v in out[s]] == words[:11]
+        assert int(end[s, 0]) == 11 and int(end[s, 1]) == 0
+    # a jump equals drawing: positions 5.. of a longer fill
+    j = oracle.philox_jump(st, 5)
+    tail, _ = oracle.philox_fill(j, 6, oracle.U32)
+    assert np.array_equal(tail, out[:, 5:])
+    # the position carries into its high word, and wraps at 2^64
+    hi = oracle.philox_jump(st, 2**32 + 7)
+    assert [int(hi[0, 0]), int(hi[0, 1])] == [7, 1]
+    wrap = oracle.philox_jump(oracle.philox_jump(st, 2**64 - 1), 1)
+    assert np.array_equal(wrap, st)
+
+
+def test_philox_conversions_are_exact_and_open():
+    for w in (0, 1, 255, 256, 2**31, 2**32 - 1, 123456789):
+        f = oracle.philox_to_f32(w)
+        d = oracle.philox_to_f64(w)
+        assert Fraction(f) * 2**24 == 2 * (w >> 9) + 1 and 0 < f < 1
+        assert Fraction(d) * 2**33 == 2 * w + 1 and 0 < d < 1
+    st = oracle.philox_streams(9, 0, 2)
+    u, _ = oracle.philox_fill(st, 40, oracle.U32)
+    f, _ = oracle.philox_fill(st, 40, oracle.F32)
+    d, _ = oracle.philox_fill(st, 40, oracle.F64, oracle.INTERLEAVED)
+    assert np.array_equal(f, np.vectorize(oracle.philox_to_f32)(u).astype(np.float32))
+    assert np.array_equal(d, np.vectorize(oracle.philox_to_f64)(u.T))
 
 
 # --------------------------------------------------------------------------
