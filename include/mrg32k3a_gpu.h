@@ -101,6 +101,22 @@ mrg_status mrg_streamset_create_random(mrg_streamset *out, uint64_t n_streams,
                                        uint64_t first_stream, uint64_t master_seed,
                                        void *stream);
 
+/* A stream set of the counter-based generator Philox4x32-10 (Salmon, Moraes,
+ * Dror & Shaw, SC 2011), the third family the paper embeds.  Stream g
+ * (global index) has the 6 state words (position lo, hi, g lo, hi, key lo,
+ * hi), position 0 at creation; its output number p is word p % 4 of the
+ * ten-round Philox block of counter (p / 4 as two words, g as two words)
+ * under `key`.  uint32 outputs are those words (all of [0, 2^32)); FP32 is
+ * (2*(w >> 9) + 1) * 2^-24 and FP64 (2*w + 1) * 2^-33 (exact, in (0, 1)).
+ * mrg_fill, mrg_jump and mrg_jump_uniform work on such a set (a jump by e
+ * adds e mod 2^64 to the position), as do mrg_get_states / mrg_set_states
+ * (any 6 words are a state).  Substream jumps, leapfrog, batches and
+ * mrg::Stream are MRG32k3a only and return MRG_EINVAL.  Sizes, errors and
+ * ownership as mrg_streamset_create; mrg_streamset_info reports an all-zero
+ * seed6. */
+mrg_status mrg_streamset_create_philox(mrg_streamset *out, uint64_t n_streams,
+                                       uint64_t first_stream, uint64_t key, void *stream);
+
 /* Release the stream set and its device memory (sec. 5.1 release()).
  * Synchronises the device work the library enqueued on the set first.
  * NULL is accepted and ignored. */

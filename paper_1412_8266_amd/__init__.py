@@ -54,19 +54,28 @@ class StreamSet:
     ``seed`` (6 words) or is expanded from ``master_seed`` (64 bits).  With
     ``spacing="random"`` (and a master seed) stream g instead starts at its
     own random state, expanded from SplitMix64 output g of the master seed
-    (random spacing, sec. 2.3).
+    (random spacing, sec. 2.3).  With ``generator="philox"`` the streams are
+    Philox4x32-10 streams under the key ``master_seed`` (stream g: counter
+    words 2-3 = g).
     """
 
     def __init__(self, n_streams: int, seed=None, master_seed: Optional[int] = None,
-                 first_stream: int = 0, stream=None, spacing: str = "jump"):
+                 first_stream: int = 0, stream=None, spacing: str = "jump",
+                 generator: str = "mrg32k3a"):
         if (seed is None) == (master_seed is None):
             raise ValueError("give exactly one of seed (6 words) or master_seed")
         if spacing not in ("jump", "random"):
             raise ValueError("spacing must be 'jump' or 'random'")
-        if spacing == "random" and master_seed is None:
-            raise ValueError("random spacing draws its states from a master_seed")
+        if generator not in ("mrg32k3a", "philox"):
+            raise ValueError("generator must be 'mrg32k3a' or 'philox'")
+        if (spacing == "random" or generator == "philox") and master_seed is None:
+            raise ValueError("random spacing and Philox take a master_seed")
+        if generator == "philox" and spacing != "jump":
+            raise ValueError("Philox streams are spaced by their counters")
         h = _stream_handle(stream)
-        if seed is not None:
+        if generator == "philox":
+            self._h = _abi.mrg_streamset_create_philox(n_streams, first_stream, master_seed, h)
+        elif seed is not None:
             self._h = _abi.mrg_streamset_create(n_streams, first_stream, seed, h)
         elif spacing == "random":
             self._h = _abi.mrg_streamset_create_random(n_streams, first_stream, master_seed, h)

@@ -53,6 +53,7 @@ _SIGS = {
     "mrg_streamset_create": [ctypes.POINTER(_P), _U64, _U64, _PU32, _P],
     "mrg_streamset_create_seed64": [ctypes.POINTER(_P), _U64, _U64, _U64, _P],
     "mrg_streamset_create_random": [ctypes.POINTER(_P), _U64, _U64, _U64, _P],
+    "mrg_streamset_create_philox": [ctypes.POINTER(_P), _U64, _U64, _U64, _P],
     "mrg_streamset_destroy": [_P],
     "mrg_streamset_info": [_P, _PU64, _PU64, _PU32],
     "mrg_streamset_states_ptr": [_P, ctypes.POINTER(_P)],
@@ -201,6 +202,14 @@ def mrg_streamset_create_random(n_streams: int, first_stream: int, master_seed: 
     h = _P()
     _call("mrg_streamset_create_random", ctypes.byref(h), n_streams, first_stream,
           master_seed & ((1 << 64) - 1), stream)
+    return h.value
+
+
+def mrg_streamset_create_philox(n_streams: int, first_stream: int, key: int,
+                                stream: int = 0) -> int:
+    h = _P()
+    _call("mrg_streamset_create_philox", ctypes.byref(h), n_streams, first_stream,
+          key & ((1 << 64) - 1), stream)
     return h.value
 
 

@@ -346,6 +346,7 @@ mrg_status mrg_batch_create(mrg_batch *out, mrg_streamset ss, const mrg_request 
     *out = nullptr;
     mrg_status st = mrg::check_streamset(ss);
     if (st) return st;
+    if (ss->gen != 0) return set_error(MRG_EINVAL, "batches take MRG32k3a stream sets only");
     if (n_reqs && !reqs) return set_error(MRG_EINVAL, "null request array");
     if (n_reqs >= ((uint64_t)1 << 31)) return set_error(MRG_ERANGE, "too many requests");
     if ((st = validate(ss, reqs, n_reqs))) return st;

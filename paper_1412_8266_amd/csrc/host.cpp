@@ -384,6 +384,27 @@ mrg_status mrg_streamset_create_random(mrg_streamset *out, uint64_t n_streams,
     return MRG_OK;
 }
 
+mrg_status mrg_streamset_create_philox(mrg_streamset *out, uint64_t n_streams,
+                                       uint64_t first_stream, uint64_t key, void *stream)
+{
+    if (!out) return set_error(MRG_EINVAL, "null argument");
+    *out = nullptr;
+    mrg_streamset ss;
+    DevCtx *ctx;
+    mrg_status st = new_streamset(n_streams, first_stream, &ss, &ctx);
+    if (st) return st;
+    ss->gen = 1;
+    hipError_t e = mrg::launch_philox_init(ss->d_planes, n_streams, n_streams, first_stream, key,
+                                           (hipStream_t)stream);
+    if (e != hipSuccess) {
+        (void)hipFree(ss->d_planes);
+        delete ss;
+        return hip_error(e, "philox init kernel launch");
+    }
+    *out = ss;
+    return MRG_OK;
+}
+
 mrg_status mrg_streamset_destroy(mrg_streamset ss)
 {
     if (!ss) return MRG_OK;
@@ -438,6 +459,11 @@ mrg_status mrg_jump(mrg_streamset ss, uint64_t first, uint64_t count, const uint
     if ((st = check_range(ss, first, count))) return st;
     if (count == 0) return MRG_OK;
     if (!d_exp) return set_error(MRG_EINVAL, "null exponent array");
+    if (ss->gen == 1) {  // the position moves by e mod 2^64
+        hipError_t e = mrg::launch_philox_jump(ss->d_planes, ss->n, first, count, d_exp, 0,
+                                               (hipStream_t)stream);
+        return e == hipSuccess ? MRG_OK : hip_error(e, "jump kernel launch");
+    }
     DevCtx *ctx;
     if ((st = device_ctx(ss->device, &ctx))) return st;
     hipError_t e = mrg::launch_jump(ss->d_planes, ss->n, first, count, d_exp, ctx->d_table,
@@ -453,6 +479,11 @@ mrg_status mrg_jump_uniform(mrg_streamset ss, uint64_t first, uint64_t count,
     if ((st = check_range(ss, first, count))) return st;
     if (!h_exp) return set_error(MRG_EINVAL, "null exponent");
     if (count == 0) return MRG_OK;
+    if (ss->gen == 1) {
+        hipError_t e = mrg::launch_philox_jump(ss->d_planes, ss->n, first, count, nullptr,
+                                               h_exp[0], (hipStream_t)stream);
+        return e == hipSuccess ? MRG_OK : hip_error(e, "jump kernel launch");
+    }
     hipError_t e = mrg::launch_jump_uniform(ss->d_planes, ss->n, first, count,
                                             jump_matrices(h_exp), (hipStream_t)stream);
     return e == hipSuccess ? MRG_OK : hip_error(e, "jump kernel launch");
@@ -461,6 +492,8 @@ mrg_status mrg_jump_uniform(mrg_streamset ss, uint64_t first, uint64_t count,
 mrg_status mrg_jump_substreams(mrg_streamset ss, uint64_t first, uint64_t count, uint64_t k,
                                void *stream)
 {
+    if (ss && ss->gen == 1)
+        return set_error(MRG_EINVAL, "substreams are defined for MRG32k3a stream sets only");
     // k * 2^76 = (k << 12) * 2^64 + (k >> 52) * 2^128
     const uint64_t e[3] = {0, k << 12, k >> 52};
     return mrg_jump_uniform(ss, first, count, e, stream);
@@ -482,6 +515,14 @@ mrg_status mrg_fill(mrg_streamset ss, uint64_t first, uint64_t count, uint64_t n
     if ((uintptr_t)d_out % es) return set_error(MRG_EINVAL, "output not aligned to its element size");
     if (n_per_stream > UINT64_MAX / es / count)
         return set_error(MRG_ERANGE, "output size overflows 64 bits");
+    if (ss->gen == 1) {
+        hipError_t e = mrg::launch_philox_fill(ss->d_planes, ss->n, first, count, n_per_stream,
+                                               (int)dtype, (int)layout, d_out, (hipStream_t)stream);
+        if (e == hipSuccess)
+            e = mrg::launch_philox_jump(ss->d_planes, ss->n, first, count, nullptr, n_per_stream,
+                                        (hipStream_t)stream);
+        return e == hipSuccess ? MRG_OK : hip_error(e, "philox fill kernel launch");
+    }
     const mrg::FillTuning tune = tuning();
     mrg::FillLaunch fl;
     if (layout == MRG_STREAM_MAJOR) {
@@ -541,6 +582,8 @@ mrg_status mrg_fill_leapfrog(mrg_streamset ss, uint64_t s, uint64_t players,
         return set_error(MRG_EINVAL, "unknown dtype %d", (int)dtype);
     if (layout != MRG_STREAM_MAJOR && layout != MRG_INTERLEAVED)
         return set_error(MRG_EINVAL, "unknown layout %d", (int)layout);
+    if (ss->gen == 1)
+        return set_error(MRG_EINVAL, "leapfrog is defined for MRG32k3a stream sets only");
     if (players == 0 || per_player == 0) return MRG_OK;
     if (!d_out) return set_error(MRG_EINVAL, "null output");
     const uint64_t es = dtype == MRG_F64 ? 8 : 4;
@@ -646,7 +689,7 @@ mrg_status mrg_set_states(mrg_streamset ss, uint64_t first, uint64_t count, cons
     if ((st = check_range(ss, first, count))) return st;
     if (count == 0) return MRG_OK;
     if (!h_in) return set_error(MRG_EINVAL, "null input");
-    for (uint64_t i = 0; i < count; ++i)
+    for (uint64_t i = 0; ss->gen == 0 && i < count; ++i)  // any 6 words are a Philox state
         if (!state_ok(h_in + 6 * i))
             return set_error(MRG_EINVAL, "state %llu is not a valid MRG32k3a state",
                         (unsigned long long)i);

@@ -11,6 +11,7 @@ struct mrg_streamset_s {
     uint64_t n = 0;                // streams in the set
     uint64_t first = 0;            // global index of stream 0 of the set
     uint32_t seed[6] = {};         // base state (global stream 0)
+    int gen = 0;                   // 0 MRG32k3a, 1 Philox4x32-10 (mrg_streamset_create_philox)
     uint32_t *d_planes = nullptr;  // [6][n]
 };
 

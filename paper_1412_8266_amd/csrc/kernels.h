@@ -86,6 +86,16 @@ hipError_t launch_partition(const uint32_t *planes, uint64_t plane_stride, uint6
                             int dtype, const PartitionLaunch &pl, void *out, int engine,
                             hipStream_t st);
 
+// Philox4x32-10 stream sets (philox.hip): states (position, id, key); fills
+// leave the positions to a following launch_philox_jump.
+hipError_t launch_philox_init(uint32_t *planes, uint64_t plane_stride, uint64_t count,
+                              uint64_t g0, uint64_t key, hipStream_t st);
+hipError_t launch_philox_jump(uint32_t *planes, uint64_t plane_stride, uint64_t first,
+                              uint64_t count, const uint64_t *d_exp, uint64_t e, hipStream_t st);
+hipError_t launch_philox_fill(const uint32_t *planes, uint64_t plane_stride, uint64_t first,
+                              uint64_t count, uint64_t n, int dtype, int layout, void *out,
+                              hipStream_t st);
+
 // Store-only bandwidth probes (probe.hip): pattern 0 streaming, 1 the
 // wave-per-stream fill's line geometry.
 hipError_t launch_write_probe(void *out, uint64_t bytes, int pattern, hipStream_t st);

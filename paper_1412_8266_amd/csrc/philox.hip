@@ -1,0 +1,238 @@
+// Philox4x32-10 stream sets (Salmon, Moraes, Dror & Shaw, SC 2011): the
+// counter-based generator family the paper embeds beside MRG32k3a.  A stream's
+// six state words are (position lo, hi, stream id lo, hi, key lo, hi); output
+// number `position` is word position % 4 of the block whose 128-bit counter is
+// (position / 4, stream id).  No jump tables: a jump adds to the position.
+//
+//   philox_init_kernel    stream g = g0 + s: position 0, id g, the set's key
+//   philox_jump_kernel    position += e (per stream from device memory, or
+//                         one e for the range)
+//   philox_sm_kernel      stream-major fill: each thread one 4-value block of
+//                         a row, 16-byte stores when the block is aligned
+//   philox_il_kernel      interleaved fill: one stream per lane, consecutive
+//                         lanes write consecutive elements
+// Fills do not move the positions; the host enqueues a uniform jump after them
+// (a row's blocks are spread over several workgroups, which all read the
+// position first).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "gen_device.hpp"
+#include "kernels.h"
+
+namespace mrg {
+namespace {
+
+constexpr uint32_t kPhiloxM0 = 0xD2511F53u;  // round multipliers
+constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
+constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;  // Weyl key increments: 2^32 (sqrt 5 - 1) / 2,
+constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;  //                       2^32 (sqrt 3 - 1)
+
+// Ten rounds on the counter c under the key (k0, k1): each round multiplies
+// words 0 and 2 by the multipliers, keeps the low halves as the new words 3
+// and 1 and xors the high halves with words 1 and 3 and the round key into
+// the new words 0 and 2; the round key moves by the Weyl increments.
+__device__ __forceinline__ void philox10(uint32_t c[4], uint32_t k0, uint32_t k1)
+{
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)kPhiloxM0 * c[0];
+        const uint64_t p1 = (uint64_t)kPhiloxM1 * c[2];
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
+        c[1] = (uint32_t)p1;
+        c[3] = (uint32_t)p0;
+        c[0] = n0;
+        c[2] = n2;
+        k0 += kPhiloxW0;
+        k1 += kPhiloxW1;
+    }
+}
+
+// The 4 words of block b of the stream with state words w (id w[2..3], key
+// w[4..5]); positions wrap at 2^64, so block numbers wrap at 2^62.
+__device__ __forceinline__ void philox_block(const uint32_t *w, uint64_t b, uint32_t out[4])
+{
+    b &= ((uint64_t)1 << 62) - 1;
+    out[0] = (uint32_t)b;
+    out[1] = (uint32_t)(b >> 32);
+    out[2] = w[2];
+    out[3] = w[3];
+    philox10(out, w[4], w[5]);
+}
+
+// Conversions of a word: (2*(w>>9)+1)*2^-24 as binary32 (1 + k*2^-23 minus
+// 1 - 2^-24, exact), (2w+1)*2^-33 as binary64 (one exact FMA).
+template <int DT> struct PhiloxOut;
+template <> struct PhiloxOut<0> {
+    using T = uint32_t;
+    __device__ static T conv(uint32_t w) { return w; }
+};
+template <> struct PhiloxOut<1> {
+    using T = float;
+    __device__ static T conv(uint32_t w)
+    {
+        return __uint_as_float(0x3F800000u | (w >> 9)) - 0x1.fffffep-1f;
+    }
+};
+template <> struct PhiloxOut<2> {
+    using T = double;
+    __device__ static T conv(uint32_t w) { return __fma_rn((double)w, 0x1p-32, 0x1p-33); }
+};
+
+__device__ __forceinline__ uint64_t position(const uint32_t *w)
+{
+    return (uint64_t)w[0] | (uint64_t)w[1] << 32;
+}
+
+__global__ void __launch_bounds__(256)
+philox_init_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t count,
+                   uint64_t g0, uint64_t key)
+{
+    const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= count) return;
+    const uint64_t g = g0 + s;
+    const uint32_t w[6] = {0u, 0u, (uint32_t)g, (uint32_t)(g >> 32), (uint32_t)key,
+                           (uint32_t)(key >> 32)};
+    store_state(planes, plane_stride, s, w);
+}
+
+__global__ void __launch_bounds__(256)
+philox_jump_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t first,
+                   uint64_t count, const uint64_t *__restrict__ exps, uint64_t e_uniform)
+{
+    const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= count) return;
+    const uint64_t idx = first + s;
+    const uint64_t e = exps ? exps[3 * s] : e_uniform;  // position wraps at 2^64
+    const uint64_t pos = ((uint64_t)planes[idx] | (uint64_t)planes[plane_stride + idx] << 32) + e;
+    planes[idx] = (uint32_t)pos;
+    planes[plane_stride + idx] = (uint32_t)(pos >> 32);
+}
+
+// Stream-major: rows of n values, row s at out + s*n.  A workgroup of 256
+// threads owns rpw rows, tpr = 256 / rpw threads each; thread j of a row
+// writes blocks j, j + tpr, ... of the row (block b: the row's values
+// [4b - off, 4b - off + 4) with off = position % 4).
+template <int DT>
+__global__ void __launch_bounds__(256)
+philox_sm_kernel(const uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t first,
+                 uint64_t count, uint64_t n, int rpw, unsigned char *__restrict__ out)
+{
+    using T = typename PhiloxOut<DT>::T;
+    const int tpr = 256 / rpw;
+    const uint64_t s = (uint64_t)blockIdx.x * rpw + threadIdx.x / tpr;
+    if (s >= count || (int)threadIdx.x >= rpw * tpr) return;
+    uint32_t w[6];
+    load_state(planes, plane_stride, first + s, w);
+    const uint64_t pos = position(w);
+    const uint64_t off = pos & 3, b0 = pos >> 2;
+    const uint64_t nb = (off + n + 3) / 4;
+    T *row = (T *)out + s * n;
+    for (uint64_t b = threadIdx.x % tpr; b < nb; b += tpr) {
+        uint32_t v[4];
+        philox_block(w, b0 + b, v);
+        const uint64_t k0 = 4 * b - off;  // row index of word 0 (wraps below 0 for b = 0)
+        if (off == 0 && k0 + 4 <= n && ((uintptr_t)(row + k0) % (4 * sizeof(T))) == 0) {
+            T *p = row + k0;
+            if constexpr (DT == 2) {
+                *(double2 *)p = make_double2(PhiloxOut<2>::conv(v[0]), PhiloxOut<2>::conv(v[1]));
+                *(double2 *)(p + 2) = make_double2(PhiloxOut<2>::conv(v[2]), PhiloxOut<2>::conv(v[3]));
+            } else {
+                uint4 q;
+                q.x = __builtin_bit_cast(uint32_t, PhiloxOut<DT>::conv(v[0]));
+                q.y = __builtin_bit_cast(uint32_t, PhiloxOut<DT>::conv(v[1]));
+                q.z = __builtin_bit_cast(uint32_t, PhiloxOut<DT>::conv(v[2]));
+                q.w = __builtin_bit_cast(uint32_t, PhiloxOut<DT>::conv(v[3]));
+                *(uint4 *)p = q;
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const uint64_t k = k0 + j;  // below 0 wraps to a huge value: skipped
+                if (k < n) row[k] = PhiloxOut<DT>::conv(v[j]);
+            }
+        }
+    }
+}
+
+// Interleaved: out[k * count + s]; lane = stream, blocks in order.
+template <int DT>
+__global__ void __launch_bounds__(256)
+philox_il_kernel(const uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t first,
+                 uint64_t count, uint64_t n, unsigned char *__restrict__ out)
+{
+    using T = typename PhiloxOut<DT>::T;
+    const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= count) return;
+    uint32_t w[6];
+    load_state(planes, plane_stride, first + s, w);
+    const uint64_t pos = position(w);
+    const uint64_t off = pos & 3, b0 = pos >> 2;
+    const uint64_t nb = (off + n + 3) / 4;
+    T *col = (T *)out + s;
+    for (uint64_t b = 0; b < nb; ++b) {
+        uint32_t v[4];
+        philox_block(w, b0 + b, v);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint64_t k = 4 * b + j - off;
+            if (k < n) col[k * count] = PhiloxOut<DT>::conv(v[j]);
+        }
+    }
+}
+
+unsigned grid256(uint64_t items) { return (unsigned)((items + 255) / 256); }
+
+}  // namespace
+
+hipError_t launch_philox_init(uint32_t *planes, uint64_t plane_stride, uint64_t count,
+                              uint64_t g0, uint64_t key, hipStream_t st)
+{
+    hipLaunchKernelGGL(philox_init_kernel, dim3(grid256(count)), dim3(256), 0, st, planes,
+                       plane_stride, count, g0, key);
+    return hipGetLastError();
+}
+
+hipError_t launch_philox_jump(uint32_t *planes, uint64_t plane_stride, uint64_t first,
+                              uint64_t count, const uint64_t *d_exp, uint64_t e, hipStream_t st)
+{
+    hipLaunchKernelGGL(philox_jump_kernel, dim3(grid256(count)), dim3(256), 0, st, planes,
+                       plane_stride, first, count, d_exp, e);
+    return hipGetLastError();
+}
+
+template <int DT>
+static hipError_t launch_philox_fill_t(const uint32_t *planes, uint64_t plane_stride,
+                                       uint64_t first, uint64_t count, uint64_t n, int layout,
+                                       void *out, hipStream_t st)
+{
+    unsigned char *o = (unsigned char *)out;
+    if (layout == 1) {
+        hipLaunchKernelGGL((philox_il_kernel<DT>), dim3(grid256(count)), dim3(256), 0, st, planes,
+                           plane_stride, first, count, n, o);
+    } else {
+        // rows per workgroup: enough threads per row for its blocks, at least 1
+        const uint64_t nb = (n + 6) / 4;
+        int rpw = 1;
+        while (rpw < 256 && (uint64_t)(256 / (rpw * 2)) >= nb) rpw *= 2;
+        const uint64_t wgs = (count + rpw - 1) / rpw;
+        if (wgs > 0x7fffffffu) return hipErrorInvalidValue;
+        hipLaunchKernelGGL((philox_sm_kernel<DT>), dim3((unsigned)wgs), dim3(256), 0, st, planes,
+                           plane_stride, first, count, n, rpw, o);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_philox_fill(const uint32_t *planes, uint64_t plane_stride, uint64_t first,
+                              uint64_t count, uint64_t n, int dtype, int layout, void *out,
+                              hipStream_t st)
+{
+    switch (dtype) {
+    case 0: return launch_philox_fill_t<0>(planes, plane_stride, first, count, n, layout, out, st);
+    case 1: return launch_philox_fill_t<1>(planes, plane_stride, first, count, n, layout, out, st);
+    default: return launch_philox_fill_t<2>(planes, plane_stride, first, count, n, layout, out, st);
+    }
+}
+
+}  // namespace mrg
