@@ -64,6 +64,8 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=10.0,
                     help="length of the replayed arrival trace (the full trace is 60 s)")
     ap.add_argument("--quick", action="store_true", help="headline only (for profiling)")
+    ap.add_argument("--partitions-only", action="store_true",
+                    help="only the leapfrog, random-spacing and Philox lines (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 2 GiB device-to-device copy 3 times (to scale HBM counters)")
     return ap.parse_args()
@@ -232,6 +234,44 @@ def serving(mg, wl, seconds, speed=1.0):
     }
 
 
+def partitions(mg, wl, torch, stream):
+    """The other partitions of sec. 2.3 and the second generator over 2^32
+    uint32 (16 GiB): one stream dealt to 2^16 players x 2^16 cards (in order,
+    and each player's cards in a row), random-spacing set creation, and a
+    Philox4x32-10 set of 2^20 streams x 4096."""
+    extra = {}
+    S, n = wl.C2_STREAMS, wl.C2_N
+    samples = S * n
+    ssl = mg.StreamSet(1, master_seed=wl.MASTER_SEED)
+    outl = torch.empty(samples, dtype=torch.uint32, device="cuda")
+    for name, lay in (("leapfrog_in_order_2^16x2^16", mg.INTERLEAVED),
+                      ("leapfrog_player_rows_2^16x2^16", mg.STREAM_MAJOR)):
+        per_l, _ = timed(lambda: ssl.fill_leapfrog(0, 1 << 16, 1 << 16, mg.U32, lay, out=outl),
+                         10, 2, stream)
+        msl = sum(per_l) / len(per_l)
+        extra[name] = {"ms": round(msl, 4), "Gsamples_s": round(samples / msl / 1e6, 2),
+                       "hbm_frac": round(samples * 4 / msl / 1e6 / HBM_PEAK_GBS, 4)}
+    ssl.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ssr = mg.StreamSet(S, master_seed=wl.MASTER_SEED, spacing="random")
+    torch.cuda.synchronize()
+    extra["random_spacing_create_2^20_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
+    ssr.close()
+    ssp = mg.StreamSet(S, master_seed=wl.MASTER_SEED, generator="philox")
+    outp = outl.view(S, n)
+    for name, lay in (("philox_fill_2^20x4096", mg.STREAM_MAJOR),
+                      ("philox_interleaved_2^20x4096", mg.INTERLEAVED)):
+        per_p, _ = timed(lambda: ssp.fill(n, mg.U32, lay, out=outp), 10, 2, stream)
+        msp = sum(per_p) / len(per_p)
+        extra[name] = {"ms": round(msp, 4), "Gsamples_s": round(samples / msp / 1e6, 2),
+                       "hbm_frac": round(samples * 4 / msp / 1e6 / HBM_PEAK_GBS, 4)}
+    ssp.close()
+    del outl, outp
+    torch.cuda.synchronize()
+    return extra
+
+
 def coop_lanes_used(mg, row_bytes):
     """Lanes per stream of the wave-per-stream fill for rows of row_bytes: the
     configured value, or the library's automatic choice (16 under 64 KiB)."""
@@ -270,6 +310,11 @@ def main():
     engine = mg.mrg_config_get("engine")
     tile = mg.mrg_config_get("tile_bytes")
     stream = torch.cuda.current_stream()
+
+    if args.partitions_only:
+        print("[bench] partitions and Philox", file=sys.stderr, flush=True)
+        print(json.dumps({"partitions": partitions(mg, wl, torch, stream)}), flush=True)
+        return
 
     if args.batch_only:
         print("[bench] batched request mix", file=sys.stderr, flush=True)
@@ -391,26 +436,7 @@ def main():
                                            "Gsamples_s": round(wl.C3_STREAMS * wl.C3_N / ms3 / 1e6, 2)}
         del out3
         ss3.close()
-        # the other partitions of sec. 2.3 over the same 2^32 uint32: one
-        # stream dealt to 2^16 players x 2^16 cards (in order, and each
-        # player's cards in a row), and random-spacing set creation
-        ssl = mg.StreamSet(1, master_seed=wl.MASTER_SEED)
-        outl = torch.empty(samples, dtype=torch.uint32, device="cuda")
-        for name, lay in (("leapfrog_in_order_2^16x2^16", mg.INTERLEAVED),
-                          ("leapfrog_player_rows_2^16x2^16", mg.STREAM_MAJOR)):
-            per_l, _ = timed(lambda: ssl.fill_leapfrog(0, 1 << 16, 1 << 16, mg.U32, lay, out=outl),
-                             10, 2, stream)
-            msl = sum(per_l) / len(per_l)
-            extra[name] = {"ms": round(msl, 4), "Gsamples_s": round(samples / msl / 1e6, 2),
-                           "hbm_frac": round(samples * 4 / msl / 1e6 / HBM_PEAK_GBS, 4)}
-        del outl
-        ssl.close()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        ssr = mg.StreamSet(S, master_seed=wl.MASTER_SEED, spacing="random")
-        torch.cuda.synchronize()
-        extra["random_spacing_create_2^20_ms"] = round((time.perf_counter() - t0) * 1e3, 3)
-        ssr.close()
+        extra.update(partitions(mg, wl, torch, stream))
     ss.close()
     torch.cuda.synchronize()
     if not args.quick and not args.no_batch:
