@@ -77,6 +77,8 @@ def _load():
         lib.orc_jump_many.argtypes = [P, u64, P, ctypes.c_int]
         lib.orc_stream_start.argtypes = [P, u64, P]
         lib.orc_streams.argtypes = [P, u64, u64, P]
+        lib.orc_streams_adjacent.argtypes = [P, u64, u64, P]
+        lib.orc_jump_uniform.argtypes = [P, u64, P]
         lib.orc_splitmix64_next.argtypes = [P]
         lib.orc_splitmix64_next.restype = u64
         lib.orc_seed_from_master.argtypes = [u64, P]
@@ -212,6 +214,23 @@ def streams(base, first: int, count: int) -> np.ndarray:
     if count:
         _load().orc_streams(_ptr(_state(base)), int(first), int(count), _ptr(out))
     return out
+
+
+def streams_adjacent(base, first: int, count: int) -> np.ndarray:
+    """As ``streams``, each start after the first computed from the previous
+    one (one product by A^(2^127)): for millions of streams."""
+    out = np.zeros((count, 6), dtype=np.uint32)
+    if count:
+        _load().orc_streams_adjacent(_ptr(_state(base)), int(first), int(count), _ptr(out))
+    return out
+
+
+def jump_uniform(states, e: int) -> np.ndarray:
+    """Every state jumped by the one exponent e (A^e formed once)."""
+    st = np.ascontiguousarray(np.array(states, dtype=np.uint32, copy=True).reshape(-1, 6))
+    w = _exp_words(int(e))
+    _load().orc_jump_uniform(_ptr(st), st.shape[0], _ptr(w))
+    return st
 
 
 def splitmix64(seed: int, count: int) -> list:

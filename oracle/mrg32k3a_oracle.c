@@ -197,6 +197,19 @@ void orc_jump_many(uint32_t *states, uint64_t S, const uint64_t *e, int e_stride
         orc_jump(states + 6 * s, e + (e_stride ? 3 * s : 0));
 }
 
+/* Every one of S states jumped by the one exponent e: A^e formed once, then
+ * one matrix-vector product per state and component. */
+void orc_jump_uniform(uint32_t *states, uint64_t S, const uint64_t e[3])
+{
+    uint32_t P1[9], P2[9];
+    orc_matpow(0, e, P1);
+    orc_matpow(1, e, P2);
+    for (uint64_t s = 0; s < S; ++s) {
+        orc_matvec(0, P1, states + 6 * s);
+        orc_matvec(1, P2, states + 6 * s + 3);
+    }
+}
+
 /* Start of stream g: A^(g * 2^127) applied to the base state (sec. 4.1).
  * g * 2^127 = (g >> 1) * 2^128 + (g & 1) * 2^127. */
 void orc_stream_start(const uint32_t base[6], uint64_t g, uint32_t out[6])
@@ -212,6 +225,25 @@ void orc_streams(const uint32_t base[6], uint64_t first, uint64_t S,
 {
     for (uint64_t i = 0; i < S; ++i)
         orc_stream_start(base, first + i, out + 6 * i);
+}
+
+/* The same starts stepped one stream at a time: stream g+1 begins 2^127
+ * outputs after stream g (adjacent streams, sec. 4.1), so after the first
+ * start each is one product by A^(2^127) of the one before. */
+void orc_streams_adjacent(const uint32_t base[6], uint64_t first, uint64_t S,
+                          uint32_t *out)
+{
+    if (S == 0) return;
+    orc_stream_start(base, first, out);
+    const uint64_t e[3] = { 0, (uint64_t)1 << 63, 0 };
+    uint32_t P1[9], P2[9];
+    orc_matpow(0, e, P1);
+    orc_matpow(1, e, P2);
+    for (uint64_t i = 1; i < S; ++i) {
+        memcpy(out + 6 * i, out + 6 * (i - 1), 6 * sizeof(uint32_t));
+        orc_matvec(0, P1, out + 6 * i);
+        orc_matvec(1, P2, out + 6 * i + 3);
+    }
 }
 
 /* ---------------------------------------------------------------------- */

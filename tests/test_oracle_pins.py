@@ -394,6 +394,18 @@ def test_seed_from_master_is_valid_and_defined():
         assert [int(x) for x in s] == want
 
 
+def test_adjacent_stream_starts_and_uniform_jump():
+    base = oracle.seed_from_master(0x0123456789ABCDEF)
+    for first in (0, 5, 2**40 - 3):
+        assert np.array_equal(oracle.streams_adjacent(base, first, 40),
+                              oracle.streams(base, first, 40))
+    st = oracle.streams(base, 0, 30)
+    for e in (0, 1, 999, 2**76 + 12345, 2**190 + 7):
+        assert np.array_equal(oracle.jump_uniform(st, e), oracle.jump_many(st, e))
+    # and against stepping, for a small exponent
+    assert np.array_equal(oracle.jump_uniform(st[:3], 57)[2], oracle.skip(st[2], 57))
+
+
 def test_splitmix64_random_access_matches_sequential():
     for seed in (0, 1, 0x0123456789ABCDEF, 2**64 - 1):
         seq = oracle.splitmix64(seed, 1500)
