@@ -190,12 +190,11 @@ class StreamSet:
     def get_states(self, first: int = 0, count: Optional[int] = None, stream=None) -> np.ndarray:
         first, count = self._range(first, count)
         w = _abi.mrg_get_states(self._h, first, count, _stream_handle(stream))
-        return np.array(w, dtype=np.uint32).reshape(count, 6)
+        return w.reshape(count, 6)
 
     def set_states(self, states, first: int = 0, stream=None) -> None:
         st = np.asarray(states, dtype=np.uint32).reshape(-1, 6)
-        _abi.mrg_set_states(self._h, first, st.shape[0], st.reshape(-1).tolist(),
-                            _stream_handle(stream))
+        _abi.mrg_set_states(self._h, first, st.shape[0], st.reshape(-1), _stream_handle(stream))
 
 
 __all__ = [

@@ -259,14 +259,19 @@ def mrg_fill_leapfrog(ss: int, s: int, players: int, per_player: int, dtype: int
 
 
 def mrg_get_states(ss: int, first: int, count: int, stream: int = 0):
-    buf = (ctypes.c_uint32 * (6 * count))()
-    _call("mrg_get_states", ss, first, count, buf, stream)
-    return list(buf)
+    """[count * 6] uint32 numpy array of the states, stream after stream."""
+    import numpy as np
+    buf = np.empty(6 * count, dtype=np.uint32)
+    _call("mrg_get_states", ss, first, count, buf.ctypes.data_as(_PU32), stream)
+    return buf
 
 
 def mrg_set_states(ss: int, first: int, count: int, words, stream: int = 0) -> None:
-    buf = _u32(words, 6 * count)
-    _call("mrg_set_states", ss, first, count, buf, stream)
+    import numpy as np
+    buf = np.ascontiguousarray(np.asarray(words, dtype=np.uint32).reshape(-1))
+    if buf.size < 6 * count:
+        raise ValueError("need 6 words per stream")
+    _call("mrg_set_states", ss, first, count, buf.ctypes.data_as(_PU32), stream)
 
 
 def mrg_seed_from_master(master_seed: int):
