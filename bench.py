@@ -404,11 +404,12 @@ def main():
                                     "ms": round(msi, 4)}
         # store-only probes over the same 16 GiB: what the stores alone attain
         probe = {}
-        for name, pat in (("streaming_16B", 0), ("fill_lines", 1)):
+        for name, pat in (("streaming_16B", 0), ("fill_lines", 1), ("fill_runs_of_8_lines", 2)):
             per_p, _ = timed(lambda: mg.write_probe(out, pat, stream), args.steps, 1, stream)
             msp = sum(per_p) / len(per_p)
             probe[name + "_GBs"] = round(out.numel() * 4 / msp / 1e6, 1)
         probe["fill_over_fill_lines"] = round(achieved / probe["fill_lines_GBs"], 4)
+        probe["fill_over_streaming"] = round(achieved / probe["streaming_16B_GBs"], 4)
         extra["store_probe"] = probe
         del outf
         del out

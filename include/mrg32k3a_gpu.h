@@ -441,11 +441,13 @@ mrg_status mrg_config_get(const char *key, int64_t *value);
  * writes `bytes` of filler to device memory d_out on `stream` with the store
  * pattern of the fills but no generation work, so that a fill's write rate can
  * be compared with what its stores alone attain.
- *   pattern 0: streaming 16-byte stores (bytes a multiple of 16, d_out
- *              16-byte aligned);
+ *   pattern 0: streaming 16-byte stores, one pass in address order (bytes a
+ *              multiple of 16, d_out 16-byte aligned);
  *   pattern 1: the wave-per-stream fill's geometry at 16 lanes per stream and
  *              1 KiB per lane: four 16 KiB rows per wave, 128-byte lines staged
- *              in LDS (bytes a multiple of 65536, d_out 128-byte aligned).
+ *              in LDS (bytes a multiple of 65536, d_out 128-byte aligned);
+ *   pattern 2: the same 64 KiB per wave as runs of 8 lines (1 KiB) per store
+ *              instruction (sizes and alignment as pattern 1).
  * Other patterns or sizes: MRG_EINVAL.  Asynchronous. */
 mrg_status mrg_write_probe(void *d_out, uint64_t bytes, int32_t pattern, void *stream);
 

@@ -206,8 +206,9 @@ __all__ = [
 
 def write_probe(out, pattern: int = 0, stream=None) -> None:
     """Store-only bandwidth probe over the whole of `out` (a CUDA tensor):
-    pattern 0 streaming 16-byte stores, 1 the wave-per-stream fill's 128-byte
-    line geometry (mrg_write_probe in the C ABI)."""
+    pattern 0 streaming 16-byte stores in one pass, 1 the wave-per-stream
+    fill's 128-byte line geometry, 2 the same with runs of 8 lines per store
+    instruction (mrg_write_probe in the C ABI)."""
     _abi.mrg_write_probe(out.data_ptr(), out.numel() * out.element_size(), pattern,
                          _stream_handle(stream))
 

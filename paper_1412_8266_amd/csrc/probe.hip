@@ -1,12 +1,17 @@
 // Store-only probes: the write bandwidth HBM grants to a store pattern, with
 // no generation work, so that the fill kernels can be compared with what the
 // same stores alone attain.
-//   pattern 0: streaming 16-byte stores, consecutive lanes on consecutive
-//              addresses (each wave instruction covers 1 KiB);
+//   pattern 0: streaming 16-byte stores, one per thread, consecutive lanes
+//              and workgroups on consecutive addresses, so the front of
+//              writes moves through memory in one pass (each wave
+//              instruction covers 1 KiB);
 //   pattern 1: the wave-per-stream fill's geometry at 16 lanes per stream and
 //              256 uint32 per lane (4 rows of 16 KiB per wave): each flush
 //              stages 64 pieces of 128 bytes in LDS and writes them as 16-byte
-//              stores, 8 lines per instruction, lines 1 KiB apart in a row.
+//              stores, 8 lines per instruction, lines 1 KiB apart in a row;
+//   pattern 2: the same 64 KiB per wave written as runs of 8 consecutive
+//              lines (1 KiB) per instruction, one run per 1 KiB member
+//              segment: what eight pieces per lane per flush would attain.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -50,13 +55,31 @@ __global__ void __launch_bounds__(64) probe_pieces_kernel(unsigned char *__restr
     }
 }
 
+__global__ void __launch_bounds__(64) probe_runs_kernel(unsigned char *__restrict__ out,
+                                                        uint64_t groups)
+{
+    const int lane = threadIdx.x, p = lane >> 3, col = (lane & 7) * 16;
+    for (uint64_t grp = blockIdx.x; grp < groups; grp += gridDim.x) {
+        unsigned char *base = out + grp * 65536;
+        const uint4 v = make_uint4((uint32_t)grp, (uint32_t)lane, 0x5A5Au, 0xA5A5u);
+#pragma unroll
+        for (int q = 0; q < 64; ++q)  // member segment q, its 8 lines
+            *(uint4 *)(base + q * 1024 + p * 128 + col) = v;
+    }
+}
+
 hipError_t launch_write_probe(void *out, uint64_t bytes, int pattern, hipStream_t st)
 {
     if (pattern == 0) {
         const uint64_t n16 = bytes / 16;
         const uint64_t blocks = (n16 + 255) / 256;
-        const unsigned grid = (unsigned)(blocks < (1u << 20) ? blocks : (1u << 20));
+        const unsigned grid = (unsigned)(blocks < 0x7fffffffu ? blocks : 0x7fffffffu);
         hipLaunchKernelGGL(probe_stream_kernel, dim3(grid), dim3(256), 0, st, (uint4 *)out, n16);
+    } else if (pattern == 2) {
+        const uint64_t groups = bytes / 65536;
+        const unsigned grid = (unsigned)(groups < (1u << 30) ? groups : (1u << 30));
+        hipLaunchKernelGGL(probe_runs_kernel, dim3(grid), dim3(64), 0, st, (unsigned char *)out,
+                           groups);
     } else {
         const uint64_t groups = bytes / (4 * 16384);
         const unsigned grid = (unsigned)(groups < (1u << 30) ? groups : (1u << 30));

@@ -91,7 +91,9 @@ def test_validation_returns_before_any_device_work():
     assert lib.mrg_streamset_destroy(None) == _abi.MRG_OK
     # store probe: pattern, size unit and alignment are checked first
     assert lib.mrg_write_probe(None, 16, 0, None) == _abi.MRG_EINVAL
-    assert lib.mrg_write_probe(4096, 16, 2, None) == _abi.MRG_EINVAL
+    assert lib.mrg_write_probe(4096, 16, 3, None) == _abi.MRG_EINVAL
+    assert lib.mrg_write_probe(4096, 16, -1, None) == _abi.MRG_EINVAL
+    assert lib.mrg_write_probe(4096, 65536 + 16, 2, None) == _abi.MRG_EINVAL
     assert lib.mrg_write_probe(4096, 24, 0, None) == _abi.MRG_EINVAL
     assert lib.mrg_write_probe(4096, 65536 + 16, 1, None) == _abi.MRG_EINVAL
     assert lib.mrg_write_probe(4096 + 16, 65536, 1, None) == _abi.MRG_EINVAL

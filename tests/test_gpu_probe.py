@@ -43,3 +43,20 @@ def test_pieces_probe_geometry(mg):
     assert np.array_equal(v[..., 2], 16 * t + g)
     assert np.array_equal(v[..., 3], q)
     assert not h[groups * 65536 // 4:].any()
+
+
+def test_runs_probe_geometry(mg):
+    import torch
+    groups = 3
+    buf = torch.zeros(groups * 65536 // 4 + 32, dtype=torch.int32, device="cuda")
+    mg.write_probe(buf[:groups * 65536 // 4], 2)
+    torch.cuda.synchronize()
+    h = buf.cpu().numpy().view(np.uint32)
+    # word offset of (group, member segment, line p, 16-byte column c): lane 8p + c
+    v = h[:groups * 65536 // 4].reshape(groups, 64, 8, 8, 4)
+    gr, _, p, c = np.meshgrid(np.arange(groups), np.arange(64), np.arange(8), np.arange(8),
+                              indexing="ij")
+    assert np.array_equal(v[..., 0], gr)
+    assert np.array_equal(v[..., 1], 8 * p + c)
+    assert np.all(v[..., 2] == 0x5A5A) and np.all(v[..., 3] == 0xA5A5)
+    assert not h[groups * 65536 // 4:].any()
