@@ -72,6 +72,13 @@ def test_config_roundtrip_and_rejects():
             _abi.mrg_config_set("no_such_key", 1)
         with pytest.raises(_abi.MRGError):
             _abi.mrg_config_set("tile_bytes", 100)
+        lanes = _abi.mrg_config_get("coop_lanes")
+        assert lanes == 0  # automatic by row length
+        for v in (64, 32, 16, 8, 0):
+            _abi.mrg_config_set("coop_lanes", v)
+            assert _abi.mrg_config_get("coop_lanes") == v
+        with pytest.raises(_abi.MRGError):
+            _abi.mrg_config_set("coop_lanes", 12)
     finally:
         _abi.mrg_config_set("engine", old)
 
@@ -87,6 +94,13 @@ def test_validation_returns_before_any_device_work():
     assert lib.mrg_streamset_create(ctypes.byref(h), 2, 2**64 - 1, good, None) == _abi.MRG_ERANGE
     assert lib.mrg_fill(None, 0, 1, 1, 0, 0, None, None) == _abi.MRG_EINVAL
     assert lib.mrg_jump(None, 0, 1, None, None) == _abi.MRG_EINVAL
+    # random-spacing and Philox sets: sizes are checked before the device
+    assert lib.mrg_streamset_create_random(None, 4, 0, 1, None) == _abi.MRG_EINVAL
+    assert lib.mrg_streamset_create_random(ctypes.byref(h), 0, 0, 1, None) == _abi.MRG_ERANGE
+    assert lib.mrg_streamset_create_philox(None, 4, 0, 1, None) == _abi.MRG_EINVAL
+    assert lib.mrg_streamset_create_philox(ctypes.byref(h), 2, 2**64 - 1, 1, None) == _abi.MRG_ERANGE
+    assert lib.mrg_streamset_create_philox(ctypes.byref(h), 2**36 + 1, 0, 1, None) == _abi.MRG_ERANGE
+    assert lib.mrg_fill_leapfrog(None, 0, 4, 4, 0, 0, None, None) == _abi.MRG_EINVAL
     assert "null" in _abi.mrg_last_error()
     assert lib.mrg_streamset_destroy(None) == _abi.MRG_OK
     # store probe: pattern, size unit and alignment are checked first
