@@ -430,6 +430,10 @@ mrg_status mrg_state_check(const uint32_t state6[6]);
  *   "coop_wgs_per_cu" wave-per-stream fill: one-wave workgroups per compute
  *                unit, each looping over stream groups (0 = one workgroup
  *                per group, the default), 0 .. 1024;
+ *   "coop_order" wave-per-stream fill: order of stream groups over the XCDs,
+ *                0 (default) chunked: 64 consecutive groups per XCD in turn,
+ *                all XCDs moving through memory together; 1: one contiguous
+ *                range per XCD;
  *   "coop_lanes" wave-per-stream fill: lanes per stream, 64, 32, 16 or 8
  *                (64/coop_lanes streams share a wave), or 0 (the default:
  *                16 for rows under 64 KiB, else 64).

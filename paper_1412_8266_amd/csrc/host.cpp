@@ -564,6 +564,7 @@ mrg_status mrg_fill(mrg_streamset ss, uint64_t first, uint64_t count, uint64_t n
             const uint64_t cap = tune.coop_wgs_per_cu ? (uint64_t)ctx->cus * tune.coop_wgs_per_cu
                                                       : ((uint64_t)1 << 31) - 1;
             fl.grid = (unsigned)(groups < cap ? groups : cap);
+            fl.order = tune.coop_order;
         }
     }
     hipError_t e = mrg::launch_fill(ss->d_planes, ss->n, first, count, n_per_stream, (int)dtype,
@@ -712,6 +713,9 @@ mrg_status mrg_config_set(const char *key, int64_t value)
     if (!std::strcmp(key, "engine")) {
         if (value != 0 && value != 1) return set_error(MRG_EINVAL, "engine must be 0 or 1");
         g_tune.engine = (int)value;
+    } else if (!std::strcmp(key, "coop_order")) {
+        if (value != 0 && value != 1) return set_error(MRG_EINVAL, "coop_order must be 0 or 1");
+        g_tune.coop_order = (int)value;
     } else if (!std::strcmp(key, "coop_wgs_per_cu")) {
         if (value < 0 || value > 1024) return set_error(MRG_EINVAL, "coop_wgs_per_cu must be in [0, 1024]");
         g_tune.coop_wgs_per_cu = (int)value;
@@ -740,6 +744,7 @@ mrg_status mrg_config_get(const char *key, int64_t *value)
     else if (!std::strcmp(key, "tile_bytes")) *value = g_tune.tile_bytes;
     else if (!std::strcmp(key, "strategy")) *value = g_tune.strategy;
     else if (!std::strcmp(key, "coop_wgs_per_cu")) *value = g_tune.coop_wgs_per_cu;
+    else if (!std::strcmp(key, "coop_order")) *value = g_tune.coop_order;
     else if (!std::strcmp(key, "coop_lanes")) *value = g_tune.coop_lanes;
     else return set_error(MRG_EINVAL, "unknown key '%s'", key);
     return MRG_OK;

@@ -29,6 +29,7 @@ struct FillTuning {
     int strategy = 0;
     int coop_wgs_per_cu = 0;  // wave per stream: 0 = one workgroup per stream group
     int coop_lanes = 0;       // wave per stream: lanes per stream (64, 32, 16, 8; 0 automatic)
+    int coop_order = 0;       // wave per stream: 0 chunked (one front), 1 one range per XCD
 };
 
 // Lane-segment lengths L of the wave-per-stream fill; table k holds A^(l*L)
@@ -47,6 +48,7 @@ struct FillLaunch {
     const uint32_t *head_tab = nullptr; // [64][18]: A^l (values before the first line boundary)
     const uint32_t *table = nullptr;    // windowed jump tables (end state of a partial chunk)
     unsigned grid = 0;                  // workgroups (wave per stream)
+    int order = 0;                      // group order (FillTuning::coop_order)
 };
 
 hipError_t launch_fill(uint32_t *planes, uint64_t plane_stride, uint64_t first, uint64_t count,

@@ -196,12 +196,27 @@ __device__ __forceinline__ XcdRange xcd_range(uint64_t items)
     return {lo + b / 8, lo + q + (x < r ? 1 : 0), (nb - x + 7) / 8};
 }
 
+// The chunked order, for one workgroup per item: in each super-chunk of 8*Q
+// items, XCD x takes the Q consecutive items [x*Q, x*Q + Q) (its workgroups
+// in dispatch order), so each XCD works on contiguous runs while all XCDs move
+// through memory together, one front of writes instead of eight.  Items past
+// the last whole super-chunk keep their own index.
+__device__ __forceinline__ XcdRange xcd_chunk(uint64_t items)
+{
+    constexpr uint64_t Q = 64, S = 8 * Q;
+    const uint64_t b = blockIdx.x;
+    if (gridDim.x != items || b >= items / S * S) return {b, b + 1, 1};
+    const uint64_t l = b % S;
+    const uint64_t g = b - l + (l % 8) * Q + l / 8;
+    return {g, g + 1, 1};
+}
+
 template <int DT, int L, int GL, class G>
 __global__ void __launch_bounds__(64)
 fill_coop_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t first,
                  uint64_t count, uint64_t n, unsigned char *__restrict__ out,
                  const uint32_t *__restrict__ lane_tab, const uint32_t *__restrict__ head_tab,
-                 const uint32_t *__restrict__ table)
+                 const uint32_t *__restrict__ table, int order)
 {
     constexpr int ES = Elem<DT>::size;
     constexpr int SPW = 64 / GL;
@@ -212,7 +227,8 @@ fill_coop_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t 
 #pragma unroll
     for (int i = 0; i < 18; ++i) m[i] = lane_tab[(lane % GL) * 18 + i];
 
-    const XcdRange R = xcd_range((count + SPW - 1) / SPW);
+    const uint64_t groups = (count + SPW - 1) / SPW;
+    const XcdRange R = order == 0 && gridDim.x == groups ? xcd_chunk(groups) : xcd_range(groups);
     for (uint64_t grp = R.first; grp < R.end; grp += R.step) {
         const uint64_t s0 = grp * SPW;
         const int nsv = count - s0 < (uint64_t)SPW ? (int)(count - s0) : SPW;
@@ -387,7 +403,8 @@ static hipError_t launch_fill_g(uint32_t *planes, uint64_t plane_stride, uint64_
         const int nh = fl.L / TV;
 #define MRG_COOP(GL, NH)                                                                        \
     hipLaunchKernelGGL((fill_coop_kernel<DT, (NH) * TV, GL, G>), grid, block, 0, st, planes,     \
-                       plane_stride, first, count, n, o, fl.lane_tab, fl.head_tab, fl.table)
+                       plane_stride, first, count, n, o, fl.lane_tab, fl.head_tab, fl.table,   \
+                       fl.order)
         if (fl.L % TV) return hipErrorInvalidValue;
         else if (fl.lanes == 64 && nh == 1) MRG_COOP(64, 1);
         else if (fl.lanes == 64 && nh == 2) MRG_COOP(64, 2);
