@@ -185,6 +185,23 @@ __device__ __forceinline__ void rows_fill(G &g, unsigned char *lds, int lane, ui
     }
 }
 
+// rows_fill_short: adjacent rows shorter than a line (n * ES < 128, row r at
+// out0 + r * n * ES) are one block of nrows * n values.  Each lane stages its
+// row in LDS (row r at r * n * ES, `lds` holding 64 * 128 bytes) and the wave
+// copies the block out as dwords, 64 consecutive dwords per store.
+template <int DT, class G>
+__device__ __forceinline__ void rows_fill_short(G &g, unsigned char *lds, int lane,
+                                                uint64_t nrows, unsigned char *out0, uint64_t n)
+{
+    constexpr int ES = Elem<DT>::size;
+    if ((uint64_t)lane < nrows)
+        for (uint64_t c = 0; c < n; ++c) put1<DT>(lds + (uint64_t)lane * n * ES + c * ES, g);
+    __syncthreads();
+    const uint64_t words = nrows * n * ES / 4;
+    for (uint64_t i = lane; i < words; i += 64) ((uint32_t *)out0)[i] = ((const uint32_t *)lds)[i];
+    __syncthreads();
+}
+
 // ---------------------------------------------------------------------------
 // wave_fill: values [v0, v1) of 64/GL streams at once, GL lanes per stream
 // (lane l serves stream l / GL as its member g = l % GL).  Stream t of the

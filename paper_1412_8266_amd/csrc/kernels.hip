@@ -139,7 +139,10 @@ fill_sm_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t fi
     if (active) load_state(planes, plane_stride, idx, w);
     G g;
     g.load(w);
-    rows_fill<DT, TB, G>(g, lds, lane, nrows, out + s0 * n * ES, n * ES, n);
+    if (n * ES < 128)  // the wave's rows are one block shorter than 64 lines
+        rows_fill_short<DT, G>(g, lds, lane, nrows, out + s0 * n * ES, n);
+    else
+        rows_fill<DT, TB, G>(g, lds, lane, nrows, out + s0 * n * ES, n * ES, n);
     if (active) {
         g.store(w);
         store_state(planes, plane_stride, idx, w);
