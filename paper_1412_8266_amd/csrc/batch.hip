@@ -82,7 +82,7 @@ __device__ __forceinline__ void wave_item(const BatchReq &R, uint64_t local, uns
         jump_global(A.table, v0, sub << 12, sub >> 52, 0, kTableWindows, w);
         const bool end = (R.flags & kReqWriteBack) && v1 == R.n;
         wave_fill<DT, L, G, false>(w, m, lds, lane, R.out + j * R.n * ES, 0, 1, v0, v1, A.table,
-                                   A.lane_tab + kHeadTable * 64 * 18, end);
+                                   A.lane_tab, end);
         if (end) {
             if (lane == 0) {
                 if (R.segs == 1) store_state(A.planes, A.plane_stride, R.stream0 + j, w);
@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(64) batch_kernel(BatchArgs A)
     const int lane = threadIdx.x;
     uint32_t m[18];  // wave items: the lane's A^(lane * L), L = 256 bytes of values
     if constexpr (KIND == kKindWave) {
-        constexpr int k = Elem<DT>::size == 4 ? 2 : 1;  // kLaneSegs[k] = 64 or 32
+        constexpr int k = lane_table(256 / Elem<DT>::size);  // L = 64 or 32 values
 #pragma unroll
         for (int i = 0; i < 18; ++i) m[i] = A.lane_tab[(k * 64 + lane) * 18 + i];
     }

@@ -212,15 +212,18 @@ __device__ __forceinline__ void rows_fill_short(G &g, unsigned char *lds, int la
 //
 // Each stream first writes its head, the values before its row's first
 // 128-byte line boundary (fewer than 128 / ES): value i of the head comes
-// from A^i applied to the state (head_tab: entry l is A^l), members taking
-// i = g, GL + g, ..., and the stream moves on to the state A^head w.  The rest
-// is cut into chunks of GL*L values; member g generates the L consecutive
-// values [g*L, g*L + L) of each chunk starting from A^(g*L) applied to the
-// chunk's first state (m: the lane's 18-word matrix pair), and the next chunk
-// starts where member GL-1 ended (sequence splitting, sec. 2.3).  Every LDS
-// flush of whole chunks writes aligned 128-byte lines; a stream's last,
-// partial chunk writes the same lines up to its end (16-byte stores, dwords
-// for the last group), and its state is then moved over that chunk with the
+// from A^i applied to the state (the head table of `tabs`: entry l is A^l),
+// members taking i = g, GL + g, ..., and the stream moves on to the state
+// A^head w.  The rest is cut into chunks of GL*L values; member g generates
+// the L consecutive values [g*L, g*L + L) of each chunk starting from
+// A^(g*L) applied to the chunk's first state (m: the lane's 18-word matrix
+// pair), and the next chunk starts where member GL-1 ended (sequence
+// splitting, sec. 2.3).  Every LDS flush of whole chunks writes aligned
+// 128-byte lines.  In a chunk where rows end (and none goes on), members take
+// only Lc <= L values each, the fewest whole pieces with GL*Lc covering the
+// longest remaining row, starting from A^(g*Lc) (the Lc table of `tabs`); it
+// writes the same lines up to each row's end (16-byte stores, dwords for the
+// last group), and the stream's state is then moved over that chunk with the
 // windowed tables.  `lds` holds 64 * 144 bytes.
 // READ_ALL: read all eight LDS pieces of a flush before the first store (else
 // each piece goes straight to memory).
@@ -230,7 +233,7 @@ __device__ __forceinline__ void wave_fill(uint32_t *w, const uint32_t *m, unsign
                                           int lane, unsigned char *srow, uint64_t row_stride,
                                           int nsv, uint64_t v0, uint64_t v1,
                                           const uint32_t *__restrict__ table,
-                                          const uint32_t *__restrict__ head_tab, bool want_end)
+                                          const uint32_t *__restrict__ tabs, bool want_end)
 {
     constexpr int ES = Elem<DT>::size;
     constexpr int TV = 128 / ES;   // values per 128-byte piece
@@ -265,7 +268,7 @@ __device__ __forceinline__ void wave_fill(uint32_t *w, const uint32_t *m, unsign
             const uint32_t i = (uint32_t)(k * GL + gl);
             uint32_t hm[18];
 #pragma unroll
-            for (int q = 0; q < 18; ++q) hm[q] = head_tab[i * 18 + q];
+            for (int q = 0; q < 18; ++q) hm[q] = tabs[(kHeadTable * 64 + i) * 18 + q];
             uint32_t st[6] = {w[0], w[1], w[2], w[3], w[4], w[5]};
             matvec3<C1>(hm, st[0], st[1], st[2]);
             matvec3<C2>(hm + 9, st[3], st[4], st[5]);
@@ -289,17 +292,12 @@ __device__ __forceinline__ void wave_fill(uint32_t *w, const uint32_t *m, unsign
     for (uint64_t c = 0;; ++c) {
         const uint64_t c0 = start + c * chunk_vals;
         if (!__any(c0 < v1)) break;
-        uint32_t st[6] = {w[0], w[1], w[2], w[3], w[4], w[5]};
-        matvec3<C1>(m, st[0], st[1], st[2]);
-        matvec3<C2>(m + 9, st[3], st[4], st[5]);
-        G g;
-        g.load(st);
         const bool active = c0 < v1;
         const bool full = c0 + chunk_vals <= v1;
         const bool cut = __any(tl < nsv && active && !full);  // a row ends in this chunk
-        // a chunk where every row ends before member 0's last piece needs
-        // only the flushes up to the longest of them
-        int h_end = NH;
+        // members' values this chunk: L, or in a chunk where every row ends,
+        // the fewest whole pieces that cover the longest of them
+        uint32_t Lc = L;
         if (cut) {
             uint64_t rmax = 0;
 #pragma unroll
@@ -308,8 +306,23 @@ __device__ __forceinline__ void wave_fill(uint32_t *w, const uint32_t *m, unsign
                 const uint64_t r = (SPW > 1 && t >= nsv) || ct >= v1 ? 0 : v1 - ct;
                 rmax = r > rmax ? r : rmax;
             }
-            if (rmax < (uint64_t)L) h_end = (int)((rmax + TV - 1) / TV);
+            if (rmax < chunk_vals) {
+                const uint64_t per = (rmax + GL - 1) / GL;
+                Lc = (uint32_t)((per + TV - 1) / TV * TV);
+            }
         }
+        const int h_end = (int)(Lc / TV);
+        uint32_t st[6] = {w[0], w[1], w[2], w[3], w[4], w[5]};
+        if (Lc == (uint32_t)L) {
+            matvec3<C1>(m, st[0], st[1], st[2]);
+            matvec3<C2>(m + 9, st[3], st[4], st[5]);
+        } else {
+            const uint32_t *mc = tabs + ((uint32_t)lane_table((int)Lc) * 64 + gl) * 18;
+            matvec3<C1>(mc, st[0], st[1], st[2]);
+            matvec3<C2>(mc + 9, st[3], st[4], st[5]);
+        }
+        G g;
+        g.load(st);
         for (int h = 0; h < h_end; ++h) {
 #pragma unroll
             for (int q = 0; q < 8; ++q) *(uint4 *)(my_lds + q * 16) = gen16<DT>(g);
@@ -353,7 +366,7 @@ __device__ __forceinline__ void wave_fill(uint32_t *w, const uint32_t *m, unsign
                     const uint64_t ct = v0 + ht + c * chunk_vals;
                     if (ct >= v1) continue;
                     const uint64_t rem = (v1 - ct < chunk_vals ? v1 - ct : chunk_vals) * ES;
-                    const uint32_t o = (uint32_t)((prow + 8 * (j % JPS)) * L * ES + pcol + h * 128);
+                    const uint32_t o = (uint32_t)((prow + 8 * (j % JPS)) * Lc * ES + pcol + h * 128);
                     if (o >= rem) continue;
                     const uint4 v = *(const uint4 *)(lds + (prow + 8 * j) * RS + pcol);
                     unsigned char *p = srow + t * row_stride + ct * ES + o;

@@ -130,9 +130,9 @@ struct DevCtx {
 // A^(l*L) for l in [0, 64) and each lane-segment length L, both components.
 std::vector<uint32_t> build_lane_tables()
 {
-    std::vector<uint32_t> t(mrg::kNumLaneSegs * 64 * 18);
-    for (int k = 0; k < mrg::kNumLaneSegs; ++k) {
-        const uint64_t L = (uint64_t)mrg::kLaneSegs[k];
+    std::vector<uint32_t> t(mrg::kNumLaneTabs * 64 * 18);
+    for (int k = 0; k < mrg::kNumLaneTabs; ++k) {
+        const uint64_t L = k == mrg::kHeadTable ? 1 : (uint64_t)(16 * (k + 1));
         for (int l = 0; l < 64; ++l) {
             const uint64_t e[3] = {L * (uint64_t)l, 0, 0};
             for (int c = 0; c < 2; ++c) {
@@ -550,14 +550,12 @@ mrg_status mrg_fill(mrg_streamset ss, uint64_t first, uint64_t count, uint64_t n
             const uint64_t gen_max = (body + ch_max - 1) / ch_max * ch_max;
             const uint64_t nh = gen_max <= gen_min ? nh_max : nh_min;
             const int L = (int)(nh * tv);
-            int k = 0;
-            while (k < mrg::kNumLaneSegs - 1 && mrg::kLaneSegs[k] != L) ++k;
-            if (mrg::kLaneSegs[k] != L) return set_error(MRG_EINVAL, "no lane table for L = %d", L);
+            if (L % 16 || L < 16 || L > 512) return set_error(MRG_EINVAL, "no lane table for L = %d", L);
             fl.kernel = 1;
             fl.L = L;
             fl.lanes = GL;
-            fl.lane_tab = ctx->d_lane_tab + k * 64 * 18;
-            fl.head_tab = ctx->d_lane_tab + mrg::kHeadTable * 64 * 18;
+            fl.lane_tab = ctx->d_lane_tab + mrg::lane_table(L) * 64 * 18;
+            fl.tabs = ctx->d_lane_tab;
             fl.table = ctx->d_table;
             // resident workgroups stride over the stream groups, or one per group
             const uint64_t groups = (count + (64 / GL) - 1) / (64 / GL);
@@ -612,11 +610,8 @@ mrg_status mrg_fill_leapfrog(mrg_streamset ss, uint64_t s, uint64_t players,
         pl.rem = N % pl.B;
         const bool one_chunk = N < 128 * tv;  // short: 64-line chunks
         pl.L = (int)(one_chunk ? tv : 2 * tv);
-        int k = 0;
-        while (k < mrg::kNumLaneSegs - 1 && mrg::kLaneSegs[k] != pl.L) ++k;
-        if (mrg::kLaneSegs[k] != pl.L) return set_error(MRG_EINVAL, "no lane table for L = %d", pl.L);
-        pl.lane_tab = ctx->d_lane_tab + k * 64 * 18;
-        pl.head_tab = ctx->d_lane_tab + mrg::kHeadTable * 64 * 18;
+        pl.lane_tab = ctx->d_lane_tab + mrg::lane_table(pl.L) * 64 * 18;
+        pl.tabs = ctx->d_lane_tab;
         const uint64_t blocks = pl.nfull + (pl.rem ? 1 : 0);
         pl.grid = (unsigned)(blocks < ((uint64_t)1 << 31) - 1 ? blocks : ((uint64_t)1 << 31) - 1);
     } else {

@@ -32,12 +32,14 @@ struct FillTuning {
     int coop_order = 0;       // wave per stream: 0 chunked (one front), 1 one range per XCD
 };
 
-// Lane-segment lengths L of the wave-per-stream fill; table k holds A^(l*L)
-// for l < 64, L = kLaneSegs[k].  The last one (L = 1) serves the values
-// before a row's first 128-byte line boundary.
-constexpr int kNumLaneSegs = 7;
-constexpr int kLaneSegs[kNumLaneSegs] = {16, 32, 64, 128, 256, 1, 512};
-constexpr int kHeadTable = 5;
+// Lane tables of the wave-per-stream writer: table lane_table(L) holds
+// A^(l*L) for l < 64 and each lane-segment length L = 16, 32, ..., 512 values
+// (a chunk's members, and the shorter members of a chunk where rows end);
+// table kHeadTable holds A^l (the values before a row's first 128-byte line
+// boundary).
+constexpr int kNumLaneTabs = 33;
+constexpr int kHeadTable = 32;
+__host__ __device__ constexpr int lane_table(int L) { return L / 16 - 1; }
 
 // How one stream-major fill is launched (chosen on the host).
 struct FillLaunch {
@@ -45,7 +47,7 @@ struct FillLaunch {
     int L = 0;                          // values per lane per chunk (wave per stream)
     int lanes = 64;                     // lanes per stream (wave per stream)
     const uint32_t *lane_tab = nullptr; // [64][18]: A^(l*L), component 1 then 2 (lane l % lanes)
-    const uint32_t *head_tab = nullptr; // [64][18]: A^l (values before the first line boundary)
+    const uint32_t *tabs = nullptr;     // all lane tables ([kNumLaneTabs][64][18])
     const uint32_t *table = nullptr;    // windowed jump tables (end state of a partial chunk)
     unsigned grid = 0;                  // workgroups (wave per stream)
     int order = 0;                      // group order (FillTuning::coop_order)
@@ -80,7 +82,7 @@ struct PartitionLaunch {
     uint64_t nfull = 0, B = 0, rem = 0;  // kind 0
     LeapArgs leap;                       // kind 1
     const uint32_t *lane_tab = nullptr;  // kind 0: [64][18] A^(l*L)
-    const uint32_t *head_tab = nullptr;  // kind 0: [64][18] A^l
+    const uint32_t *tabs = nullptr;      // kind 0: all lane tables
     const uint32_t *table = nullptr;     // windowed jump tables
     unsigned grid = 0;
 };

@@ -218,7 +218,7 @@ template <int DT, int L, int GL, class G>
 __global__ void __launch_bounds__(64)
 fill_coop_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t first,
                  uint64_t count, uint64_t n, unsigned char *__restrict__ out,
-                 const uint32_t *__restrict__ lane_tab, const uint32_t *__restrict__ head_tab,
+                 const uint32_t *__restrict__ lane_tab, const uint32_t *__restrict__ tabs,
                  const uint32_t *__restrict__ table, int order)
 {
     constexpr int ES = Elem<DT>::size;
@@ -239,7 +239,7 @@ fill_coop_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t 
         uint32_t w[6] = {1u, 1u, 1u, 1u, 1u, 1u};
         if (t < nsv) load_state(planes, plane_stride, idx, w);
         wave_fill<DT, L, G, true, GL>(w, m, lds, lane, out + s0 * n * ES, n * ES, nsv, 0, n, table,
-                                      head_tab, true);
+                                      tabs, true);
         if (lane % GL == 0 && t < nsv) store_state(planes, plane_stride, idx, w);
     }
 }
@@ -255,7 +255,7 @@ template <int DT, int L, class G>
 __global__ void __launch_bounds__(64)
 fill_split_kernel(const uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t sidx,
                   uint64_t nfull, uint64_t B, uint64_t rem, unsigned char *__restrict__ out,
-                  const uint32_t *__restrict__ lane_tab, const uint32_t *__restrict__ head_tab,
+                  const uint32_t *__restrict__ lane_tab, const uint32_t *__restrict__ tabs,
                   const uint32_t *__restrict__ table)
 {
     constexpr int ES = Elem<DT>::size;
@@ -271,7 +271,7 @@ fill_split_kernel(const uint32_t *__restrict__ planes, uint64_t plane_stride, ui
         uint32_t w[6] = {s0[0], s0[1], s0[2], s0[3], s0[4], s0[5]};
         jump_global(table, r * B, 0, 0, 0, 16, w);
         wave_fill<DT, L, G, true, 64>(w, m, lds, lane, out + r * B * ES, B * ES, 1, 0,
-                                      r < nfull ? B : rem, table, head_tab, false);
+                                      r < nfull ? B : rem, table, tabs, false);
     }
 }
 
@@ -408,7 +408,7 @@ static hipError_t launch_fill_g(uint32_t *planes, uint64_t plane_stride, uint64_
         const int nh = fl.L / TV;
 #define MRG_COOP(GL, NH)                                                                        \
     hipLaunchKernelGGL((fill_coop_kernel<DT, (NH) * TV, GL, G>), grid, block, 0, st, planes,     \
-                       plane_stride, first, count, n, o, fl.lane_tab, fl.head_tab, fl.table,   \
+                       plane_stride, first, count, n, o, fl.lane_tab, fl.tabs, fl.table,   \
                        fl.order)
         if (fl.L % TV) return hipErrorInvalidValue;
         else if (fl.lanes == 64 && nh == 1) MRG_COOP(64, 1);
@@ -472,11 +472,11 @@ static hipError_t launch_partition_g(const uint32_t *planes, uint64_t plane_stri
         if (pl.L == TV)
             hipLaunchKernelGGL((fill_split_kernel<DT, TV, G>), dim3(pl.grid), dim3(64), 0, st, planes,
                                plane_stride, sidx, pl.nfull, pl.B, pl.rem, o, pl.lane_tab,
-                               pl.head_tab, pl.table);
+                               pl.tabs, pl.table);
         else if (pl.L == 2 * TV)
             hipLaunchKernelGGL((fill_split_kernel<DT, 2 * TV, G>), dim3(pl.grid), dim3(64), 0, st,
                                planes, plane_stride, sidx, pl.nfull, pl.B, pl.rem, o, pl.lane_tab,
-                               pl.head_tab, pl.table);
+                               pl.tabs, pl.table);
         else
             return hipErrorInvalidValue;
     } else {
