@@ -7,8 +7,9 @@
 //   philox_init_kernel    stream g = g0 + s: position 0, id g, the set's key
 //   philox_jump_kernel    position += e (per stream from device memory, or
 //                         one e for the range)
-//   philox_sm_kernel      stream-major fill: each thread one 4-value block of
-//                         a row, 16-byte stores when the block is aligned
+//   philox_sm_kernel      stream-major fill: each thread about 16 4-value
+//                         blocks of a row, consecutive threads on consecutive
+//                         blocks, 16-byte stores when a block is aligned
 //   philox_il_kernel      interleaved fill: one stream per lane, consecutive
 //                         lanes write consecutive elements
 // Fills do not move the positions; the host enqueues a uniform jump after them
@@ -212,10 +213,12 @@ static hipError_t launch_philox_fill_t(const uint32_t *planes, uint64_t plane_st
         hipLaunchKernelGGL((philox_il_kernel<DT>), dim3(grid256(count)), dim3(256), 0, st, planes,
                            plane_stride, first, count, n, o);
     } else {
-        // rows per workgroup: enough threads per row for its blocks, at least 1
+        // threads per row: about 16 blocks each (a power of two, 1 .. 256), so
+        // that each thread's state load and setup serve 64 values or more
         const uint64_t nb = (n + 6) / 4;
-        int rpw = 1;
-        while (rpw < 256 && (uint64_t)(256 / (rpw * 2)) >= nb) rpw *= 2;
+        int tpr = 1;
+        while (tpr < 256 && (uint64_t)tpr * 16 < nb) tpr *= 2;
+        const int rpw = 256 / tpr;
         const uint64_t wgs = (count + rpw - 1) / rpw;
         if (wgs > 0x7fffffffu) return hipErrorInvalidValue;
         hipLaunchKernelGGL((philox_sm_kernel<DT>), dim3((unsigned)wgs), dim3(256), 0, st, planes,
