@@ -1,9 +1,12 @@
 // Device building blocks shared by the fill kernels and the persistent batch
 // kernel: the two generator engines, 16-byte output packing, state planes,
-// jump-table application, and the two LDS-staged writers
-//   rows_fill -- one stream per lane (rows of the LDS tile are streams);
-//   wave_fill -- one stream per wave, lane l owning consecutive L-value
-//                segments, so that each flush tiles contiguous memory.
+// jump-table application, and the LDS-staged writers
+//   rows_fill       -- one stream per lane (rows of the LDS tile are streams);
+//   rows_fill_short -- one stream per lane, rows shorter than a line, the
+//                      wave's rows copied out as one block;
+//   wave_fill       -- GL lanes per stream (64/GL streams per wave), member g
+//                      owning consecutive L-value segments, so that each flush
+//                      writes whole 128-byte lines.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>

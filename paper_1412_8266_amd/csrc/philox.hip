@@ -20,47 +20,10 @@
 
 #include "gen_device.hpp"
 #include "kernels.h"
+#include "philox_device.h"  // philox10, philox_block, conversions
 
 namespace mrg {
 namespace {
-
-constexpr uint32_t kPhiloxM0 = 0xD2511F53u;  // round multipliers
-constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
-constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;  // Weyl key increments: 2^32 (sqrt 5 - 1) / 2,
-constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;  //                       2^32 (sqrt 3 - 1)
-
-// Ten rounds on the counter c under the key (k0, k1): each round multiplies
-// words 0 and 2 by the multipliers, keeps the low halves as the new words 3
-// and 1 and xors the high halves with words 1 and 3 and the round key into
-// the new words 0 and 2; the round key moves by the Weyl increments.
-__device__ __forceinline__ void philox10(uint32_t c[4], uint32_t k0, uint32_t k1)
-{
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        const uint64_t p0 = (uint64_t)kPhiloxM0 * c[0];
-        const uint64_t p1 = (uint64_t)kPhiloxM1 * c[2];
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c[1] ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c[3] ^ k1;
-        c[1] = (uint32_t)p1;
-        c[3] = (uint32_t)p0;
-        c[0] = n0;
-        c[2] = n2;
-        k0 += kPhiloxW0;
-        k1 += kPhiloxW1;
-    }
-}
-
-// The 4 words of block b of the stream with state words w (id w[2..3], key
-// w[4..5]); positions wrap at 2^64, so block numbers wrap at 2^62.
-__device__ __forceinline__ void philox_block(const uint32_t *w, uint64_t b, uint32_t out[4])
-{
-    b &= ((uint64_t)1 << 62) - 1;
-    out[0] = (uint32_t)b;
-    out[1] = (uint32_t)(b >> 32);
-    out[2] = w[2];
-    out[3] = w[3];
-    philox10(out, w[4], w[5]);
-}
 
 // Conversions of a word: (2*(w>>9)+1)*2^-24 as binary32 (1 + k*2^-23 minus
 // 1 - 2^-24, exact), (2w+1)*2^-33 as binary64 (one exact FMA).
@@ -71,14 +34,11 @@ template <> struct PhiloxOut<0> {
 };
 template <> struct PhiloxOut<1> {
     using T = float;
-    __device__ static T conv(uint32_t w)
-    {
-        return __uint_as_float(0x3F800000u | (w >> 9)) - 0x1.fffffep-1f;
-    }
+    __device__ static T conv(uint32_t w) { return philox_to_f32(w); }
 };
 template <> struct PhiloxOut<2> {
     using T = double;
-    __device__ static T conv(uint32_t w) { return __fma_rn((double)w, 0x1p-32, 0x1p-33); }
+    __device__ static T conv(uint32_t w) { return philox_to_f64(w); }
 };
 
 __device__ __forceinline__ uint64_t position(const uint32_t *w)

@@ -1,7 +1,9 @@
-"""The public device header (include/mrg32k3a_device.h) is self-contained: a
-user kernel that includes only it compiles for gfx950 (compile only, no GPU).
-Its draws are those of the interleaved fill, which is written with the same
-Stream type and checked against the oracle in the GPU parity tests."""
+"""The public device headers (include/mrg32k3a_device.h, include/philox_device.h)
+are self-contained: user kernels that include only them compile for gfx950
+(compile only, no GPU).  Their draws are those of the library's fills, which
+are written with the same Stream type (MRG32k3a interleaved fill, batch row
+items) and the same Philox block and conversion functions, and checked
+against the oracle in the GPU parity tests."""
 import os
 import subprocess
 
@@ -40,6 +42,42 @@ __global__ void int_kernel(const uint32_t *planes, uint64_t n_streams, const uin
     out[n_streams + i] = (uint32_t)(s.next_f64() * 4294967296.0);
 }
 """
+
+
+PHILOX_KERNEL = r"""
+#include "philox_device.h"
+
+// Each thread draws k values of its Philox stream, skips 2^40, draws one more.
+__global__ void philox_user(uint32_t *planes, uint64_t n_streams, int k, double *out)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_streams) return;
+    mrg::PhiloxStream s;
+    s.load(planes, n_streams, i);
+    double acc = 0.0;
+    for (int j = 0; j < k; ++j) acc += s.next_f64() + s.next_f32() + (double)s.next_u32();
+    s.jump((uint64_t)1 << 40);
+    out[i] = acc + s.next_f64();
+    s.store(planes, n_streams, i);
+}
+"""
+
+
+def compile_device(tmp_path, name, text):
+    src = tmp_path / (name + ".hip")
+    src.write_text(text)
+    out = tmp_path / (name + ".o")
+    subprocess.check_call([HIPCC, "--offload-arch=gfx950", "--offload-device-only", "-O3",
+                           "-std=c++17", "-Xclang", "-target-feature", "-Xclang",
+                           "-packed-fp32-ops", "-Wno-unused-command-line-argument",
+                           "-I", os.path.join(ROOT, "include"), "-c", str(src), "-o", str(out)],
+                          stderr=subprocess.DEVNULL)
+    return out
+
+
+@pytest.mark.skipif(not os.path.exists(HIPCC), reason="no hipcc")
+def test_philox_user_kernel_compiles_with_public_header(tmp_path):
+    assert compile_device(tmp_path, "philox_user", PHILOX_KERNEL).stat().st_size > 0
 
 
 @pytest.mark.skipif(not os.path.exists(HIPCC), reason="no hipcc")
