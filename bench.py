@@ -345,9 +345,10 @@ def main():
     torch.cuda.synchronize()
     first_create_s = time.perf_counter() - t0  # includes the device's one-time table setup
     t0 = time.perf_counter()
-    mg.StreamSet(S, master_seed=wl.MASTER_SEED ^ 1).close()
+    ss2 = mg.StreamSet(S, master_seed=wl.MASTER_SEED ^ 1)
     torch.cuda.synchronize()
     create_s = time.perf_counter() - t0
+    ss2.close()
     out = torch.empty((S, n), dtype=torch.uint32, device="cuda")
     ptr = out.data_ptr()
 
