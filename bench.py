@@ -299,7 +299,8 @@ def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the stream library has no multi-GPU path "
-              "(streams shard by index with no exchange; see DESIGN.md)", file=sys.stderr)
+              "(streams would shard by global index, GPU d taking a contiguous range as a "
+              "stream set with first_stream, with no exchange)", file=sys.stderr)
         sys.exit(2)
     import torch
     if args.copy_calibration:
