@@ -199,6 +199,17 @@ mrg_status launch_tick(mrg_server s, Slot &slot)
     return MRG_OK;
 }
 
+// A tick that failed to launch or to complete: its requests are dropped (their
+// arena space returned, no longer in flight) and the slot freed.  Called with
+// the server lock held.
+void drop_tick(mrg_server s, Slot &slot)
+{
+    for (const Req &r : slot.reqs) s->arena->release(r.offset, r.bytes);
+    s->inflight_reqs -= slot.reqs.size();
+    slot.reqs.clear();
+    slot.busy = false;
+}
+
 void scheduler(mrg_server s)
 {
     (void)hipSetDevice(s->device);
@@ -214,7 +225,8 @@ void scheduler(mrg_server s)
                 s->worker_status = MRG_EHIP;
                 s->worker_error = hipGetErrorString(q);
                 s->stop = true;
-                break;
+                drop_tick(s, slot);  // its outputs are lost; let the scheduler exit
+                continue;
             }
             const double t = now_s();
             for (Req &r : slot.reqs) {
@@ -273,6 +285,7 @@ void scheduler(mrg_server s)
                         s->worker_status = st;
                         s->worker_error = err;
                         s->stop = true;
+                        drop_tick(s, *free_slot);
                     }
                     progressed = true;
                 }
