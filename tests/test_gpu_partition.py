@@ -166,3 +166,37 @@ def test_leapfrog_large_sampled(mg, players, per_player, layout, dtype):
         assert np.array_equal(states_of(ss)[0], end[0])
         if dtype != 0:
             assert np.all(out > 0) and np.all(out < 1)
+
+
+def test_random_spacing_set_with_jumps_batches_and_leapfrog(mg):
+    """A random-spacing set is an ordinary stream set: substream jumps, a
+    batch over it and a leapfrog deal of one of its streams all match the
+    oracle run on the expanded states."""
+    import torch
+    say("random spacing: jumps, batch, leapfrog")
+    master, S = 0xC0FFEE, 200
+    with mg.StreamSet(S, master_seed=master, spacing="random") as ss:
+        st = oracle.random_spacing_states(master, 0, S)
+        ss.jump_substreams(3)
+        st = oracle.jump_many(st, 3 * 2**76)
+        assert np.array_equal(states_of(ss), st)
+        # a batch of three plain requests
+        specs = [(0, 50, 5000, 0), (50, 100, 300, 2), (150, 50, 4097, 1)]
+        outs, rows = [], []
+        for first, k, n, dt in specs:
+            t = torch.empty((k, n), dtype=mg.torch_dtype(dt), device="cuda")
+            outs.append(t)
+            rows.append((first, k, n, 0, t.data_ptr(), dt, 0))
+        b = mg.Batch(ss, rows)
+        b.run()
+        for (first, k, n, dt), t in zip(specs, outs):
+            want, end = oracle.fill(st[first:first + k], n, dt)
+            assert np.array_equal(host(t).view(np.uint8), want.view(np.uint8)), (first, k, n)
+            st[first:first + k] = end
+        b.close()
+        assert np.array_equal(states_of(ss), st)
+        # leapfrog of stream 7
+        cards = host(ss.fill_leapfrog(7, 33, 70, mg.U32, mg.STREAM_MAJOR))
+        want, end = oracle.leapfrog(st[7], 33, 70, oracle.U32, oracle.STREAM_MAJOR)
+        assert np.array_equal(cards, want)
+        assert np.array_equal(states_of(ss)[7], end)
