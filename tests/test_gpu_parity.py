@@ -286,3 +286,54 @@ def test_c2_full_size_sampled(mg, dtype):
         assert bool(((out > 0) & (out < 1)).all())
     del out
     ss.close()
+
+
+def test_random_fill_sweep(mg):
+    """Seeded random fills against the oracle: row counts and lengths across
+    the lane-per-stream / wave-per-stream boundary and several chunks,
+    output pointers off their 128-byte lines by any number of elements,
+    8/16/32/64 lanes per stream or automatic, both engines, every dtype,
+    both layouts, and a second fill continuing from the first.  Guard words
+    around the output must stay untouched."""
+    import torch
+    rng = np.random.default_rng(1412)
+    keys = ("engine", "strategy", "coop_lanes")
+    old = [mg.mrg_config_get(k) for k in keys]
+    base = oracle.seed_from_master(2012)
+    try:
+        for case in range(200):
+            engine = int(rng.integers(2))
+            lanes = int(rng.choice([0, 8, 16, 32, 64]))
+            strategy = int(rng.choice([0, 0, 1, 2]))
+            dt = int(rng.integers(3))
+            layout = int(rng.integers(2)) if case % 3 == 0 else 0
+            count = int(rng.integers(1, 200))
+            n = int(np.exp(rng.uniform(0, np.log(12000))))
+            first = int(rng.integers(0, 50))
+            es = 8 if dt == 2 else 4
+            off = int(rng.integers(0, 128 // es))
+            for k, v in zip(keys, (engine, strategy, lanes)):
+                mg.mrg_config_set(k, v)
+            say("sweep", case, dict(engine=engine, lanes=lanes, strategy=strategy, dt=dt,
+                                    layout=layout, count=count, n=n, first=first, off=off))
+            ss = mg.StreamSet(first + count + 3, seed=[int(x) for x in base])
+            st = oracle.streams(base, first, count)
+            tdt = mg.torch_dtype(dt)
+            guard = 16
+            buf = torch.zeros(count * n + off + 2 * guard, dtype=tdt, device="cuda")
+            for rep in range(2):
+                buf.zero_()
+                view = buf[guard + off:guard + off + count * n]
+                ss.fill_ptr(n, dt, layout, view.data_ptr(), first=first, count=count)
+                h = host(buf)
+                want, st = oracle.fill(st, n, dt, layout)
+                got = h[guard + off:guard + off + count * n]
+                assert np.array_equal(got.view(np.uint8), want.reshape(-1).view(np.uint8)), \
+                    (case, rep)
+                assert not h[:guard + off].view(np.uint8).any(), (case, rep, "before")
+                assert not h[guard + off + count * n:].view(np.uint8).any(), (case, rep, "after")
+            assert np.array_equal(ss.get_states(first, count), st), case
+            ss.close()
+    finally:
+        for k, v in zip(keys, old):
+            mg.mrg_config_set(k, v)
