@@ -200,3 +200,44 @@ def test_random_spacing_set_with_jumps_batches_and_leapfrog(mg):
         want, end = oracle.leapfrog(st[7], 33, 70, oracle.U32, oracle.STREAM_MAJOR)
         assert np.array_equal(cards, want)
         assert np.array_equal(states_of(ss)[7], end)
+
+
+def test_random_leapfrog_sweep(mg):
+    """Seeded random deals against the oracle: players and cards from 1 to
+    thousands (fewer and more than 64 cards), both layouts, every dtype, both
+    engines, output pointers off their lines, guard words untouched, and two
+    deals in a row continuing the stream."""
+    import torch
+    rng = np.random.default_rng(2003)
+    old = mg.mrg_config_get("engine")
+    try:
+        for case in range(80):
+            engine = int(rng.integers(2))
+            mg.mrg_config_set("engine", engine)
+            players = int(np.exp(rng.uniform(0, np.log(5000))))
+            per_player = int(np.exp(rng.uniform(0, np.log(3000))))
+            if players * per_player > 3_000_000:
+                per_player = max(1, 3_000_000 // players)
+            dt = int(rng.integers(3))
+            layout = int(rng.integers(2))
+            es = 8 if dt == 2 else 4
+            off = int(rng.integers(0, 128 // es))
+            say("leapfrog sweep", case, players, per_player, dt, layout, off, engine)
+            with mg.StreamSet(4, master_seed=case) as ss:
+                st = states_of(ss)[2]
+                guard = 16
+                size = players * per_player
+                buf = torch.zeros(size + off + 2 * guard, dtype=mg.torch_dtype(dt), device="cuda")
+                for rep in range(2):
+                    buf.zero_()
+                    view = buf[guard + off:guard + off + size]
+                    ss.fill_leapfrog(2, players, per_player, dt, layout, out=view)
+                    h = host(buf)
+                    want, st = oracle.leapfrog(st, players, per_player, dt, layout)
+                    assert np.array_equal(h[guard + off:guard + off + size].view(np.uint8),
+                                          want.reshape(-1).view(np.uint8)), (case, rep)
+                    assert not h[:guard + off].view(np.uint8).any(), (case, rep)
+                    assert not h[guard + off + size:].view(np.uint8).any(), (case, rep)
+                assert np.array_equal(states_of(ss)[2], st), case
+    finally:
+        mg.mrg_config_set("engine", old)
