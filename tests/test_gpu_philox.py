@@ -133,3 +133,44 @@ def test_philox_large_sampled(mg):
         rows = [0, S - 1] + [int(x) for x in rng.integers(0, S, 40)]
         want, _ = oracle.philox_fill(st[rows], n, oracle.U32)
         assert np.array_equal(out[rows], want)
+
+
+def test_philox_random_sweep(mg):
+    """Seeded random Philox fills against the oracle: arbitrary positions
+    (near the 2^64 wrap too), ids and keys, row lengths from 1 to tens of
+    thousands, both layouts, every dtype, sub-ranges, output pointers off
+    their 16-byte and line boundaries, guard words untouched."""
+    import torch
+    rng = np.random.default_rng(1011)
+    for case in range(60):
+        total = int(np.exp(rng.uniform(0, np.log(3000))))
+        first = int(rng.integers(0, total))
+        count = int(rng.integers(1, total - first + 1))
+        n = int(np.exp(rng.uniform(0, np.log(40000))))
+        if count * n > 2_000_000:
+            n = max(1, 2_000_000 // count)
+        dt = int(rng.integers(3))
+        layout = int(rng.integers(2))
+        es = 8 if dt == 2 else 4
+        off = int(rng.integers(0, 128 // es))
+        say("philox sweep", case, total, first, count, n, dt, layout, off)
+        st = rng.integers(0, 2**32, size=(total, 6), dtype=np.uint64).astype(np.uint32)
+        if case % 3 == 0:
+            st[:, 1] = 0xFFFFFFFF  # positions within 2^32 of the wrap
+        with mg.StreamSet(total, master_seed=case, generator="philox") as ss:
+            ss.set_states(st)
+            guard = 16
+            size = count * n
+            buf = torch.zeros(size + off + 2 * guard, dtype=mg.torch_dtype(dt), device="cuda")
+            view = buf[guard + off:guard + off + size]
+            ss.fill(n, dt, layout, out=view, first=first, count=count)
+            h = host(buf)
+            want, end = oracle.philox_fill(st[first:first + count], n, dt, layout)
+            assert np.array_equal(h[guard + off:guard + off + size].view(np.uint8),
+                                  want.reshape(-1).view(np.uint8)), case
+            assert not h[:guard + off].view(np.uint8).any(), case
+            assert not h[guard + off + size:].view(np.uint8).any(), case
+            got = states_of(ss)
+            assert np.array_equal(got[first:first + count], end), case
+            assert np.array_equal(got[:first], st[:first]), case
+            assert np.array_equal(got[first + count:], st[first + count:]), case
