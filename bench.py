@@ -36,10 +36,10 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
 METRIC = "uint32 Gsamples/s (% HBM write roofline), batched vs plain; p50/p99 latency"
 # HBM bytes per launch read by rocprofv3 (FETCH_SIZE + WRITE_SIZE, scaled by a
 # copy-kernel calibration); None until measured for the current kernel.
-COUNTER_TRAFFIC = 17232538368  # fill_coop_kernel<u32,256,16>: profiles/fill_coop_u32_16lanes_2p20x4096.md
+COUNTER_TRAFFIC = 17232614912  # fill_coop_kernel<u32,256,16>: profiles/fill_coop_u32_16lanes_2p20x4096.md
 # VALU wave instructions per launch of the same kernel (SQ_INSTS_VALU, same profile);
 # None until measured for the current kernel.
-COUNTER_VALU_INSTS = 1176502272
+COUNTER_VALU_INSTS = 1159200768
 SIMDS, PEAK_SCLK_MHZ = 1024, 2400  # MI355X: 256 CUs x 4 SIMDs, 2.4 GHz peak shader clock
 
 

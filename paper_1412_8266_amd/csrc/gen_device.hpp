@@ -50,6 +50,22 @@ __device__ __forceinline__ void put1(unsigned char *p, G &g)
     else *(double *)p = g.next_f64();
 }
 
+// 16-byte store at base + off where base is the same for the whole wave: the
+// base goes into a raw buffer descriptor in scalar registers (word 3 0x20000:
+// 32-bit data format, as gfx9 raw buffers take it), so a lane spends no vector
+// instruction on its 64-bit address.  Offsets at or past span are dropped.
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void store16_uniform(const unsigned char *base, uint32_t off,
+                                                uint32_t span, uint4 v)
+{
+    const uint64_t b = (uint64_t)base;
+    const uint64_t bu = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b) |
+                        (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32)) << 32;
+    const __amdgpu_buffer_rsrc_t r =
+        __builtin_amdgcn_make_buffer_rsrc((void *)bu, 0, (int)span, 0x00020000);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, v), r, off, 0, 0);
+}
+
 template <int ES>
 __device__ __forceinline__ void copy_elem(unsigned char *dst, const unsigned char *src)
 {
@@ -344,7 +360,8 @@ __device__ __forceinline__ void wave_fill(uint32_t *w, const uint32_t *m, unsign
                         const uint64_t ct = v0 + hvt[t] + c * chunk_vals;
                         if ((SPW > 1 && t >= nsv) || ct + chunk_vals > v1) continue;
                         const uint32_t loff = (uint32_t)((prow + 8 * (j % JPS)) * L * ES + pcol);
-                        *(uint4 *)(srow + t * row_stride + (ct + (uint64_t)h * TV) * ES + loff) = v[j];
+                        store16_uniform(srow + t * row_stride + (ct + (uint64_t)h * TV) * ES, loff,
+                                        (uint32_t)(GL * L * ES), v[j]);
                     }
                 } else {
 #pragma unroll
@@ -354,7 +371,8 @@ __device__ __forceinline__ void wave_fill(uint32_t *w, const uint32_t *m, unsign
                         if ((SPW > 1 && t >= nsv) || ct + chunk_vals > v1) continue;
                         const uint4 v = *(const uint4 *)(lds + (prow + 8 * j) * RS + pcol);
                         const uint32_t loff = (uint32_t)((prow + 8 * (j % JPS)) * L * ES + pcol);
-                        *(uint4 *)(srow + t * row_stride + (ct + (uint64_t)h * TV) * ES + loff) = v;
+                        store16_uniform(srow + t * row_stride + (ct + (uint64_t)h * TV) * ES, loff,
+                                        (uint32_t)(GL * L * ES), v);
                     }
                 }
             } else {
