@@ -337,3 +337,35 @@ def test_random_fill_sweep(mg):
     finally:
         for k, v in zip(keys, old):
             mg.mrg_config_set(k, v)
+
+
+@pytest.mark.parametrize("gen", ["mrg32k3a", "philox"])
+def test_degenerate_calls_change_nothing(mg, gen):
+    """Empty ranges, zero-length fills, zero jumps and empty deals write
+    nothing and move no state; a zero jump of the whole set is the identity."""
+    import torch
+    with mg.StreamSet(70, master_seed=5, generator=gen) as ss:
+        st = np.asarray(ss.get_states(), dtype=np.uint32).copy()
+        guard = torch.full((256,), 0x5A5A5A5A, dtype=torch.int32, device="cuda")
+        assert ss.fill(7, mg.U32, first=10, count=0).numel() == 0
+        assert ss.fill(0, mg.F64, mg.INTERLEAVED).numel() == 0
+        ss.fill_ptr(0, mg.U32, mg.STREAM_MAJOR, guard.data_ptr())
+        ss.fill_ptr(0, mg.F64, mg.INTERLEAVED, guard.data_ptr(), first=3, count=5)
+        ss.fill_ptr(9, mg.F32, mg.STREAM_MAJOR, guard.data_ptr(), first=69, count=0)
+        ss.jump_uniform(0)
+        ss.jump_uniform(12345, first=20, count=0)
+        ss.jump(torch.zeros(3 * 70, dtype=torch.int64, device="cuda"))
+        if gen == "mrg32k3a":
+            ss.jump_substreams(0)
+            assert ss.fill_leapfrog(4, 0, 9).numel() == 0
+            assert ss.fill_leapfrog(4, 5, 0, mg.F64, mg.INTERLEAVED).numel() == 0
+        torch.cuda.synchronize()
+        assert np.all(guard.cpu().numpy().view(np.uint32) == 0x5A5A5A5A)
+        assert np.array_equal(np.asarray(ss.get_states(), dtype=np.uint32), st)
+        # and the set still continues its streams: one value each equals the oracle
+        one = host(ss.fill(1, mg.U32))
+        if gen == "mrg32k3a":
+            want, _ = oracle.fill(st, 1, oracle.U32)
+        else:
+            want, _ = oracle.philox_fill(st, 1, oracle.U32)
+        assert np.array_equal(one, want)
