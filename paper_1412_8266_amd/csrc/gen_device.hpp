@@ -1,6 +1,7 @@
 // Device building blocks shared by the fill kernels and the persistent batch
 // kernel: the two generator engines, 16-byte output packing, state planes,
-// jump-table application, and the LDS-staged writers
+// jump-table application, workgroup placement on the XCDs, and the LDS-staged
+// writers
 //   rows_fill       -- one stream per lane (rows of the LDS tile are streams);
 //   rows_fill_short -- one stream per lane, rows shorter than a line, the
 //                      wave's rows copied out as one block;
@@ -413,6 +414,35 @@ __device__ __forceinline__ void wave_fill(uint32_t *w, const uint32_t *m, unsign
     }
     // w is the last chunk's first state: move it over the partial chunk
     if (!whole && want_end) jump_global(table, (v1 - start) % chunk_vals, 0, 0, 0, 16, w);
+}
+
+// Workgroups are dispatched to the 8 XCDs in turn (workgroup b on XCD b % 8).
+// xcd_range gives the workgroups of each XCD a contiguous range of the items,
+// so that work which varies with the item index in a period dividing 8 still
+// spreads evenly over the XCDs, and neighbouring rows meet in one L2.
+struct XcdRange { uint64_t first, end, step; };
+__device__ __forceinline__ XcdRange xcd_range(uint64_t items)
+{
+    const uint64_t nb = gridDim.x, b = blockIdx.x;
+    if (nb < 8) return {b, items, nb};
+    const uint64_t x = b % 8, q = items / 8, r = items % 8;
+    const uint64_t lo = x * q + (x < r ? x : r);
+    return {lo + b / 8, lo + q + (x < r ? 1 : 0), (nb - x + 7) / 8};
+}
+
+// The chunked order, for one workgroup per item: in each super-chunk of 8*Q
+// items, XCD x takes the Q consecutive items [x*Q, x*Q + Q) (its workgroups
+// in dispatch order), so each XCD works on contiguous runs while all XCDs move
+// through memory together, one front of writes instead of eight.  Items past
+// the last whole super-chunk keep their own index.
+__device__ __forceinline__ XcdRange xcd_chunk(uint64_t items)
+{
+    constexpr uint64_t Q = 64, S = 8 * Q;
+    const uint64_t b = blockIdx.x;
+    if (gridDim.x != items || b >= items / S * S) return {b, b + 1, 1};
+    const uint64_t l = b % S;
+    const uint64_t g = b - l + (l % 8) * Q + l / 8;
+    return {g, g + 1, 1};
 }
 
 }  // namespace mrg

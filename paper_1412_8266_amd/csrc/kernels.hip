@@ -184,36 +184,8 @@ fill_il_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t fi
 // groups of 64/GL streams, GL lanes per stream; each group is written by
 // wave_fill, so that every flush writes whole 128-byte lines and the streams
 // in flight stay adjacent.  Lanes of a group past the last stream run on a
-// dummy state and write nothing.
-// Workgroups are dispatched to the 8 XCDs in turn (workgroup b on XCD b % 8).
-// xcd_range gives the workgroups of each XCD a contiguous range of the items,
-// so that work which varies with the item index in a period dividing 8 still
-// spreads evenly over the XCDs, and neighbouring rows meet in one L2.
-struct XcdRange { uint64_t first, end, step; };
-__device__ __forceinline__ XcdRange xcd_range(uint64_t items)
-{
-    const uint64_t nb = gridDim.x, b = blockIdx.x;
-    if (nb < 8) return {b, items, nb};
-    const uint64_t x = b % 8, q = items / 8, r = items % 8;
-    const uint64_t lo = x * q + (x < r ? x : r);
-    return {lo + b / 8, lo + q + (x < r ? 1 : 0), (nb - x + 7) / 8};
-}
-
-// The chunked order, for one workgroup per item: in each super-chunk of 8*Q
-// items, XCD x takes the Q consecutive items [x*Q, x*Q + Q) (its workgroups
-// in dispatch order), so each XCD works on contiguous runs while all XCDs move
-// through memory together, one front of writes instead of eight.  Items past
-// the last whole super-chunk keep their own index.
-__device__ __forceinline__ XcdRange xcd_chunk(uint64_t items)
-{
-    constexpr uint64_t Q = 64, S = 8 * Q;
-    const uint64_t b = blockIdx.x;
-    if (gridDim.x != items || b >= items / S * S) return {b, b + 1, 1};
-    const uint64_t l = b % S;
-    const uint64_t g = b - l + (l % 8) * Q + l / 8;
-    return {g, g + 1, 1};
-}
-
+// dummy state and write nothing.  Groups go to XCDs by xcd_chunk (or
+// xcd_range), gen_device.hpp.
 template <int DT, int L, int GL, class G>
 __global__ void __launch_bounds__(64)
 fill_coop_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t first,

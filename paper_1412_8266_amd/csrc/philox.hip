@@ -82,7 +82,12 @@ philox_sm_kernel(const uint32_t *__restrict__ planes, uint64_t plane_stride, uin
 {
     using T = typename PhiloxOut<DT>::T;
     const int tpr = 256 / rpw;
-    const uint64_t s = (uint64_t)blockIdx.x * rpw + threadIdx.x / tpr;
+    // several rows per workgroup: row groups in the chunked XCD order, so the
+    // rows whose states share a state-plane line run on one XCD and each line
+    // is fetched into one L2 (one row per workgroup keeps the dispatch order,
+    // measured faster for such long rows)
+    const uint64_t wg = rpw > 1 ? xcd_chunk(gridDim.x).first : blockIdx.x;
+    const uint64_t s = wg * rpw + threadIdx.x / tpr;
     if (s >= count || (int)threadIdx.x >= rpw * tpr) return;
     uint32_t w[6];
     load_state(planes, plane_stride, first + s, w);
