@@ -9,7 +9,8 @@
 //                         one e for the range)
 //   philox_sm_kernel      stream-major fill: each thread about 16 4-value
 //                         blocks of a row, consecutive threads on consecutive
-//                         blocks, 16-byte stores when a block is aligned
+//                         blocks, 16-byte stores when a block is aligned; row
+//                         groups placed on the XCDs in the chunked order
 //   philox_il_kernel      interleaved fill: one stream per lane, consecutive
 //                         lanes write consecutive elements
 // Fills do not move the positions; the host enqueues a uniform jump after them
