@@ -1,9 +1,7 @@
 """The public device headers (include/mrg32k3a_device.h, include/philox_device.h)
 are self-contained: user kernels that include only them compile for gfx950
-(compile only, no GPU).  Their draws are those of the library's fills, which
-are written with the same Stream type (MRG32k3a interleaved fill, batch row
-items) and the same Philox block and conversion functions, and checked
-against the oracle in the GPU parity tests."""
+(compile only, no GPU).  tests/test_gpu_device_api.py runs such user kernels
+on the GPU against the oracle."""
 import os
 import subprocess
 
