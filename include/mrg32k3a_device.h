@@ -57,6 +57,11 @@ struct GenI {
     __device__ __forceinline__ uint32_t next_u32() { return step(); }
     __device__ __forceinline__ float next_f32() { return to_f32(step()); }
     __device__ __forceinline__ double next_f64() { return to_f64(step()); }
+    // Same values (the integer combination has no cheaper form to check).
+    static constexpr bool kCheckedDraws = false;
+    __device__ __forceinline__ uint32_t next_u32(uint32_t &) { return next_u32(); }
+    __device__ __forceinline__ float next_f32(uint32_t &) { return next_f32(); }
+    __device__ __forceinline__ double next_f64(uint32_t &) { return next_f64(); }
 };
 
 // Binary64 generator: near-canonical integer-valued doubles, five FP64 operations
@@ -84,6 +89,29 @@ struct GenF {
     __device__ __forceinline__ uint32_t next_u32() { return (uint32_t)step(); }
     __device__ __forceinline__ float next_f32() { return to_f32f(step()); }
     __device__ __forceinline__ double next_f64() { return to_f64f(step()); }
+
+    // Checked draws: the state moves exactly as in step(), but the output
+    // takes the three-operation combination combinef_nn, which is exact
+    // unless the new component-2 word is negative (its residue within about
+    // 5 of m2, some 5 times in 2^32 outputs).  That case sets the sign bit of
+    // `neg`; a caller that sees it must replace the outputs drawn since it
+    // cleared `neg` by ones drawn with next_*() from the same state.
+    static constexpr bool kCheckedDraws = true;
+    __device__ __forceinline__ double step_nn(uint32_t &neg)
+    {
+        const double r1 = next1f(a0, a1);
+        const double r2 = next2f(b0, b2);
+        a0 = a1; a1 = a2; a2 = r1;
+        b0 = b1; b1 = b2; b2 = r2;
+        // one v_or_b32 per draw, kept as written: left to itself the compiler
+        // merges the ORs of an unrolled run of draws into 64-bit ORs at its
+        // end, which keeps every component-2 word of the run live until then
+        asm("v_or_b32 %0, %0, %1" : "+v"(neg) : "v"(__builtin_bit_cast(uint2, r2).y));
+        return combinef_nn(r1, r2);
+    }
+    __device__ __forceinline__ uint32_t next_u32(uint32_t &neg) { return (uint32_t)step_nn(neg); }
+    __device__ __forceinline__ float next_f32(uint32_t &neg) { return to_f32f(step_nn(neg)); }
+    __device__ __forceinline__ double next_f64(uint32_t &neg) { return to_f64f(step_nn(neg)); }
 };
 
 __device__ __forceinline__ void load_state(const uint32_t *planes, uint64_t stride, uint64_t idx,

@@ -113,7 +113,11 @@ mrg_status mrg_streamset_create_random(mrg_streamset *out, uint64_t n_streams,
  * (any 6 words are a state).  Substream jumps, leapfrog, batches and
  * mrg::Stream are MRG32k3a only and return MRG_EINVAL.  Sizes, errors and
  * ownership as mrg_streamset_create; mrg_streamset_info reports an all-zero
- * seed6. */
+ * seed6.
+ * Parity unpinned: the two round multipliers (0xD2511F53, 0xCD9E8D57) are
+ * typed from the published definition; no known-answer vector was available
+ * to check them, so agreement with other Philox4x32-10 implementations rests
+ * on those two constants (the oracle and the library agree bit for bit). */
 mrg_status mrg_streamset_create_philox(mrg_streamset *out, uint64_t n_streams,
                                        uint64_t first_stream, uint64_t key, void *stream);
 
@@ -147,7 +151,9 @@ mrg_status mrg_streamset_tables_ptr(mrg_streamset ss, const void **d_tables);
  * moved e_i outputs ahead, e_i given as 3 little-endian uint64 words at
  * d_exp[3*i .. 3*i+2] (device memory, e_i < 2^192).  Uses 4-bit windowed
  * tables of A^(d * 16^w) mod m staged in LDS.  count == 0 is a no-op.
- * Errors: MRG_EINVAL (null), MRG_ERANGE (range outside the set). */
+ * Errors: MRG_EINVAL (null, or d_exp not device memory of the set's device),
+ * MRG_ERANGE (range outside the set, or the 24 * count bytes at d_exp run
+ * past the end of their allocation). */
 mrg_status mrg_jump(mrg_streamset ss, uint64_t first, uint64_t count,
                     const uint64_t *d_exp, void *stream);
 
@@ -175,7 +181,9 @@ mrg_status mrg_jump_substreams(mrg_streamset ss, uint64_t first, uint64_t count,
  * row start works: each row is written in whole 128-byte lines after its
  * first line boundary).  n_per_stream == 0 or count == 0
  * is a no-op.  Errors: MRG_EINVAL (null d_out, bad dtype/layout,
- * misaligned), MRG_ERANGE (range outside the set). */
+ * misaligned, d_out not device (or managed) memory of the set's device),
+ * MRG_ERANGE (range outside the set, or the output runs past the end of the
+ * allocation holding d_out).  Nothing is enqueued on an error. */
 mrg_status mrg_fill(mrg_streamset ss, uint64_t first, uint64_t count,
                     uint64_t n_per_stream, mrg_dtype dtype, mrg_layout layout,
                     void *d_out, void *stream);
@@ -192,8 +200,9 @@ mrg_status mrg_fill(mrg_streamset ss, uint64_t first, uint64_t count,
  *                            splitting over the whole device)
  * Advances stream s by P * K.  d_out holds P * K elements of the dtype,
  * aligned to the element size.  P == 0 or K == 0 is a no-op.  Errors:
- * MRG_EINVAL (null d_out, bad dtype/layout, misaligned), MRG_ERANGE (s
- * outside the set, P * K * element size above 2^64 - 1). */
+ * MRG_EINVAL (null d_out, bad dtype/layout, misaligned, d_out not device
+ * memory of the set's device), MRG_ERANGE (s outside the set, P * K *
+ * element size above 2^64 - 1 or past the end of d_out's allocation). */
 mrg_status mrg_fill_leapfrog(mrg_streamset ss, uint64_t s, uint64_t players,
                              uint64_t per_player, mrg_dtype dtype, mrg_layout layout,
                              void *d_out, void *stream);
@@ -267,7 +276,9 @@ typedef struct mrg_batch_s *mrg_batch;
  * stream that a plain request advances, else MRG_EINVAL), cut them into
  * one-wave work items, group them by (dtype, item kind) and capture one
  * hipGraph (per group a counter reset and a persistent kernel, then the
- * copy-back of end states).  reqs is copied; cfg may be
+ * copy-back of end states).  Every non-empty request's d_out must be device
+ * memory of the set's device holding its output inside one allocation (else
+ * MRG_EINVAL / MRG_ERANGE naming the request).  reqs is copied; cfg may be
  * NULL.  The plan refers to ss and to the output buffers, which must outlive
  * it.  Free with mrg_batch_destroy. */
 mrg_status mrg_batch_create(mrg_batch *out, mrg_streamset ss, const mrg_request *reqs,
@@ -325,7 +336,8 @@ typedef struct {
     uint64_t n_clients;     /* client streams */
     uint64_t first_stream;  /* global index of client 0's stream */
     uint64_t master_seed;   /* base state via mrg_seed_from_master */
-    uint64_t arena_bytes;   /* device output arena: the admission cap */
+    uint64_t arena_bytes;   /* device output arena: the admission cap (rounded down to a
+                               multiple of 256 bytes, the arena's block unit; at least 256) */
     uint32_t max_inflight;  /* HIP streams, i.e. groups in flight (0: 8; at most 64) */
     uint32_t max_batch;     /* requests per group (0: 4096; at most 2^20) */
     uint32_t waves_per_cu;  /* persistent workgroups per CU per tick kernel (0: 8) */
@@ -452,7 +464,8 @@ mrg_status mrg_config_get(const char *key, int64_t *value);
  *              in LDS (bytes a multiple of 65536, d_out 128-byte aligned);
  *   pattern 2: the same 64 KiB per wave as runs of 8 lines (1 KiB) per store
  *              instruction (sizes and alignment as pattern 1).
- * Other patterns or sizes: MRG_EINVAL.  Asynchronous. */
+ * Other patterns or sizes, or d_out not device memory of the current device:
+ * MRG_EINVAL.  Asynchronous. */
 mrg_status mrg_write_probe(void *d_out, uint64_t bytes, int32_t pattern, void *stream);
 
 /* Static text of a status code. */

@@ -170,6 +170,28 @@ MRG_HD double combinef(double r1, double r2)
     return __builtin_fma(k, M1D, w);
 }
 
+// The same combination when r2 >= 0 (then r2 is already the canonical x2):
+// w = r1 - r2 lies in [-m2 - 4, m1 - 1] (r1 >= -5 and r2 < m2) and is
+// congruent to the combination mod m1, so z = w + m1 * [w <= 0] lands in
+// [m1 - m2 - 4, m1] as above; three operations instead of five.  For
+// r2 in [-5, 0) the result is wrong (x2 is r2 + m2 there); a caller that
+// uses this form must detect that case (the sign bit of r2) and recompute
+// with combinef.  The reductions give r2 < 0 only when the residue lies
+// within about 5.4 of m2, about 5 times in 2^32 outputs.
+MRG_HD double combinef_nn(double r1, double r2)
+{
+    const double w = r1 - r2;
+    const double k = __builtin_fmin(__builtin_fmax(1.0 - w, 0.0), 1.0);
+    return __builtin_fma(k, M1D, w);
+}
+
+// High word of a binary64 value: its sign bit is set for negative values
+// (and for -0.0, which the reductions never produce: a false alarm at worst).
+MRG_HD uint32_t hi_word(double x)
+{
+    return (uint32_t)(__builtin_bit_cast(uint64_t, x) >> 32);
+}
+
 // Canonical residue (as uint32) of a near-canonical word.
 MRG_HD uint32_t canonf(double r, double m)
 {
@@ -205,16 +227,16 @@ MRG_HD uint64_t splitmix64_next(uint64_t &x)
 // A 64-bit seed expanded into a valid state (random spacing, sec. 2.3):
 // successive SplitMix64 outputs mod m1 for words 0-2 and mod m2 for words
 // 3-5; a triple that comes out all zero (probability below 2^-95) is drawn
-// again, at most 16 times in all.
+// again, as often as it takes (the generator's outputs are a bijection of
+// its 2^64 states, so a nonzero triple always comes).
 MRG_HD void expand_seed(uint64_t seed, uint32_t out[6])
 {
     uint64_t x = seed;
     for (int c = 0; c < 2; ++c) {
         const uint64_t m = c ? M2 : M1;
-        for (int attempt = 0; attempt < 16; ++attempt) {
+        do {
             for (int i = 0; i < 3; ++i) out[3 * c + i] = (uint32_t)(splitmix64_next(x) % m);
-            if (out[3 * c] | out[3 * c + 1] | out[3 * c + 2]) break;
-        }
+        } while ((out[3 * c] | out[3 * c + 1] | out[3 * c + 2]) == 0u);
     }
 }
 

@@ -37,6 +37,21 @@ def torch_dtype(dtype: int):
     return {U32: torch.uint32, F32: torch.float32, F64: torch.float64}[dtype]
 
 
+def check_tensor(t, device: int, elems: int, esize: int, what: str = "output") -> None:
+    """Raise ValueError unless ``t`` is a contiguous tensor in the memory of GPU
+    ``device`` holding at least ``elems`` elements of ``esize`` bytes: the
+    kernels store through its address, so a host tensor must never reach
+    them (the C entry points check the pointer again)."""
+    if not getattr(t, "is_cuda", False):
+        raise ValueError("%s tensor must be on the GPU, not %s" % (what, getattr(t, "device", type(t))))
+    if t.device.index != device:
+        raise ValueError("%s tensor is on cuda:%s, the stream set on cuda:%d" % (what, t.device.index, device))
+    if t.numel() < elems or t.element_size() != esize:
+        raise ValueError("%s tensor too small or of the wrong element size" % what)
+    if not t.is_contiguous():
+        raise ValueError("%s tensor must be contiguous" % what)
+
+
 def _stream_handle(stream) -> int:
     torch = _torch()
     if stream is None:
@@ -83,6 +98,7 @@ class StreamSet:
             self._h = _abi.mrg_streamset_create_seed64(n_streams, first_stream, master_seed, h)
         self.n_streams = int(n_streams)
         self.first_stream = int(first_stream)
+        self.device = _torch().cuda.current_device()  # the set's states live here
 
     # -- lifetime -----------------------------------------------------------
     def close(self) -> None:
@@ -135,12 +151,9 @@ class StreamSet:
         first, count = self._range(first, count)
         shape = (count, n) if layout == STREAM_MAJOR else (n, count)
         if out is None:
-            out = torch.empty(shape, dtype=torch_dtype(dtype), device="cuda")
+            out = torch.empty(shape, dtype=torch_dtype(dtype), device="cuda:%d" % self.device)
         else:
-            if out.numel() < count * n or out.element_size() != _ESIZE[dtype]:
-                raise ValueError("output tensor too small or of the wrong element size")
-            if not out.is_contiguous():
-                raise ValueError("output tensor must be contiguous")
+            check_tensor(out, self.device, count * n, _ESIZE[dtype])
         _abi.mrg_fill(self._h, first, count, n, dtype, layout,
                       out.data_ptr() if out.numel() else 0, _stream_handle(stream))
         return out
@@ -159,10 +172,9 @@ class StreamSet:
         torch = _torch()
         shape = (players, per_player) if layout == STREAM_MAJOR else (per_player, players)
         if out is None:
-            out = torch.empty(shape, dtype=torch_dtype(dtype), device="cuda")
-        elif (out.numel() < players * per_player or out.element_size() != _ESIZE[dtype]
-              or not out.is_contiguous()):
-            raise ValueError("output tensor too small, of the wrong element size or not contiguous")
+            out = torch.empty(shape, dtype=torch_dtype(dtype), device="cuda:%d" % self.device)
+        else:
+            check_tensor(out, self.device, players * per_player, _ESIZE[dtype])
         _abi.mrg_fill_leapfrog(self._h, s, players, per_player, dtype, layout,
                                out.data_ptr() if out.numel() else 0, _stream_handle(stream))
         return out
@@ -172,8 +184,7 @@ class StreamSet:
         """Jump stream first+i by exps[i]; ``exps`` is a device uint64 tensor
         [count, 3] (little-endian words of each exponent)."""
         first, count = self._range(first, count)
-        if exps.numel() < 3 * count or not exps.is_cuda or exps.element_size() != 8:
-            raise ValueError("exps must be a CUDA tensor of >= 3*count 64-bit words")
+        check_tensor(exps, self.device, 3 * count, 8, "exponent")
         _abi.mrg_jump(self._h, first, count, exps.data_ptr(), _stream_handle(stream))
 
     def jump_uniform(self, e: int, first: int = 0, count: Optional[int] = None,
@@ -200,7 +211,7 @@ class StreamSet:
 __all__ = [
     "StreamSet", "MRGError", "U32", "F32", "F64", "STREAM_MAJOR", "INTERLEAVED", "M1", "M2",
     "mrg_seed_from_master", "mrg_jump_matrix", "mrg_state_check", "mrg_config_set",
-    "mrg_config_get", "mrg_version", "torch_dtype", "write_probe",
+    "mrg_config_get", "mrg_version", "torch_dtype", "write_probe", "check_tensor",
 ]
 
 

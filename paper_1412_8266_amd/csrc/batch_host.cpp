@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdio>
 #include <cstring>
 #include <iterator>
 #include <new>
@@ -301,6 +302,11 @@ mrg_status validate(mrg_streamset ss, const mrg_request *reqs, uint64_t n)
                              (unsigned long long)i);
         if (q.n_per_stream > UINT64_MAX / es / q.count)
             return set_error(MRG_ERANGE, "request %llu: output size overflows", (unsigned long long)i);
+        char what[64];
+        snprintf(what, sizeof what, "request %llu: output", (unsigned long long)i);
+        if (mrg_status st = mrg::check_device_span(q.d_out, q.count * q.n_per_stream * es,
+                                                   ss->device, what))
+            return st;
         if (q.flags & MRG_REQ_SUBSTREAMS) {
             if (q.first >= ss->n)
                 return set_error(MRG_ERANGE, "request %llu: stream outside the set", (unsigned long long)i);

@@ -43,6 +43,28 @@ __device__ __forceinline__ uint4 gen16(G &g)
     return v;
 }
 
+// The same 16 bytes from checked draws (G::kCheckedDraws): exact unless the
+// sign bit of `neg` comes out set (see GenF).
+template <int DT, class G>
+__device__ __forceinline__ uint4 gen16(G &g, uint32_t &neg)
+{
+    uint4 v;
+    if constexpr (DT == 0) {
+        v.x = g.next_u32(neg); v.y = g.next_u32(neg); v.z = g.next_u32(neg); v.w = g.next_u32(neg);
+    } else if constexpr (DT == 1) {
+        v.x = __float_as_uint(g.next_f32(neg));
+        v.y = __float_as_uint(g.next_f32(neg));
+        v.z = __float_as_uint(g.next_f32(neg));
+        v.w = __float_as_uint(g.next_f32(neg));
+    } else {
+        const uint64_t u0 = (uint64_t)__double_as_longlong(g.next_f64(neg));
+        const uint64_t u1 = (uint64_t)__double_as_longlong(g.next_f64(neg));
+        v.x = (uint32_t)u0; v.y = (uint32_t)(u0 >> 32);
+        v.z = (uint32_t)u1; v.w = (uint32_t)(u1 >> 32);
+    }
+    return v;
+}
+
 template <int DT, class G>
 __device__ __forceinline__ void put1(unsigned char *p, G &g)
 {
@@ -55,7 +77,9 @@ __device__ __forceinline__ void put1(unsigned char *p, G &g)
 // base goes into a raw buffer descriptor in scalar registers (word 3 0x20000:
 // 32-bit data format, as gfx9 raw buffers take it), so a lane spends no vector
 // instruction on its 64-bit address.  Offsets at or past span are dropped.
+// AUX is the instruction's cache-policy field (0: the default write-back).
 typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+template <int AUX = 0>
 __device__ __forceinline__ void store16_uniform(const unsigned char *base, uint32_t off,
                                                 uint32_t span, uint4 v)
 {
@@ -64,7 +88,7 @@ __device__ __forceinline__ void store16_uniform(const unsigned char *base, uint3
                         (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32)) << 32;
     const __amdgpu_buffer_rsrc_t r =
         __builtin_amdgcn_make_buffer_rsrc((void *)bu, 0, (int)span, 0x00020000);
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, v), r, off, 0, 0);
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, v), r, off, 0, AUX);
 }
 
 template <int ES>
@@ -245,10 +269,15 @@ __device__ __forceinline__ void rows_fill_short(G &g, unsigned char *lds, int la
 // writes the same lines up to each row's end (16-byte stores, dwords for the
 // last group), and the stream's state is then moved over that chunk with the
 // windowed tables.  `lds` holds 64 * 144 bytes.
+// With a generator that has checked draws (GenF), each piece is drawn with
+// the cheaper combination; in the rare piece where some lane's check fails,
+// the whole wave draws the piece again exactly, from the chunk's first state
+// jumped to the piece (the generator state itself is exact either way).
 // READ_ALL: read all eight LDS pieces of a flush before the first store (else
-// each piece goes straight to memory).
+// each piece goes straight to memory).  AUX: cache policy of the whole-line
+// stores.
 // ---------------------------------------------------------------------------
-template <int DT, int L, class G, bool READ_ALL = true, int GL = 64>
+template <int DT, int L, class G, bool READ_ALL = true, int GL = 64, int AUX = 0>
 __device__ __forceinline__ void wave_fill(uint32_t *w, const uint32_t *m, unsigned char *lds,
                                           int lane, unsigned char *srow, uint64_t row_stride,
                                           int nsv, uint64_t v0, uint64_t v1,
@@ -344,8 +373,23 @@ __device__ __forceinline__ void wave_fill(uint32_t *w, const uint32_t *m, unsign
         G g;
         g.load(st);
         for (int h = 0; h < h_end; ++h) {
+            if constexpr (G::kCheckedDraws) {
+                uint32_t neg = 0;
 #pragma unroll
-            for (int q = 0; q < 8; ++q) *(uint4 *)(my_lds + q * 16) = gen16<DT>(g);
+                for (int q = 0; q < 8; ++q) *(uint4 *)(my_lds + q * 16) = gen16<DT>(g, neg);
+                if (__any((int32_t)neg < 0)) {
+                    // this member's piece h starts gl*Lc + h*TV values into the chunk
+                    uint32_t ps[6] = {w[0], w[1], w[2], w[3], w[4], w[5]};
+                    jump_global(table, (uint64_t)gl * Lc + (uint64_t)h * TV, 0, 0, 0, 16, ps);
+                    G ge;
+                    ge.load(ps);
+#pragma unroll 1
+                    for (int q = 0; q < 8; ++q) *(uint4 *)(my_lds + q * 16) = gen16<DT>(ge);
+                }
+            } else {
+#pragma unroll
+                for (int q = 0; q < 8; ++q) *(uint4 *)(my_lds + q * 16) = gen16<DT>(g);
+            }
             __syncthreads();
             // piece row prow + 8j is stream j / JPS, member prow + 8 (j % JPS);
             // each piece is one aligned 128-byte line of the row
@@ -361,8 +405,8 @@ __device__ __forceinline__ void wave_fill(uint32_t *w, const uint32_t *m, unsign
                         const uint64_t ct = v0 + hvt[t] + c * chunk_vals;
                         if ((SPW > 1 && t >= nsv) || ct + chunk_vals > v1) continue;
                         const uint32_t loff = (uint32_t)((prow + 8 * (j % JPS)) * L * ES + pcol);
-                        store16_uniform(srow + t * row_stride + (ct + (uint64_t)h * TV) * ES, loff,
-                                        (uint32_t)(GL * L * ES), v[j]);
+                        store16_uniform<AUX>(srow + t * row_stride + (ct + (uint64_t)h * TV) * ES,
+                                             loff, (uint32_t)(GL * L * ES), v[j]);
                     }
                 } else {
 #pragma unroll
@@ -372,8 +416,8 @@ __device__ __forceinline__ void wave_fill(uint32_t *w, const uint32_t *m, unsign
                         if ((SPW > 1 && t >= nsv) || ct + chunk_vals > v1) continue;
                         const uint4 v = *(const uint4 *)(lds + (prow + 8 * j) * RS + pcol);
                         const uint32_t loff = (uint32_t)((prow + 8 * (j % JPS)) * L * ES + pcol);
-                        store16_uniform(srow + t * row_stride + (ct + (uint64_t)h * TV) * ES, loff,
-                                        (uint32_t)(GL * L * ES), v);
+                        store16_uniform<AUX>(srow + t * row_stride + (ct + (uint64_t)h * TV) * ES,
+                                             loff, (uint32_t)(GL * L * ES), v);
                     }
                 }
             } else {

@@ -235,6 +235,34 @@ mrg_status check_streamset(mrg_streamset ss)
     return MRG_OK;
 }
 
+mrg_status check_device_span(const void *p, uint64_t bytes, int dev, const char *what)
+{
+    hipPointerAttribute_t a;
+    hipError_t e = hipPointerGetAttributes(&a, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();  // keep the failed lookup from reaching a later launch check
+        return set_error(MRG_EINVAL, "%s (%p) is not memory known to HIP: %s", what, p,
+                         hipGetErrorString(e));
+    }
+    const bool managed = a.type == hipMemoryTypeManaged || a.isManaged;
+    if (!managed && !(a.type == hipMemoryTypeDevice && a.device == dev))
+        return set_error(MRG_EINVAL, "%s (%p) is not device memory of device %d (memory type %d, "
+                         "device %d)", what, p, dev, (int)a.type, a.device);
+    hipDeviceptr_t base = nullptr;
+    size_t size = 0;
+    e = hipMemGetAddressRange(&base, &size, (hipDeviceptr_t)p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return MRG_OK;  // no extent known: the type check above is all there is
+    }
+    const uint64_t off = (uint64_t)((uintptr_t)p - (uintptr_t)base);
+    if (off > size || bytes > size - off)
+        return set_error(MRG_ERANGE, "%s (%p, %llu bytes) extends past the end of its allocation "
+                         "(%llu bytes at %p)", what, p, (unsigned long long)bytes,
+                         (unsigned long long)size, (void *)base);
+    return MRG_OK;
+}
+
 mrg_status check_range(mrg_streamset ss, uint64_t first, uint64_t count)
 {
     if (first > ss->n || count > ss->n - first)
@@ -459,6 +487,7 @@ mrg_status mrg_jump(mrg_streamset ss, uint64_t first, uint64_t count, const uint
     if ((st = check_range(ss, first, count))) return st;
     if (count == 0) return MRG_OK;
     if (!d_exp) return set_error(MRG_EINVAL, "null exponent array");
+    if ((st = mrg::check_device_span(d_exp, 24 * count, ss->device, "exponent array"))) return st;
     if (ss->gen == 1) {  // the position moves by e mod 2^64
         hipError_t e = mrg::launch_philox_jump(ss->d_planes, ss->n, first, count, d_exp, 0,
                                                (hipStream_t)stream);
@@ -515,6 +544,8 @@ mrg_status mrg_fill(mrg_streamset ss, uint64_t first, uint64_t count, uint64_t n
     if ((uintptr_t)d_out % es) return set_error(MRG_EINVAL, "output not aligned to its element size");
     if (n_per_stream > UINT64_MAX / es / count)
         return set_error(MRG_ERANGE, "output size overflows 64 bits");
+    if ((st = mrg::check_device_span(d_out, count * n_per_stream * es, ss->device, "output")))
+        return st;
     if (ss->gen == 1) {
         hipError_t e = mrg::launch_philox_fill(ss->d_planes, ss->n, first, count, n_per_stream,
                                                (int)dtype, (int)layout, d_out, (hipStream_t)stream);
@@ -590,6 +621,7 @@ mrg_status mrg_fill_leapfrog(mrg_streamset ss, uint64_t s, uint64_t players,
     if (players > UINT64_MAX / per_player || players * per_player > UINT64_MAX / es)
         return set_error(MRG_ERANGE, "players * per_player * element size overflows 64 bits");
     const uint64_t N = players * per_player;
+    if ((st = mrg::check_device_span(d_out, N * es, ss->device, "output"))) return st;
     DevCtx *ctx;
     if ((st = device_ctx(ss->device, &ctx))) return st;
     const mrg::FillTuning tune = tuning();
@@ -774,6 +806,7 @@ mrg_status mrg_write_probe(void *d_out, uint64_t bytes, int32_t pattern, void *s
     int dev;
     mrg_status st = current_device(&dev);
     if (st) return st;
+    if ((st = mrg::check_device_span(d_out, bytes, dev, "probe output"))) return st;
     hipError_t e = mrg::launch_write_probe(d_out, bytes, pattern, (hipStream_t)stream);
     return e == hipSuccess ? MRG_OK : hip_error(e, "probe launch");
 }

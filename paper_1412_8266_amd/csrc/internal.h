@@ -34,5 +34,9 @@ FillTuning current_tuning();
 // Stream set usable on the current device; range inside the set.
 mrg_status check_streamset(mrg_streamset ss);
 mrg_status check_range(mrg_streamset ss, uint64_t first, uint64_t count);
+// [p, p + bytes) is device memory of device dev (or managed memory) inside
+// one allocation, else MRG_EINVAL / MRG_ERANGE naming `what`.  Kernels store
+// through such pointers, so a host address must never reach them.
+mrg_status check_device_span(const void *p, uint64_t bytes, int dev, const char *what);
 
 }  // namespace mrg

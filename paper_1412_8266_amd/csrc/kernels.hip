@@ -185,9 +185,10 @@ fill_il_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t fi
 // wave_fill, so that every flush writes whole 128-byte lines and the streams
 // in flight stay adjacent.  Lanes of a group past the last stream run on a
 // dummy state and write nothing.  Groups go to XCDs by xcd_chunk (or
-// xcd_range), gen_device.hpp.
+// xcd_range), gen_device.hpp.  Four waves per SIMD is what the LDS allows
+// (9 KiB per wave); the bound keeps the register count inside that.
 template <int DT, int L, int GL, class G>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(64, 4)
 fill_coop_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t first,
                  uint64_t count, uint64_t n, unsigned char *__restrict__ out,
                  const uint32_t *__restrict__ lane_tab, const uint32_t *__restrict__ tabs,
@@ -198,9 +199,6 @@ fill_coop_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t 
     __shared__ __attribute__((aligned(16))) unsigned char lds[64 * 144];
     const int lane = threadIdx.x;
     const int t = lane / GL;  // this lane's stream within the group
-    uint32_t m[18];
-#pragma unroll
-    for (int i = 0; i < 18; ++i) m[i] = lane_tab[(lane % GL) * 18 + i];
 
     const uint64_t groups = (count + SPW - 1) / SPW;
     const XcdRange R = order == 0 && gridDim.x == groups ? xcd_chunk(groups) : xcd_range(groups);
@@ -210,6 +208,11 @@ fill_coop_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t 
         const uint64_t idx = first + s0 + t;
         uint32_t w[6] = {1u, 1u, 1u, 1u, 1u, 1u};
         if (t < nsv) load_state(planes, plane_stride, idx, w);
+        // this member's lane matrix, loaded per group (L2-resident) so that it
+        // holds no registers while the group's values are drawn
+        uint32_t m[18];
+#pragma unroll
+        for (int i = 0; i < 18; ++i) m[i] = lane_tab[(lane % GL) * 18 + i];
         wave_fill<DT, L, G, true, GL>(w, m, lds, lane, out + s0 * n * ES, n * ES, nsv, 0, n, table,
                                       tabs, true);
         if (lane % GL == 0 && t < nsv) store_state(planes, plane_stride, idx, w);

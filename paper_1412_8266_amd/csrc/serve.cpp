@@ -308,7 +308,10 @@ mrg_status mrg_server_create(mrg_server *out, const mrg_server_config *cfg_in)
     *out = nullptr;
     mrg_server_config cfg = *cfg_in;
     if (!cfg.n_clients) return set_error(MRG_ERANGE, "n_clients must be >= 1");
-    if (!cfg.arena_bytes) return set_error(MRG_ERANGE, "arena_bytes must be > 0");
+    // the arena hands out 256-byte-aligned blocks of whole 256-byte units, so
+    // only whole units of it can ever be used
+    cfg.arena_bytes = cfg.arena_bytes / 256 * 256;
+    if (!cfg.arena_bytes) return set_error(MRG_ERANGE, "arena_bytes must be at least 256");
     if (!cfg.max_inflight) cfg.max_inflight = 8;
     if (!cfg.max_batch) cfg.max_batch = 4096;
     if (!cfg.waves_per_cu) cfg.waves_per_cu = 8;
@@ -380,7 +383,10 @@ mrg_status mrg_server_submit(mrg_server s, uint64_t client, uint64_t n_streams,
         return set_error(MRG_EINVAL, "unknown dtype");
     if (!n_streams || !n_per_stream) return set_error(MRG_EINVAL, "empty request");
     const uint64_t es = dtype == MRG_F64 ? 8 : 4;
-    if (n_per_stream > s->cfg.arena_bytes / es / n_streams)
+    // compared as the arena will hold it (rounded up to 256 bytes), so that a
+    // request admitted here always fits once the arena is empty
+    if (n_per_stream > s->cfg.arena_bytes / es / n_streams ||
+        (n_streams * n_per_stream * es + 255) / 256 * 256 > s->cfg.arena_bytes)
         return set_error(MRG_ERANGE, "request larger than the arena");
     Req r;
     r.client = client;

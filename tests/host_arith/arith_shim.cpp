@@ -40,7 +40,45 @@ void shim_run_f64(uint32_t *w, uint64_t n, uint32_t *out, float *outf, double *o
     w[3] = canonf(b0, M2D); w[4] = canonf(b1, M2D); w[5] = canonf(b2, M2D);
 }
 
+// Checked draws as the wave writer takes them: blocks of `block` values drawn
+// with the three-operation combination while the high words of the new
+// component-2 words are or-ed together; a block whose or comes out with the
+// sign bit set is drawn again, exactly, from the state it started at.
+// Returns the number of blocks drawn again; w as in shim_run_f64.
+uint64_t shim_run_f64_checked(uint32_t *w, uint64_t n, uint64_t block, uint32_t *out)
+{
+    double a0 = w[0], a1 = w[1], a2 = w[2], b0 = w[3], b1 = w[4], b2 = w[5];
+    uint64_t redrawn = 0;
+    for (uint64_t k0 = 0; k0 < n; k0 += block) {
+        const uint64_t k1 = k0 + block < n ? k0 + block : n;
+        const double s[6] = {a0, a1, a2, b0, b1, b2};
+        uint32_t neg = 0;
+        for (uint64_t k = k0; k < k1; ++k) {
+            const double r1 = next1f(a0, a1), r2 = next2f(b0, b2);
+            a0 = a1; a1 = a2; a2 = r1;
+            b0 = b1; b1 = b2; b2 = r2;
+            neg |= hi_word(r2);
+            out[k] = (uint32_t)combinef_nn(r1, r2);
+        }
+        if ((int32_t)neg < 0) {
+            ++redrawn;
+            double c0 = s[0], c1 = s[1], c2 = s[2], d0 = s[3], d1 = s[4], d2 = s[5];
+            for (uint64_t k = k0; k < k1; ++k) {
+                const double r1 = next1f(c0, c1), r2 = next2f(d0, d2);
+                c0 = c1; c1 = c2; c2 = r1;
+                d0 = d1; d1 = d2; d2 = r2;
+                out[k] = (uint32_t)combinef(r1, r2);
+            }
+        }
+    }
+    w[0] = canonf(a0, M1D); w[1] = canonf(a1, M1D); w[2] = canonf(a2, M1D);
+    w[3] = canonf(b0, M2D); w[4] = canonf(b1, M2D); w[5] = canonf(b2, M2D);
+    return redrawn;
+}
+
 uint32_t shim_combine(uint32_t x1, uint32_t x2) { return combine(x1, x2); }
+double shim_combinef_nn(double r1, double r2) { return combinef_nn(r1, r2); }
+uint32_t shim_hi_word(double x) { return hi_word(x); }
 double shim_combinef(double r1, double r2) { return combinef(r1, r2); }
 double shim_next1f(double s0, double s1) { return next1f(s0, s1); }
 double shim_next2f(double s3, double s5) { return next2f(s3, s5); }

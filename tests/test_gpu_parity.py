@@ -3,9 +3,10 @@
 Every output of every dtype must equal the oracle's (tolerance 0: the
 generator is an exact integer recurrence and both conversions are defined
 by a single rounding or none).  Small cases span several LDS tiles and
-ragged tails; the full-size workloads are checked on sampled streams that
-the oracle recomputes one by one, plus properties over every output.
+ragged tails; the headline workload (2^20 streams x 4096) is checked in
+full, slice by slice, against the oracle run on several threads.
 """
+import os
 import sys
 
 import numpy as np
@@ -258,34 +259,145 @@ def test_c3_full(mg, engine):
     ss.close()
 
 
-@pytest.mark.parametrize("dtype", [0, 1], ids=["u32", "f32"])
-def test_c2_full_size_sampled(mg, dtype):
-    """The benchmark's launch: 2^20 streams x 4096 outputs (16 GiB).  Sampled
-    streams are recomputed by the oracle in full; every output is range
-    checked; end states of sampled streams equal the oracle's."""
+@pytest.mark.parametrize("dtype", [0, 1, 2], ids=["u32", "f32", "f64"])
+def test_negative_component2_words(mg, engine, dtype):
+    """Streams steered so that one output each draws the component-2 residue
+    m2 - 1 or m2 - 2, where the binary64 reduction's biased quotient is one
+    too big and the word comes out negative: the wave-per-stream writer's
+    checked draws must draw that piece again.  Positions fall in row heads,
+    first and last pieces, chunk and member boundaries and row tails, for
+    aligned and unaligned rows, inside guard words."""
     import torch
-    say("C2 full", dtype)
-    base = oracle.seed_from_master(wl.MASTER_SEED)
+    from tests import crafted
+    rng = np.random.default_rng(77)
+    es = 8 if dtype == 2 else 4
+    for n, off in [(4096, 0), (5000, 3), (2048, 0), (9000, 1), (300, 1)]:
+        pos = {0, 1, 2, 31, 32, 33, 63, 64, 127, 128, 255, 256, 257, 511, 512, 1023, 1024,
+               n - 33, n - 32, n - 2, n - 1} | set(int(x) for x in rng.integers(0, n, 12))
+        positions = sorted(k for k in pos if 0 <= k < n)
+        starts = crafted.hits(positions, [oracle.M2 - 1, oracle.M2 - 2], seed=n + dtype)
+        S = len(starts)
+        say("negative words", engine, dtype, n, off, S)
+        ss = mg.StreamSet(S, master_seed=1)
+        ss.set_states(starts)
+        guard = 16
+        buf = torch.zeros(S * n + off + 2 * guard, dtype=mg.torch_dtype(dtype), device="cuda")
+        ss.fill_ptr(n, dtype, mg.STREAM_MAJOR, buf.data_ptr() + (guard + off) * es)
+        h = host(buf)
+        want, st = oracle.fill(starts, n, dtype)
+        got = h[guard + off:guard + off + S * n]
+        assert np.array_equal(got.view(np.uint8), want.reshape(-1).view(np.uint8)), (n, off)
+        assert not h[:guard + off].view(np.uint8).any() and not h[guard + off + S * n:].view(np.uint8).any()
+        assert np.array_equal(ss.get_states(), st), (n, off)
+        ss.close()
+
+
+def test_negative_component2_words_batch_and_deal(mg):
+    """The same steered streams through the other users of the wave writer:
+    the persistent batch's stream segments and the in-order leapfrog deal."""
+    import torch
+    from tests import crafted
+    n = 40000  # 160 KiB per stream: several batch segments
+    positions = [0, 33, 4095, 4096, 16383, 16384, 20000, 32768, 39999]
+    starts = crafted.hits(positions, [oracle.M2 - 1, oracle.M2 - 2], seed=3)
+    S = len(starts)
+    ss = mg.StreamSet(S, master_seed=2)
+    ss.set_states(starts)
+    out = torch.zeros((S, n), dtype=torch.uint32, device="cuda")
+    b = mg.Batch(ss, [(0, 4, n, 0, out.data_ptr(), mg.U32, 0),
+                      (4, S - 4, n, 0, out[4].data_ptr(), mg.U32, 0)],
+                 mg.batch_config(segment_bytes=64 << 10))
+    b.run()
+    want, st = oracle.fill(starts, n, oracle.U32)
+    assert np.array_equal(host(out), want)
+    assert np.array_equal(ss.get_states(), st)
+    b.close()
+    ss.close()
+    # one stream dealt in order: P * K outputs of it, blocks of 16-256 KiB
+    k = 300001
+    start = crafted.hits([k], [oracle.M2 - 1], seed=4)[0]
+    ss = mg.StreamSet(1, master_seed=3)
+    ss.set_states(start[None, :])
+    P, K = 1000, 700
+    got = host(ss.fill_leapfrog(0, P, K, mg.U32, mg.INTERLEAVED))
+    want, st = oracle.fill(start[None, :], P * K, oracle.U32)
+    assert np.array_equal(got.reshape(-1), want[0])
+    assert np.array_equal(ss.get_states(), st)
+    ss.close()
+
+
+def oracle_threaded(st, n, dtype, layout=oracle.STREAM_MAJOR):
+    """oracle.fill over the rows of st, split across up to 16 threads (the C
+    oracle runs outside the interpreter lock); same result as one call."""
+    from concurrent.futures import ThreadPoolExecutor
+    threads = max(1, min(16, os.cpu_count() or 1))
+    parts = [ix for ix in np.array_split(np.arange(len(st)), threads) if len(ix)]
+    with ThreadPoolExecutor(len(parts)) as ex:
+        res = list(ex.map(lambda ix: oracle.fill(st[ix[0]:ix[-1] + 1], n, dtype, layout), parts))
+    axis = 0 if layout == oracle.STREAM_MAJOR else 1
+    return np.concatenate([r[0] for r in res], axis=axis), np.concatenate([r[1] for r in res])
+
+
+@pytest.mark.parametrize("dtype,layout", [(0, 0), (1, 0), (0, 1)], ids=["u32-sm", "f32-sm", "u32-il"])
+def test_c2_full(mg, dtype, layout):
+    """The benchmark's workload in full: 2^20 streams from the master seed,
+    4096 outputs each (16 GiB), every output and every end state against the
+    oracle, copied back and recomputed in slices of 2^15 streams."""
+    import torch
     S, n = wl.C2_STREAMS, wl.C2_N
+    say("C2 full", dtype, layout)
+    base = oracle.seed_from_master(wl.MASTER_SEED)
+    st0 = oracle.streams_adjacent(base, 0, S)
     ss = mg.StreamSet(S, master_seed=wl.MASTER_SEED)
-    out = ss.fill(n, dtype)
+    assert np.array_equal(ss.get_states(), st0)
+    out = ss.fill(n, dtype, layout)
     torch.cuda.synchronize()
-    rng = np.random.default_rng(1234)
-    idx = np.unique(np.concatenate([[0, 1, 63, 64, S - 1], rng.integers(0, S, 300)]))
-    rows = host(out.view(torch.int32)[torch.from_numpy(idx).cuda()]).view(np.uint32)
-    for j, g in enumerate(idx):
-        want, st = oracle.fill(oracle.stream_start(base, int(g))[None, :], n, dtype)
-        assert np.array_equal(rows[j], want[0].view(np.uint32)), g
-        assert np.array_equal(ss.get_states(int(g), 1)[0], st[0]), g
-    if dtype == 0:
-        o = out.view(torch.int32)
-        # uint32 values lie in [1, m1]: as int32, either >= 1 or <= m1 - 2^32
-        lo = (o >= 1) | (o <= oracle.M1 - 2**32)
-        assert bool(lo.all())
-    else:
-        assert bool(((out > 0) & (out < 1)).all())
+    ends = []
+    ch = 1 << 15
+    for c0 in range(0, S, ch):
+        part = out[c0:c0 + ch] if layout == 0 else out[:, c0:c0 + ch].contiguous()
+        got = host(part)
+        want, st = oracle_threaded(st0[c0:c0 + ch], n, dtype, layout)
+        assert np.array_equal(got.view(np.uint32), want.view(np.uint32)), c0
+        ends.append(st)
+        del part, got, want
+    assert np.array_equal(ss.get_states(), np.concatenate(ends))
     del out
     ss.close()
+
+
+# whole and partial super-chunks of 512 stream groups (16 lanes per stream
+# below 64 KiB rows, 4 streams per group; one stream per group from 64 KiB)
+PLACEMENT_SHAPES = [(3000, 4096, 0), (4100, 4096, 0), (2052, 2048, 0), (1100, 20000, 0),
+                    (600, 4100, 2), (2049, 3000, 1)]
+PLACEMENT_KNOBS = [(1, 0, 0), (1, 1, 0), (1, 0, 1), (1, 0, 3), (1, 1, 2), (0, 0, 0), (0, 1, 3)]
+
+
+@pytest.mark.parametrize("knobs", PLACEMENT_KNOBS,
+                         ids=["chunked", "ranges", "persist1", "persist3", "ranges-persist2",
+                              "int-chunked", "int-ranges-persist3"])
+def test_wave_writer_placements(mg, knobs):
+    """The wave-per-stream writer's group placements (chunked XCD order with
+    its tail of groups past the last whole super-chunk, one range per XCD,
+    persistent workgroups looping over groups: settings that promise no
+    effect on results) against the oracle, every output and end state."""
+    keys = ("engine", "coop_order", "coop_wgs_per_cu")
+    old = [mg.mrg_config_get(k) for k in keys]
+    base = oracle.seed_from_master(31)
+    try:
+        for k, v in zip(keys, knobs):
+            mg.mrg_config_set(k, v)
+        for count, n, dtype in PLACEMENT_SHAPES:
+            say("placement", knobs, count, n, dtype)
+            ss = mg.StreamSet(count + 5, seed=[int(x) for x in base])
+            got = host(ss.fill(n, dtype, first=5, count=count))
+            want, st = oracle_threaded(oracle.streams(base, 5, count), n, dtype)
+            assert np.array_equal(got.view(np.uint8), want.view(np.uint8)), (count, n, dtype)
+            assert np.array_equal(ss.get_states(5, count), st), (count, n, dtype)
+            ss.close()
+    finally:
+        for k, v in zip(keys, old):
+            mg.mrg_config_set(k, v)
 
 
 def test_random_fill_sweep(mg):

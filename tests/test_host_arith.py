@@ -34,6 +34,12 @@ def shim(tmp_path_factory):
     lib.shim_combine.restype = ctypes.c_uint32
     lib.shim_combinef.argtypes = [ctypes.c_double, ctypes.c_double]
     lib.shim_combinef.restype = ctypes.c_double
+    lib.shim_combinef_nn.argtypes = [ctypes.c_double, ctypes.c_double]
+    lib.shim_combinef_nn.restype = ctypes.c_double
+    lib.shim_hi_word.argtypes = [ctypes.c_double]
+    lib.shim_hi_word.restype = ctypes.c_uint32
+    lib.shim_run_f64_checked.argtypes = [P, ctypes.c_uint64, ctypes.c_uint64, P]
+    lib.shim_run_f64_checked.restype = ctypes.c_uint64
     for n in ("shim_next1f", "shim_next2f"):
         getattr(lib, n).argtypes = [ctypes.c_double, ctypes.c_double]
         getattr(lib, n).restype = ctypes.c_double
@@ -143,6 +149,55 @@ def test_combinef_boundaries(shim):
         assert shim.shim_canonf(float(r), 0) == r % M1
     for r in (-5, -1, 0, 1, M2 - 1):
         assert shim.shim_canonf(float(r), 1) == r % M2
+
+
+def test_checked_combination(shim):
+    """The three-operation combination equals the exact one whenever the
+    component-2 word is non-negative, and the sign bit of its high word
+    flags every negative one (the case it gets wrong)."""
+    rng = random.Random(13)
+    r1s = ([-5, -4, -1, 0, 1, 2, 22643, 22644, 22645, M2 - 1, M2, M1 - 2, M1 - 1, 2**31]
+           + [rng.randrange(-5, M1) for _ in range(300)])
+    r2s = ([-5, -4, -3, -2, -1, 0, 1, 2, 22644, M2 - 2, M2 - 1, 2**31]
+           + [rng.randrange(-5, M2) for _ in range(300)])
+    for r1 in r1s:
+        for r2 in r2s:
+            flagged = shim.shim_hi_word(float(r2)) >> 31
+            assert flagged == (r2 < 0), (r1, r2)
+            if r2 >= 0:
+                assert shim.shim_combinef_nn(float(r1), float(r2)) == \
+                    shim.shim_combinef(float(r1), float(r2)), (r1, r2)
+
+
+def test_checked_draws_redraw_exactly_where_needed(shim):
+    """Streams steered so that output k draws the component-2 residue m2 - 1
+    or m2 - 2 (where the binary64 reduction's biased quotient is one too big,
+    so the word comes out negative): the checked run flags those blocks,
+    draws them again and matches the oracle; untouched streams never redraw."""
+    from tests import crafted
+    n, block = 300, 32
+    positions = [0, 1, 2, 31, 32, 33, 95, 150, 255, 299]
+    starts = crafted.hits(positions, [M2 - 1, M2 - 2], seed=5)
+    for k, s in zip(positions, starts):
+        # the kernel arithmetic itself: the word drawn at output k is negative
+        w = s.copy()
+        got = np.empty(n, dtype=np.uint32)
+        if k:
+            gf, gd = np.empty(k, np.float32), np.empty(k, np.float64)
+            shim.shim_run_f64(_p(w), k, _p(got), _p(gf), _p(gd))
+        assert shim.shim_next2f(float(w[3]), float(w[5])) < 0, k
+        want, st = oracle.fill(s[None, :], n, oracle.U32)
+        w = s.copy()
+        redrawn = shim.shim_run_f64_checked(_p(w), n, block, _p(got))
+        assert redrawn >= 1, k
+        assert np.array_equal(got, want[0]), k
+        assert np.array_equal(w, st[0]), k
+    for s in _states()[:20]:
+        want, _ = oracle.fill(s[None, :], n, oracle.U32)
+        w = s.copy()
+        got = np.empty(n, dtype=np.uint32)
+        shim.shim_run_f64_checked(_p(w), n, block, _p(got))
+        assert np.array_equal(got, want[0])
 
 
 def test_binary64_reduction_at_quotient_boundaries(shim):
