@@ -34,13 +34,36 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E peak
 METRIC = "uint32 Gsamples/s (% HBM write roofline), batched vs plain; p50/p99 latency"
-# HBM bytes per launch read by rocprofv3 (FETCH_SIZE + WRITE_SIZE, scaled by a
-# copy-kernel calibration); None until measured for the current kernel.
-COUNTER_TRAFFIC = 17232614912  # fill_coop_kernel<u32,256,16>: profiles/fill_coop_u32_16lanes_2p20x4096.md
-# VALU wave instructions per launch of the same kernel (SQ_INSTS_VALU, same profile);
-# None until measured for the current kernel.
-COUNTER_VALU_INSTS = 1159200768
+# rocprofv3 counters of the headline kernel, taken on the kernel sources whose
+# hash is recorded with them: HBM bytes per launch (FETCH_SIZE + WRITE_SIZE,
+# scaled by a copy-kernel calibration) and VALU wave instructions per launch
+# (SQ_INSTS_VALU).  They are reported only while the sources still hash the
+# same; after any change to the kernel they read null until profiled again.
+COUNTERS = {
+    "traffic": None,
+    "valu_insts": None,
+    "source": None,
+    "kernel_sources_sha256": None,
+}
+KERNEL_SOURCES = ["include/mrg_arith.hpp", "include/mrg32k3a_device.h",
+                  "paper_1412_8266_amd/csrc/gen_device.hpp", "paper_1412_8266_amd/csrc/kernels.hip",
+                  "paper_1412_8266_amd/csrc/kernels.h"]
 SIMDS, PEAK_SCLK_MHZ = 1024, 2400  # MI355X: 256 CUs x 4 SIMDs, 2.4 GHz peak shader clock
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for rel in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def counters_current():
+    """The recorded counters if they were taken on the current kernel sources."""
+    sha = COUNTERS["kernel_sources_sha256"]
+    return sha is not None and sha == kernel_sources_sha256()
 
 
 def parse():
@@ -59,10 +82,12 @@ def parse():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving trace")
     ap.add_argument("--batch-only", action="store_true",
                     help="only the batched request mix (prints its JSON object; for profiling)")
-    ap.add_argument("--serve-speeds", type=float, nargs="*", default=[1.1, 1.2],
-                    help="arrival-rate multiples replayed for 4 s each")
-    ap.add_argument("--serve-seconds", type=float, default=10.0,
-                    help="length of the replayed arrival trace (the full trace is 60 s)")
+    ap.add_argument("--serve-step", type=float, default=0.1,
+                    help="arrival-rate multiple step of the sustainable-rate sweep (4 s windows, "
+                         "from 1 + step up to the first rate that falls behind)")
+    ap.add_argument("--serve-max-speed", type=float, default=3.0)
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
+                    help="length of the replayed arrival trace (the whole trace is 60 s)")
     ap.add_argument("--quick", action="store_true", help="headline only (for profiling)")
     ap.add_argument("--partitions-only", action="store_true",
                     help="only the leapfrog, random-spacing and Philox lines (for profiling)")
@@ -394,19 +419,22 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": COUNTER_TRAFFIC,
+            "traffic": COUNTERS["traffic"] if counters_current() else None,
+            "traffic_source": COUNTERS["source"] if counters_current() else
+            "none: the kernel sources changed since the last counter profile",
             "kernel": ("fill_coop_kernel<u32, %d lanes per stream>" % coop_lanes_used(mg, n * 4))
                       if n >= 2048 and mg.mrg_config_get("strategy") != 1
                       else "fill_sm_kernel<u32>",
             "alg_bytes_per_launch": alg_bytes,
             "avg_launch_ms": round(ms, 4),
         },
-        "valu": None if COUNTER_VALU_INSTS is None else {
+        "valu": None if not counters_current() else {
             # issue cycles at 4 clocks per wave instruction (FP64 rate) over the
             # cycles the launch would span at the peak clock: VALU use against peak
-            "instr_per_sample": round(COUNTER_VALU_INSTS * 64 / samples, 2),
-            "issue_frac_at_peak_clock": round(COUNTER_VALU_INSTS * 4 / SIMDS
+            "instr_per_sample": round(COUNTERS["valu_insts"] * 64 / samples, 2),
+            "issue_frac_at_peak_clock": round(COUNTERS["valu_insts"] * 4 / SIMDS
                                               / (ms * 1e-3 * PEAK_SCLK_MHZ * 1e6), 4),
+            "source": COUNTERS["source"],
         },
         "wall_s_timed": round(wall, 3),
     }
@@ -470,14 +498,26 @@ def main():
         print("[bench] serving trace (%g s)" % args.serve_seconds, file=sys.stderr, flush=True)
         torch.cuda.empty_cache()
         extra["serving"] = serving(mg, wl, args.serve_seconds)
-        # the highest arrival rate served without falling behind (short windows)
-        sweep = []
-        for speed in args.serve_speeds:
+        # the highest arrival rate served without falling behind: 4-second
+        # windows at rising rates, up to the first one that falls behind
+        sweep, best = [], None
+        k = 1
+        while True:
+            speed = round(1.0 + k * args.serve_step, 6)
+            if speed > args.serve_max_speed:
+                break
             print("[bench] serving at %g x the arrival rate" % speed, file=sys.stderr, flush=True)
             r = serving(mg, wl, 4.0, speed)
-            sweep.append({k: r[k] for k in ("rate_per_s", "offered_Gsamples_s", "served_Gsamples_s",
-                                             "kept_up", "latency_ms")})
+            sweep.append({key: r[key] for key in ("rate_per_s", "offered_Gsamples_s",
+                                                  "served_Gsamples_s", "kept_up", "latency_ms")})
+            if not r["kept_up"]:
+                break
+            best = r
+            k += 1
         extra["serving_rate_sweep"] = sweep
+        extra["serving_max_sustained"] = None if best is None else {
+            "rate_per_s": best["rate_per_s"], "offered_Gsamples_s": best["offered_Gsamples_s"],
+            "first_rate_behind_per_s": sweep[-1]["rate_per_s"] if not sweep[-1]["kept_up"] else None}
     res["extra"] = extra
 
     if not args.no_cpu and not args.quick:
