@@ -27,6 +27,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "mrg32k3a_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "tinymt_oracle.c")]
 _LIB = os.path.join(_HERE, "libmrg32k3a_oracle.so")
 
 U32, F32, F64 = 0, 1, 2
@@ -41,11 +42,13 @@ _lib = None
 
 def build(force: bool = False) -> str:
     """Compile the C oracle into ``oracle/libmrg32k3a_oracle.so``."""
-    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    stale = not os.path.exists(_LIB) or any(
+        os.path.getmtime(_LIB) < os.path.getmtime(src) for src in _SRCS)
+    if force or stale:
         tmp = _LIB + ".tmp%d" % os.getpid()
         subprocess.check_call([
             "gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fno-fast-math",
-            "-fPIC", "-shared", "-o", tmp, _SRC,
+            "-fPIC", "-shared", "-o", tmp, *_SRCS,
         ])
         os.replace(tmp, _LIB)
     return _LIB
@@ -98,6 +101,38 @@ def _load():
         lib.orc_philox_fill.restype = None
         lib.orc_philox_streams.argtypes = [u64, u64, u64, P]
         lib.orc_philox_streams.restype = None
+        lib.orc_tmt_next.argtypes = [P, P]
+        lib.orc_tmt_next.restype = None
+        lib.orc_tmt_temper.argtypes = [P, P]
+        lib.orc_tmt_temper.restype = ctypes.c_uint32
+        lib.orc_tmt_draw.argtypes = [P, P]
+        lib.orc_tmt_draw.restype = ctypes.c_uint32
+        lib.orc_tmt_init.argtypes = [ctypes.c_uint32, P, P]
+        lib.orc_tmt_init.restype = None
+        lib.orc_gf2_irreducible_prime_degree.argtypes = [P]
+        lib.orc_gf2_irreducible_prime_degree.restype = ctypes.c_int
+        lib.orc_gf2_berlekamp_massey.argtypes = [P, ctypes.c_int, P]
+        lib.orc_gf2_berlekamp_massey.restype = ctypes.c_int
+        lib.orc_tmt_charpoly.argtypes = [P, P]
+        lib.orc_tmt_charpoly.restype = ctypes.c_int
+        lib.orc_tmt_params_ok.argtypes = [P]
+        lib.orc_tmt_params_ok.restype = ctypes.c_int
+        lib.orc_tmt_jump.argtypes = [P, P, P, P]
+        lib.orc_tmt_jump.restype = None
+        lib.orc_tmt_skip.argtypes = [P, P, u64]
+        lib.orc_tmt_skip.restype = None
+        lib.orc_tmt_candidate.argtypes = [u64, u64, P]
+        lib.orc_tmt_candidate.restype = None
+        lib.orc_tmt_search.argtypes = [u64, u64, P, P]
+        lib.orc_tmt_search.restype = None
+        lib.orc_tmt_streams.argtypes = [u64, u64, u64, u64, P, u64, P]
+        lib.orc_tmt_streams.restype = None
+        lib.orc_tmt_to_f32.argtypes = [ctypes.c_uint32]
+        lib.orc_tmt_to_f32.restype = ctypes.c_float
+        lib.orc_tmt_to_f64.argtypes = [ctypes.c_uint32]
+        lib.orc_tmt_to_f64.restype = ctypes.c_double
+        lib.orc_tmt_fill.argtypes = [P, u64, u64, ctypes.c_int, ctypes.c_int, P, u64, P]
+        lib.orc_tmt_fill.restype = None
         lib.orc_state_valid.argtypes = [P]
         lib.orc_state_valid.restype = ctypes.c_int
         _lib = lib
@@ -335,3 +370,126 @@ def philox_jump(states, e) -> np.ndarray:
 
 def state_valid(state) -> bool:
     return bool(_load().orc_state_valid(_ptr(_state(state))))
+
+
+# --------------------------------------------------------------------------
+# TinyMT32 (sec. 4.2): states [4] uint32 (s0..s3) for the generator
+# functions; stream-set states [S, 6] = (s0, s1, s2, s3, parameter set, 0).
+# Parameter sets are [3] uint32 (mat1, mat2, tmat).  Polynomials over GF(2)
+# are Python ints (bit i = coefficient of x^i).
+# --------------------------------------------------------------------------
+def _u32a(a, n) -> np.ndarray:
+    out = np.ascontiguousarray(np.asarray(a, dtype=np.uint32).reshape(-1))
+    assert out.size == n
+    return out
+
+
+def _poly_words(f: int) -> np.ndarray:
+    return np.array([(f >> (64 * i)) & ((1 << 64) - 1) for i in range(4)], dtype=np.uint64)
+
+
+def _words_poly(w: np.ndarray) -> int:
+    return sum(int(x) << (64 * i) for i, x in enumerate(w))
+
+
+def tmt_next(state, params) -> np.ndarray:
+    s = _u32a(state, 4).copy()
+    _load().orc_tmt_next(_ptr(s), _ptr(_u32a(params, 3)))
+    return s
+
+
+def tmt_temper(state, params) -> int:
+    return int(_load().orc_tmt_temper(_ptr(_u32a(state, 4)), _ptr(_u32a(params, 3))))
+
+
+def tmt_init(seed: int, params) -> np.ndarray:
+    s = np.zeros(4, dtype=np.uint32)
+    _load().orc_tmt_init(int(seed) & 0xFFFFFFFF, _ptr(_u32a(params, 3)), _ptr(s))
+    return s
+
+
+def tmt_outputs(state, params, n: int):
+    """(n uint32 outputs, state after them) from a [4] state."""
+    s = _u32a(state, 4).copy()
+    p = _u32a(params, 3)
+    lib = _load()
+    out = np.array([lib.orc_tmt_draw(_ptr(s), _ptr(p)) for _ in range(n)], dtype=np.uint32)
+    return out, s
+
+
+def gf2_irreducible_prime_degree(f: int) -> bool:
+    return bool(_load().orc_gf2_irreducible_prime_degree(_ptr(_poly_words(f))))
+
+
+def gf2_berlekamp_massey(bits):
+    """(L, C) for a sequence of 0/1 values (at most 255 of them); C as an int."""
+    a = np.ascontiguousarray(np.asarray(bits, dtype=np.uint8))
+    w = np.zeros(4, dtype=np.uint64)
+    L = _load().orc_gf2_berlekamp_massey(_ptr(a), int(a.size), _ptr(w))
+    return int(L), _words_poly(w)
+
+
+def tmt_charpoly(params):
+    """(degree, phi) of the parameter set's transition."""
+    w = np.zeros(4, dtype=np.uint64)
+    L = _load().orc_tmt_charpoly(_ptr(_u32a(params, 3)), _ptr(w))
+    return int(L), _words_poly(w)
+
+
+def tmt_params_ok(params) -> bool:
+    return bool(_load().orc_tmt_params_ok(_ptr(_u32a(params, 3))))
+
+
+def tmt_jump(state, params, e: int) -> np.ndarray:
+    """T^e state for 0 <= e < 2^128."""
+    assert 0 <= e < 1 << 128
+    s = _u32a(state, 4).copy()
+    p = _u32a(params, 3)
+    _, phi = tmt_charpoly(p)
+    ew = np.array([e & ((1 << 64) - 1), e >> 64], dtype=np.uint64)
+    _load().orc_tmt_jump(_ptr(s), _ptr(p), _ptr(_poly_words(phi)), _ptr(ew))
+    return s
+
+
+def tmt_skip(state, params, k: int) -> np.ndarray:
+    s = _u32a(state, 4).copy()
+    _load().orc_tmt_skip(_ptr(s), _ptr(_u32a(params, 3)), int(k))
+    return s
+
+
+def tmt_candidate(master: int, c: int) -> np.ndarray:
+    p = np.zeros(3, dtype=np.uint32)
+    _load().orc_tmt_candidate(int(master), int(c), _ptr(p))
+    return p
+
+
+def tmt_search(master: int, count: int):
+    """([count, 3] parameter sets, [count] candidate numbers) of master's search."""
+    out = np.zeros((max(count, 1), 3), dtype=np.uint32)
+    cand = np.zeros(max(count, 1), dtype=np.uint64)
+    if count:
+        _load().orc_tmt_search(int(master), int(count), _ptr(out), _ptr(cand))
+    return out[:count], cand[:count]
+
+
+def tmt_streams(master: int, per_param: int, first: int, count: int, params, q0: int = 0):
+    """[count, 6] start states of streams first .. first+count-1 of a TinyMT
+    stream set (params: sets q0, q0 + 1, ... of master's search)."""
+    pr = np.ascontiguousarray(np.asarray(params, dtype=np.uint32).reshape(-1))
+    out = np.zeros((max(count, 1), 6), dtype=np.uint32)
+    if count:
+        _load().orc_tmt_streams(int(master), int(per_param), int(first), int(count), _ptr(pr),
+                                int(q0), _ptr(out))
+    return out[:count]
+
+
+def tmt_fill(states, n: int, dtype: int, layout: int, params, q0: int = 0):
+    """(out, advanced states) as ``fill`` for TinyMT stream-set states."""
+    st = np.ascontiguousarray(np.array(states, dtype=np.uint32, copy=True).reshape(-1, 6))
+    S = st.shape[0]
+    pr = np.ascontiguousarray(np.asarray(params, dtype=np.uint32).reshape(-1))
+    shape = (S, n) if layout == STREAM_MAJOR else (n, S)
+    out = np.empty(shape, dtype=_DTYPES[dtype])
+    _load().orc_tmt_fill(_ptr(st), S, n, dtype, layout, _ptr(pr), int(q0),
+                         _ptr(out) if out.size else None)
+    return out, st

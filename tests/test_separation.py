@@ -47,8 +47,9 @@ def test_native_sources_name_no_oracle_file():
         assert "mrg32k3a_oracle" not in text and "orc_" not in text, f
 
 
-def test_oracle_c_includes_only_the_c_library():
-    src = open(os.path.join(ROOT, "oracle", "mrg32k3a_oracle.c")).read()
+@pytest.mark.parametrize("name", ["mrg32k3a_oracle.c", "tinymt_oracle.c"])
+def test_oracle_c_includes_only_the_c_library(name):
+    src = open(os.path.join(ROOT, "oracle", name)).read()
     heads = re.findall(r"#include\s*[<\"]([^>\"]+)[>\"]", src)
     assert heads and all(h in ("stdint.h", "stddef.h", "string.h", "stdlib.h", "stdio.h")
                          for h in heads), heads
