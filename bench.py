@@ -276,10 +276,11 @@ def serving(mg, wl, seconds, speed=1.0):
 
 
 def partitions(mg, wl, torch, stream):
-    """The other partitions of sec. 2.3 and the second generator over 2^32
+    """The other partitions of sec. 2.3 and the other generators over 2^32
     uint32 (16 GiB): one stream dealt to 2^16 players x 2^16 cards (in order,
-    and each player's cards in a row), random-spacing set creation, and a
-    Philox4x32-10 set of 2^20 streams x 4096."""
+    and each player's cards in a row), random-spacing set creation, a
+    Philox4x32-10 set of 2^20 streams x 4096, and a TinyMT32 hybrid set of
+    2^20 streams x 4096 (256 streams per parameter set)."""
     extra = {}
     S, n = wl.C2_STREAMS, wl.C2_N
     samples = S * n
@@ -308,6 +309,20 @@ def partitions(mg, wl, torch, stream):
         extra[name] = {"ms": round(msp, 4), "Gsamples_s": round(samples / msp / 1e6, 2),
                        "hbm_frac": round(samples * 4 / msp / 1e6 / HBM_PEAK_GBS, 4)}
     ssp.close()
+    # TinyMT32 hybrid (sec. 4.2): 256 consecutive streams share a parameter
+    # set (4096 sets from the device search), sub-streams 2^64 apart
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sst = mg.StreamSet(S, master_seed=wl.MASTER_SEED, generator="tinymt", per_param=256)
+    torch.cuda.synchronize()
+    extra["tinymt_create_2^20_streams_4096_sets_ms"] = round((time.perf_counter() - t0) * 1e3, 2)
+    for name, lay in (("tinymt_fill_2^20x4096", mg.STREAM_MAJOR),
+                      ("tinymt_interleaved_2^20x4096", mg.INTERLEAVED)):
+        per_t, _ = timed(lambda: sst.fill(n, mg.U32, lay, out=outp), 10, 2, stream)
+        mst = sum(per_t) / len(per_t)
+        extra[name] = {"ms": round(mst, 4), "Gsamples_s": round(samples / mst / 1e6, 2),
+                       "hbm_frac": round(samples * 4 / mst / 1e6 / HBM_PEAK_GBS, 4)}
+    sst.close()
     del outl, outp
     torch.cuda.synchronize()
     return extra

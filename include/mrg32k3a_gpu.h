@@ -121,6 +121,81 @@ mrg_status mrg_streamset_create_random(mrg_streamset *out, uint64_t n_streams,
 mrg_status mrg_streamset_create_philox(mrg_streamset *out, uint64_t n_streams,
                                        uint64_t first_stream, uint64_t key, void *stream);
 
+/* ---------------------------------------------------------------------- */
+/* TinyMT32 stream sets (sec. 4.2: the hybrid of parameterisation and      */
+/* sequence splitting)                                                     */
+/* ---------------------------------------------------------------------- */
+/* TinyMT32 (Saito & Matsumoto, 2011) has a 127-bit state and period
+ * 2^127 - 1 for a good parameter set (mat1, mat2, tmat).  In the paper's
+ * hybrid the threads of a group share one parameter set and each takes its
+ * own sub-stream of that generator by sequence splitting.  Here global
+ * stream g uses parameter set q = g / per_param and starts
+ * (g % per_param) * 2^64 outputs past the set's base status, the published
+ * seeding from the 32-bit seed (uint32)SplitMix64_q(master_seed) (output q,
+ * as mrg_streamset_create_random numbers them).  A stream's six state words
+ * are (s0, s1, s2, s3, q, 0).
+ *
+ * Parameter sets replace Dynamic Creator's files: candidate c of the search
+ * under master_seed takes SplitMix64 outputs 2c and 2c+1 of master_seed + 1
+ * (mat1 | mat2 << 32 = the first, tmat = the low half of the second), and a
+ * candidate is accepted when the characteristic polynomial of its
+ * transition (Berlekamp-Massey on 254 output bits) has degree 127 and is
+ * irreducible (Rabin's test), which for the Mersenne exponent 127 gives the
+ * full period.  Parameter set q is the q-th accepted candidate.
+ *
+ * uint32 outputs are the tempered words (all of [0, 2^32)); FP32
+ * (2*(w >> 9) + 1) * 2^-24 and FP64 (2*w + 1) * 2^-33, exact, in (0, 1).
+ * mrg_fill (both layouts), mrg_jump / mrg_jump_uniform (polynomial jumps,
+ * any exponent below 2^192), mrg_get_states / mrg_set_states work on such a
+ * set; substream jumps, leapfrog and batches return MRG_EINVAL.
+ * Parity unpinned: no known-answer output of TinyMT32 was available, so the
+ * transition, tempering and seeding rest on their written definition (the
+ * oracle and the library agree bit for bit). */
+
+/* Test candidates c0 .. c0+n-1 of the search under master_seed on the
+ * device: d_flags[i] (device, n uint32) = L | accepted << 16, L the linear
+ * complexity found by Berlekamp-Massey; d_phi (device, 4n uint32, may be
+ * NULL) receives each characteristic polynomial (bit b of word k the
+ * coefficient of x^(32k+b); written when L = 127, zero otherwise).
+ * Asynchronous on `stream`.  n <= 2^31.  Errors: MRG_EINVAL (null flags,
+ * pointers not device memory), MRG_ERANGE, MRG_EHIP. */
+mrg_status mrg_tinymt_test_candidates(uint64_t master_seed, uint64_t c0, uint64_t n,
+                                      uint32_t *d_flags, uint32_t *d_phi, void *stream);
+
+/* Parameter sets 0 .. count-1 of the search under master_seed: h_params
+ * (host, 3*count words: mat1, mat2, tmat) and, if not NULL, h_cand (host,
+ * count words) their candidate numbers.  Candidates are tested on the
+ * device in batches; synchronous on `stream`.  count <= 2^20.  Errors:
+ * MRG_EINVAL, MRG_ERANGE, MRG_ENOMEM, MRG_EHIP. */
+mrg_status mrg_tinymt_search(uint64_t master_seed, uint64_t count, uint32_t *h_params,
+                             uint64_t *h_cand, void *stream);
+
+/* Create a TinyMT32 stream set of n_streams streams from global index
+ * first_stream, per_param consecutive global streams per parameter set (a
+ * workgroup's threads, in the paper's hybrid).  The sets used, q0 =
+ * first_stream / per_param .. qlast = (first_stream + n_streams - 1) /
+ * per_param (at most 2^20 of them, qlast < 2^32), come from h_params (host,
+ * 3 words per set, holding sets params_first .. params_first + n_params - 1,
+ * which must cover q0 .. qlast, else MRG_ERANGE) or, when h_params is NULL,
+ * from mrg_tinymt_search(master_seed, qlast + 1).  Every set is checked on
+ * the device (MRG_EINVAL names a set without a degree-127 irreducible
+ * characteristic polynomial) and gets a record (parameters, polynomial,
+ * x^(2^i) mod phi for i < 192).  Synchronous on `stream`.  Sizes as
+ * mrg_streamset_create; per_param >= 1.  Errors: MRG_EINVAL, MRG_ERANGE,
+ * MRG_ENOMEM, MRG_EHIP. */
+mrg_status mrg_streamset_create_tinymt(mrg_streamset *out, uint64_t n_streams,
+                                       uint64_t first_stream, uint64_t per_param,
+                                       uint64_t master_seed, const uint32_t *h_params,
+                                       uint64_t params_first, uint64_t n_params, void *stream);
+
+/* Description of a TinyMT32 set for user kernels (tinymt_device.h): streams
+ * per parameter set, global index q0 of the first set held, number of sets,
+ * and the device address of their records (n_sets * 776 uint32, owned by
+ * the set, valid until destroy).  Any output may be NULL.  MRG_EINVAL for a
+ * set of another generator. */
+mrg_status mrg_streamset_tinymt_info(mrg_streamset ss, uint64_t *per_param, uint64_t *q0,
+                                     uint64_t *n_sets, const void **d_records);
+
 /* Release the stream set and its device memory (sec. 5.1 release()).
  * Synchronises the device work the library enqueued on the set first.
  * NULL is accepted and ignored. */

@@ -71,24 +71,33 @@ class StreamSet:
     own random state, expanded from SplitMix64 output g of the master seed
     (random spacing, sec. 2.3).  With ``generator="philox"`` the streams are
     Philox4x32-10 streams under the key ``master_seed`` (stream g: counter
-    words 2-3 = g).
+    words 2-3 = g).  With ``generator="tinymt"`` they are TinyMT32 streams in
+    the hybrid of sec. 4.2: ``per_param`` consecutive streams share a
+    parameter set (``params``: a [k, 3] array of sets ``params_first`` ..,
+    else the library's search under ``master_seed``) and stream g starts
+    (g % per_param) * 2^64 outputs past its set's base status.
     """
 
     def __init__(self, n_streams: int, seed=None, master_seed: Optional[int] = None,
                  first_stream: int = 0, stream=None, spacing: str = "jump",
-                 generator: str = "mrg32k3a"):
+                 generator: str = "mrg32k3a", per_param: int = 256, params=None,
+                 params_first: int = 0):
         if (seed is None) == (master_seed is None):
             raise ValueError("give exactly one of seed (6 words) or master_seed")
         if spacing not in ("jump", "random"):
             raise ValueError("spacing must be 'jump' or 'random'")
-        if generator not in ("mrg32k3a", "philox"):
-            raise ValueError("generator must be 'mrg32k3a' or 'philox'")
-        if (spacing == "random" or generator == "philox") and master_seed is None:
-            raise ValueError("random spacing and Philox take a master_seed")
-        if generator == "philox" and spacing != "jump":
-            raise ValueError("Philox streams are spaced by their counters")
+        if generator not in ("mrg32k3a", "philox", "tinymt"):
+            raise ValueError("generator must be 'mrg32k3a', 'philox' or 'tinymt'")
+        if (spacing == "random" or generator != "mrg32k3a") and master_seed is None:
+            raise ValueError("random spacing, Philox and TinyMT take a master_seed")
+        if generator != "mrg32k3a" and spacing != "jump":
+            raise ValueError("Philox and TinyMT streams are placed by their own scheme")
         h = _stream_handle(stream)
-        if generator == "philox":
+        self.generator = generator
+        if generator == "tinymt":
+            self._h = _abi.mrg_streamset_create_tinymt(n_streams, first_stream, per_param,
+                                                       master_seed, params, params_first, h)
+        elif generator == "philox":
             self._h = _abi.mrg_streamset_create_philox(n_streams, first_stream, master_seed, h)
         elif seed is not None:
             self._h = _abi.mrg_streamset_create(n_streams, first_stream, seed, h)
@@ -131,6 +140,12 @@ class StreamSet:
         """Device address of the six state planes ([6][n] uint32), for user
         kernels built on mrg::Stream (include/mrg32k3a_device.h)."""
         return _abi.mrg_streamset_states_ptr(self._h)
+
+    @property
+    def tinymt_info(self):
+        """(per_param, q0, n_sets, records address) of a TinyMT set, for user
+        kernels built on mrg::TinyMTStream (include/tinymt_device.h)."""
+        return _abi.mrg_streamset_tinymt_info(self._h)
 
     @property
     def tables_ptr(self) -> int:
@@ -212,7 +227,29 @@ __all__ = [
     "StreamSet", "MRGError", "U32", "F32", "F64", "STREAM_MAJOR", "INTERLEAVED", "M1", "M2",
     "mrg_seed_from_master", "mrg_jump_matrix", "mrg_state_check", "mrg_config_set",
     "mrg_config_get", "mrg_version", "torch_dtype", "write_probe", "check_tensor",
+    "tinymt_search", "tinymt_test_candidates",
 ]
+
+
+def tinymt_search(master_seed: int, count: int, stream=None):
+    """Parameter sets 0 .. count-1 of the TinyMT32 search under master_seed:
+    ([count, 3] uint32 array, [count] candidate numbers)."""
+    p, c = _abi.mrg_tinymt_search(master_seed, count, _stream_handle(stream))
+    return (np.array(p, dtype=np.uint32).reshape(-1, 3), np.array(c, dtype=np.uint64))
+
+
+def tinymt_test_candidates(master_seed: int, c0: int, n: int, with_phi: bool = False,
+                           stream=None):
+    """Device test of candidates c0 .. c0+n-1: (flags tensor [n] int32 holding
+    L | accepted << 16, characteristic polynomials [n, 4] or None)."""
+    torch = _torch()
+    dev = "cuda:%d" % torch.cuda.current_device()
+    flags = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    phi = torch.empty((max(n, 1), 4), dtype=torch.int32, device=dev) if with_phi else None
+    _abi.mrg_tinymt_test_candidates(master_seed, c0, n, flags.data_ptr(),
+                                    phi.data_ptr() if phi is not None else 0,
+                                    _stream_handle(stream))
+    return flags[:n], (phi[:n] if phi is not None else None)
 
 
 def write_probe(out, pattern: int = 0, stream=None) -> None:

@@ -54,6 +54,11 @@ _SIGS = {
     "mrg_streamset_create_seed64": [ctypes.POINTER(_P), _U64, _U64, _U64, _P],
     "mrg_streamset_create_random": [ctypes.POINTER(_P), _U64, _U64, _U64, _P],
     "mrg_streamset_create_philox": [ctypes.POINTER(_P), _U64, _U64, _U64, _P],
+    "mrg_streamset_create_tinymt": [ctypes.POINTER(_P), _U64, _U64, _U64, _U64, _PU32, _U64, _U64,
+                                    _P],
+    "mrg_streamset_tinymt_info": [_P, _PU64, _PU64, _PU64, ctypes.POINTER(_P)],
+    "mrg_tinymt_test_candidates": [_U64, _U64, _U64, _P, _P, _P],
+    "mrg_tinymt_search": [_U64, _U64, _PU32, _PU64, _P],
     "mrg_streamset_destroy": [_P],
     "mrg_streamset_info": [_P, _PU64, _PU64, _PU32],
     "mrg_streamset_states_ptr": [_P, ctypes.POINTER(_P)],
@@ -211,6 +216,46 @@ def mrg_streamset_create_philox(n_streams: int, first_stream: int, key: int,
     _call("mrg_streamset_create_philox", ctypes.byref(h), n_streams, first_stream,
           key & ((1 << 64) - 1), stream)
     return h.value
+
+
+def mrg_streamset_create_tinymt(n_streams: int, first_stream: int, per_param: int,
+                                master_seed: int, params=None, params_first: int = 0,
+                                stream: int = 0) -> int:
+    """params: None (the library searches the sets) or a [k, 3] array of
+    parameter sets params_first .. params_first + k - 1."""
+    h = _P()
+    if params is None:
+        arr, k = None, 0
+    else:
+        flat = [int(w) for row in params for w in row]
+        k = len(flat) // 3
+        arr = _u32(flat, len(flat))
+    _call("mrg_streamset_create_tinymt", ctypes.byref(h), n_streams, first_stream, per_param,
+          master_seed & ((1 << 64) - 1), arr, params_first, k, stream)
+    return h.value
+
+
+def mrg_streamset_tinymt_info(ss: int):
+    """(per_param, q0, n_sets, device address of the parameter records)."""
+    per, q0, n = _U64(), _U64(), _U64()
+    rec = _P()
+    _call("mrg_streamset_tinymt_info", ss, ctypes.byref(per), ctypes.byref(q0), ctypes.byref(n),
+          ctypes.byref(rec))
+    return per.value, q0.value, n.value, int(rec.value or 0)
+
+
+def mrg_tinymt_test_candidates(master_seed: int, c0: int, n: int, d_flags: int, d_phi: int = 0,
+                               stream: int = 0) -> None:
+    _call("mrg_tinymt_test_candidates", master_seed & ((1 << 64) - 1), c0, n, d_flags,
+          d_phi or None, stream)
+
+
+def mrg_tinymt_search(master_seed: int, count: int, stream: int = 0):
+    """([count][3] parameter sets, [count] candidate numbers) as lists."""
+    params = (ctypes.c_uint32 * max(3 * count, 1))()
+    cand = (ctypes.c_uint64 * max(count, 1))()
+    _call("mrg_tinymt_search", master_seed & ((1 << 64) - 1), count, params, cand, stream)
+    return ([list(params[3 * i:3 * i + 3]) for i in range(count)], list(cand[:count]))
 
 
 def mrg_streamset_destroy(ss: int) -> None:

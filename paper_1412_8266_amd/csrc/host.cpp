@@ -215,6 +215,8 @@ namespace mrg {
 
 FillTuning current_tuning() { return tuning(); }
 
+mrg_status current_device_id(int *dev) { return current_device(dev); }
+
 mrg_status device_tables(int dev, DeviceTables *out)
 {
     DevCtx *ctx;
@@ -445,6 +447,10 @@ mrg_status mrg_streamset_destroy(mrg_streamset ss)
         if (e != hipSuccess) st = hip_error(e, "hipDeviceSynchronize before free");
         e = hipFree(ss->d_planes);
         if (e != hipSuccess && st == MRG_OK) st = hip_error(e, "hipFree(states)");
+        if (ss->d_records) {
+            e = hipFree(ss->d_records);
+            if (e != hipSuccess && st == MRG_OK) st = hip_error(e, "hipFree(parameter records)");
+        }
         if (prev != ss->device && prev >= 0) (void)hipSetDevice(prev);
     }
     delete ss;
@@ -488,9 +494,15 @@ mrg_status mrg_jump(mrg_streamset ss, uint64_t first, uint64_t count, const uint
     if (count == 0) return MRG_OK;
     if (!d_exp) return set_error(MRG_EINVAL, "null exponent array");
     if ((st = mrg::check_device_span(d_exp, 24 * count, ss->device, "exponent array"))) return st;
-    if (ss->gen == 1) {  // the position moves by e mod 2^64
+    if (ss->gen == mrg::kGenPhilox) {  // the position moves by e mod 2^64
         hipError_t e = mrg::launch_philox_jump(ss->d_planes, ss->n, first, count, d_exp, 0,
                                                (hipStream_t)stream);
+        return e == hipSuccess ? MRG_OK : hip_error(e, "jump kernel launch");
+    }
+    if (ss->gen == mrg::kGenTinyMT) {
+        const uint64_t none[3] = {0, 0, 0};
+        hipError_t e = mrg::launch_tmt_jump(ss->d_planes, ss->n, first, count, d_exp, none,
+                                            ss->d_records, ss->q0, (hipStream_t)stream);
         return e == hipSuccess ? MRG_OK : hip_error(e, "jump kernel launch");
     }
     DevCtx *ctx;
@@ -508,9 +520,14 @@ mrg_status mrg_jump_uniform(mrg_streamset ss, uint64_t first, uint64_t count,
     if ((st = check_range(ss, first, count))) return st;
     if (!h_exp) return set_error(MRG_EINVAL, "null exponent");
     if (count == 0) return MRG_OK;
-    if (ss->gen == 1) {
+    if (ss->gen == mrg::kGenPhilox) {
         hipError_t e = mrg::launch_philox_jump(ss->d_planes, ss->n, first, count, nullptr,
                                                h_exp[0], (hipStream_t)stream);
+        return e == hipSuccess ? MRG_OK : hip_error(e, "jump kernel launch");
+    }
+    if (ss->gen == mrg::kGenTinyMT) {
+        hipError_t e = mrg::launch_tmt_jump(ss->d_planes, ss->n, first, count, nullptr, h_exp,
+                                            ss->d_records, ss->q0, (hipStream_t)stream);
         return e == hipSuccess ? MRG_OK : hip_error(e, "jump kernel launch");
     }
     hipError_t e = mrg::launch_jump_uniform(ss->d_planes, ss->n, first, count,
@@ -521,7 +538,7 @@ mrg_status mrg_jump_uniform(mrg_streamset ss, uint64_t first, uint64_t count,
 mrg_status mrg_jump_substreams(mrg_streamset ss, uint64_t first, uint64_t count, uint64_t k,
                                void *stream)
 {
-    if (ss && ss->gen == 1)
+    if (ss && ss->gen != mrg::kGenMRG)
         return set_error(MRG_EINVAL, "substreams are defined for MRG32k3a stream sets only");
     // k * 2^76 = (k << 12) * 2^64 + (k >> 52) * 2^128
     const uint64_t e[3] = {0, k << 12, k >> 52};
@@ -546,7 +563,7 @@ mrg_status mrg_fill(mrg_streamset ss, uint64_t first, uint64_t count, uint64_t n
         return set_error(MRG_ERANGE, "output size overflows 64 bits");
     if ((st = mrg::check_device_span(d_out, count * n_per_stream * es, ss->device, "output")))
         return st;
-    if (ss->gen == 1) {
+    if (ss->gen == mrg::kGenPhilox) {
         hipError_t e = mrg::launch_philox_fill(ss->d_planes, ss->n, first, count, n_per_stream,
                                                (int)dtype, (int)layout, d_out, (hipStream_t)stream);
         if (e == hipSuccess)
@@ -555,6 +572,12 @@ mrg_status mrg_fill(mrg_streamset ss, uint64_t first, uint64_t count, uint64_t n
         return e == hipSuccess ? MRG_OK : hip_error(e, "philox fill kernel launch");
     }
     const mrg::FillTuning tune = tuning();
+    if (ss->gen == mrg::kGenTinyMT) {
+        hipError_t e = mrg::launch_tmt_fill(ss->d_planes, ss->n, first, count, n_per_stream,
+                                            (int)dtype, (int)layout, d_out, ss->d_records, ss->q0,
+                                            tune.tile_bytes, (hipStream_t)stream);
+        return e == hipSuccess ? MRG_OK : hip_error(e, "tinymt fill kernel launch");
+    }
     mrg::FillLaunch fl;
     if (layout == MRG_STREAM_MAJOR) {
         // wave per stream when a stream fills at least one chunk of 64 lanes x
@@ -612,7 +635,7 @@ mrg_status mrg_fill_leapfrog(mrg_streamset ss, uint64_t s, uint64_t players,
         return set_error(MRG_EINVAL, "unknown dtype %d", (int)dtype);
     if (layout != MRG_STREAM_MAJOR && layout != MRG_INTERLEAVED)
         return set_error(MRG_EINVAL, "unknown layout %d", (int)layout);
-    if (ss->gen == 1)
+    if (ss->gen != mrg::kGenMRG)
         return set_error(MRG_EINVAL, "leapfrog is defined for MRG32k3a stream sets only");
     if (players == 0 || per_player == 0) return MRG_OK;
     if (!d_out) return set_error(MRG_EINVAL, "null output");
@@ -717,10 +740,20 @@ mrg_status mrg_set_states(mrg_streamset ss, uint64_t first, uint64_t count, cons
     if ((st = check_range(ss, first, count))) return st;
     if (count == 0) return MRG_OK;
     if (!h_in) return set_error(MRG_EINVAL, "null input");
-    for (uint64_t i = 0; ss->gen == 0 && i < count; ++i)  // any 6 words are a Philox state
+    for (uint64_t i = 0; ss->gen == mrg::kGenMRG && i < count; ++i)  // any 6 words are a Philox state
         if (!state_ok(h_in + 6 * i))
             return set_error(MRG_EINVAL, "state %llu is not a valid MRG32k3a state",
                         (unsigned long long)i);
+    for (uint64_t i = 0; ss->gen == mrg::kGenTinyMT && i < count; ++i) {
+        // a TinyMT state: nonzero 127-bit part, a parameter set of this set
+        // (the one its stream was created with), word 5 zero
+        const uint32_t *w = h_in + 6 * i;
+        const uint64_t q_want = (ss->first + first + i) / ss->per_param;
+        if (((w[0] & 0x7fffffffu) | w[1] | w[2] | w[3]) == 0u || w[4] != q_want || w[5] != 0u)
+            return set_error(MRG_EINVAL, "state %llu is not a TinyMT32 state of its stream "
+                             "(nonzero state, parameter set %llu, last word 0)",
+                             (unsigned long long)i, (unsigned long long)q_want);
+    }
     std::vector<uint32_t> tmp(6 * count);
     for (uint64_t i = 0; i < count; ++i)
         for (int c = 0; c < 6; ++c) tmp[c * count + i] = h_in[6 * i + c];

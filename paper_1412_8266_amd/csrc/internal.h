@@ -11,9 +11,17 @@ struct mrg_streamset_s {
     uint64_t n = 0;                // streams in the set
     uint64_t first = 0;            // global index of stream 0 of the set
     uint32_t seed[6] = {};         // base state (global stream 0)
-    int gen = 0;                   // 0 MRG32k3a, 1 Philox4x32-10 (mrg_streamset_create_philox)
+    int gen = 0;                   // 0 MRG32k3a, 1 Philox4x32-10, 2 TinyMT32
     uint32_t *d_planes = nullptr;  // [6][n]
+    // TinyMT32 sets: records of parameter sets q0 .. q0 + n_sets - 1, each
+    // shared by per_param consecutive global streams
+    uint32_t *d_records = nullptr;
+    uint64_t per_param = 0, q0 = 0, n_sets = 0;
 };
+
+namespace mrg {
+constexpr int kGenMRG = 0, kGenPhilox = 1, kGenTinyMT = 2;
+}
 
 namespace mrg {
 
@@ -30,6 +38,9 @@ struct DeviceTables {
 mrg_status device_tables(int dev, DeviceTables *out);
 
 FillTuning current_tuning();
+
+// The calling thread's current HIP device (MRG_ENODEV when there is none).
+mrg_status current_device_id(int *dev);
 
 // Stream set usable on the current device; range inside the set.
 mrg_status check_streamset(mrg_streamset ss);

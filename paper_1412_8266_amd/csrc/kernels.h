@@ -100,6 +100,25 @@ hipError_t launch_philox_fill(const uint32_t *planes, uint64_t plane_stride, uin
                               uint64_t count, uint64_t n, int dtype, int layout, void *out,
                               hipStream_t st);
 
+// TinyMT32 stream sets (tinymt.hip): states (s0, s1, s2, s3, q, 0), one
+// record of tmt::kRecordWords words per parameter set (sets q0, q0 + 1, ...).
+// Candidates: flags[i] = L | accepted << 16 for candidate c0 + i, phis
+// (optional) its characteristic polynomial.  Records: ok[i] = 1 when set i
+// is accepted.
+hipError_t launch_tmt_candidates(uint64_t master, uint64_t c0, uint64_t n, uint32_t *flags,
+                                 uint32_t *phis, hipStream_t st);
+hipError_t launch_tmt_records(const uint32_t *params, uint64_t n, uint32_t *records, uint32_t *ok,
+                              hipStream_t st);
+hipError_t launch_tmt_init(uint32_t *planes, uint64_t plane_stride, uint64_t count, uint64_t g0,
+                           uint64_t per_param, uint64_t q0, uint64_t master,
+                           const uint32_t *records, hipStream_t st);
+hipError_t launch_tmt_jump(uint32_t *planes, uint64_t plane_stride, uint64_t first, uint64_t count,
+                           const uint64_t *d_exp, const uint64_t e[3], const uint32_t *records,
+                           uint64_t q0, hipStream_t st);
+hipError_t launch_tmt_fill(uint32_t *planes, uint64_t plane_stride, uint64_t first, uint64_t count,
+                           uint64_t n, int dtype, int layout, void *out, const uint32_t *records,
+                           uint64_t q0, int tile_bytes, hipStream_t st);
+
 // Store-only bandwidth probes (probe.hip): pattern 0 streaming, 1 the
 // wave-per-stream fill's line geometry.
 hipError_t launch_write_probe(void *out, uint64_t bytes, int pattern, hipStream_t st);
