@@ -392,6 +392,31 @@ mrg_status mrg_batch_autotune(mrg_batch b, const mrg_batch_config *cands, uint32
 /* Release the plan (synchronises the device first).  NULL is ignored. */
 mrg_status mrg_batch_destroy(mrg_batch b);
 
+/* Bytes of the fixed device array behind mrg_batch_run_noalloc (per device,
+ * held until the process ends). */
+#define MRG_NOALLOC_SCRATCH_BYTES (16u << 20)
+
+/* For callers that cannot allocate device memory (serving loops and
+ * harnesses that forbid hipMalloc, code that must not grow the device heap):
+ * plan and run one batch -- the same validation, work items, kernels and
+ * results as mrg_batch_create(ss, reqs, n_reqs, cfg) followed by
+ * mrg_batch_run and mrg_batch_destroy -- without any device or pinned
+ * allocation.  The request descriptors, item prefixes, claim counters and the
+ * staged end states of multi-segment streams go into one fixed device array
+ * of MRG_NOALLOC_SCRATCH_BYTES bytes; a batch needing more (about 80 bytes per
+ * request plus 24 bytes per stream of more than one segment) returns
+ * MRG_ERANGE before anything is enqueued, naming the size it needs.  The
+ * caller passes the stream set, the requests (host memory, read during the
+ * call) and the outputs, as for mrg_batch_create.  Host planning uses ordinary
+ * heap memory.  The call waits for earlier work on `stream`, uploads the plan
+ * (waiting for that copy), then enqueues the kernels and returns; no
+ * completion stamps are kept.  Every call on one device shares the array, and
+ * each call overwrites what the last one left there: calls that may overlap
+ * on one device (other host threads, other streams) race and must be ordered
+ * by the caller. */
+mrg_status mrg_batch_run_noalloc(mrg_streamset ss, const mrg_request *reqs, uint64_t n_reqs,
+                                 const mrg_batch_config *cfg, void *stream);
+
 /* ---------------------------------------------------------------------- */
 /* Serving: continuous batching of client requests                         */
 /* ---------------------------------------------------------------------- */

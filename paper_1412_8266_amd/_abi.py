@@ -109,6 +109,8 @@ _SIGS.update({
     "mrg_batch_autotune": [_P, ctypes.POINTER(mrg_batch_config), ctypes.c_uint32, ctypes.c_uint32,
                            _P, ctypes.POINTER(ctypes.c_uint32), ctypes.POINTER(ctypes.c_float)],
     "mrg_batch_destroy": [_P],
+    "mrg_batch_run_noalloc": [_P, ctypes.POINTER(mrg_request), _U64,
+                              ctypes.POINTER(mrg_batch_config), _P],
 })
 
 class mrg_server_config(ctypes.Structure):
@@ -420,6 +422,11 @@ def mrg_batch_autotune(b: int, configs, reps: int = 1, stream: int = 0):
 
 def mrg_batch_destroy(b: int) -> None:
     _call("mrg_batch_destroy", b)
+
+
+def mrg_batch_run_noalloc(ss: int, reqs, n_reqs: int, cfg=None, stream: int = 0) -> None:
+    _call("mrg_batch_run_noalloc", ss, reqs, n_reqs,
+          ctypes.byref(cfg) if cfg is not None else None, stream)
 
 
 def mrg_server_create(n_clients, first_stream, master_seed, arena_bytes, max_inflight=0,

@@ -15,8 +15,8 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libmrg32k3a_gpu.so")
 
-SOURCES = ["kernels.hip", "batch.hip", "probe.hip", "philox.hip", "tinymt.hip", "host.cpp",
-           "batch_host.cpp", "serve.cpp", "tinymt_host.cpp"]
+SOURCES = ["kernels.hip", "batch.hip", "batch_noalloc.hip", "probe.hip", "philox.hip", "tinymt.hip",
+           "host.cpp", "batch_host.cpp", "serve.cpp", "tinymt_host.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "kernels.h"
+#include "mrg32k3a_gpu.h"
 
 namespace mrg {
 
@@ -88,6 +89,26 @@ struct Grouped {
 };
 
 void group_requests(const std::vector<BatchReq> &in, Grouped *out);
+
+// A batch cut into work items on the host, before any upload: the grouped
+// descriptors, which input request each non-empty one came from, and the
+// copy-back table of multi-segment streams (entry e covers copy-back slots
+// [cb_prefix[e], cb_prefix[e+1]): streams cb_stream0[e] + j, staged in scratch
+// slots cb_scratch0[e] + j).
+struct HostPlan {
+    std::vector<BatchReq> in;       // non-empty requests in input order
+    Grouped plan;
+    std::vector<uint32_t> req_of;   // non-empty request -> input index
+    std::vector<uint64_t> cb_prefix, cb_stream0, cb_scratch0;
+    uint64_t scratch_slots = 0, samples = 0, bytes = 0;
+};
+// Work items of each request under cfg (an effective configuration).
+void plan_batch(const mrg_request *reqs, uint64_t n, const mrg_batch_config &cfg, HostPlan *out);
+// cfg with defaults filled in (cfg may be NULL).
+mrg_batch_config batch_config(const mrg_batch_config *cfg);
+// The checks of mrg_batch_create: dtypes, flags, outputs (device memory of
+// the set's device, inside one allocation), stream ranges, overlaps.
+mrg_status validate_batch(mrg_streamset ss, const mrg_request *reqs, uint64_t n);
 
 // Launch every group (counter reset + persistent kernel) on one stream.
 // base carries the state planes, tables, scratch and schedule; counters holds

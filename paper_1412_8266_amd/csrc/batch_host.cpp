@@ -64,6 +64,56 @@ void group_requests(const std::vector<BatchReq> &in, Grouped *out)
     out->groups.swap(sorted);
 }
 
+void plan_batch(const mrg_request *reqs, uint64_t n, const mrg_batch_config &cfg, HostPlan *out)
+{
+    HostPlan &P = *out;
+    P.in.clear();
+    P.req_of.clear();
+    P.cb_prefix.assign(1, 0);
+    P.cb_stream0.clear();
+    P.cb_scratch0.clear();
+    P.scratch_slots = P.samples = P.bytes = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+        const mrg_request &q = reqs[i];
+        if (!q.count || !q.n_per_stream) continue;
+        const uint64_t es = q.dtype == MRG_F64 ? 8 : 4;
+        const uint64_t chunk = 64 * (256 / es);  // values per wave_fill chunk
+        BatchReq R = {};
+        R.out = (unsigned char *)q.d_out;
+        R.stream0 = q.first;
+        R.k = q.count;
+        R.n = q.n_per_stream;
+        R.sub0 = q.substream0;
+        R.dtype = (uint32_t)q.dtype;
+        R.flags = (q.flags & MRG_REQ_SUBSTREAMS) ? kReqSubstreams : kReqWriteBack;
+        if (R.n * es >= cfg.wave_min_bytes) {
+            uint64_t seg = cfg.segment_bytes / es / chunk * chunk;
+            if (seg < chunk) seg = chunk;
+            R.seg = seg;
+            R.segs = (R.n + seg - 1) / seg;
+            // streams that fit one segment are packed, about a segment per item
+            R.spi = R.segs == 1 ? (uint32_t)std::min<uint64_t>(seg / R.n, 1u << 20) : 1;
+            if (!R.spi) R.spi = 1;
+            if (R.segs > 1 && (R.flags & kReqWriteBack)) {
+                R.scratch0 = P.scratch_slots;
+                P.cb_stream0.push_back(R.stream0);
+                P.cb_scratch0.push_back(R.scratch0);
+                P.cb_prefix.push_back(P.cb_prefix.back() + R.k);
+                P.scratch_slots += R.k;
+            }
+        } else {
+            R.seg = 0;
+            R.segs = 1;
+            R.spi = 1;
+        }
+        P.in.push_back(R);
+        P.req_of.push_back((uint32_t)i);
+        P.samples += R.k * R.n;
+        P.bytes += R.k * R.n * es;
+    }
+    group_requests(P.in, &P.plan);
+}
+
 hipError_t launch_grouped(const Grouped &g, const BatchReq *d_reqs, const uint64_t *d_prefix,
                           unsigned long long *d_counters, const BatchArgs &base,
                           uint64_t grid_cap, int engine, hipStream_t st)
@@ -161,51 +211,17 @@ mrg_status upload(T **dst, const std::vector<T> &src, const char *what)
 mrg_status build_plan(mrg_batch b)
 {
     free_plan(b);
-    b->req_of.clear();
-    b->cb_prefix.assign(1, 0);
-    b->cb_stream0.clear();
-    b->cb_scratch0.clear();
-    b->scratch_slots = b->samples = b->bytes = 0;
-    std::vector<mrg::BatchReq> in;
-    for (size_t i = 0; i < b->reqs.size(); ++i) {
-        const mrg_request &q = b->reqs[i];
-        if (!q.count || !q.n_per_stream) continue;
-        const uint64_t es = q.dtype == MRG_F64 ? 8 : 4;
-        const uint64_t chunk = 64 * (256 / es);  // values per wave_fill chunk
-        mrg::BatchReq R = {};
-        R.out = (unsigned char *)q.d_out;
-        R.stream0 = q.first;
-        R.k = q.count;
-        R.n = q.n_per_stream;
-        R.sub0 = q.substream0;
-        R.dtype = (uint32_t)q.dtype;
-        R.flags = (q.flags & MRG_REQ_SUBSTREAMS) ? mrg::kReqSubstreams : mrg::kReqWriteBack;
-        if (R.n * es >= b->cfg.wave_min_bytes) {
-            uint64_t seg = b->cfg.segment_bytes / es / chunk * chunk;
-            if (seg < chunk) seg = chunk;
-            R.seg = seg;
-            R.segs = (R.n + seg - 1) / seg;
-            // streams that fit one segment are packed, about a segment per item
-            R.spi = R.segs == 1 ? (uint32_t)std::min<uint64_t>(seg / R.n, 1u << 20) : 1;
-            if (!R.spi) R.spi = 1;
-            if (R.segs > 1 && (R.flags & mrg::kReqWriteBack)) {
-                R.scratch0 = b->scratch_slots;
-                b->cb_stream0.push_back(R.stream0);
-                b->cb_scratch0.push_back(R.scratch0);
-                b->cb_prefix.push_back(b->cb_prefix.back() + R.k);
-                b->scratch_slots += R.k;
-            }
-        } else {
-            R.seg = 0;
-            R.segs = 1;
-            R.spi = 1;
-        }
-        in.push_back(R);
-        b->req_of.push_back((uint32_t)i);
-        b->samples += R.k * R.n;
-        b->bytes += R.k * R.n * es;
-    }
-    mrg::group_requests(in, &b->plan);
+    mrg::HostPlan hp;
+    mrg::plan_batch(b->reqs.data(), b->reqs.size(), b->cfg, &hp);
+    b->plan = std::move(hp.plan);
+    b->req_of = std::move(hp.req_of);
+    b->cb_prefix = std::move(hp.cb_prefix);
+    b->cb_stream0 = std::move(hp.cb_stream0);
+    b->cb_scratch0 = std::move(hp.cb_scratch0);
+    b->scratch_slots = hp.scratch_slots;
+    b->samples = hp.samples;
+    b->bytes = hp.bytes;
+    const std::vector<mrg::BatchReq> &in = hp.in;
     std::vector<uint64_t> solo;
     for (const mrg::BatchReq &R : in) {
         solo.push_back(0);
@@ -342,6 +358,17 @@ mrg_status validate(mrg_streamset ss, const mrg_request *reqs, uint64_t n)
 }
 
 }  // namespace
+
+namespace mrg {
+
+mrg_batch_config batch_config(const mrg_batch_config *c) { return effective(c); }
+
+mrg_status validate_batch(mrg_streamset ss, const mrg_request *reqs, uint64_t n)
+{
+    return validate(ss, reqs, n);
+}
+
+}  // namespace mrg
 
 extern "C" {
 
