@@ -273,11 +273,14 @@ __device__ __forceinline__ void rows_fill_short(G &g, unsigned char *lds, int la
 // the cheaper combination; in the rare piece where some lane's check fails,
 // the whole wave draws the piece again exactly, from the chunk's first state
 // jumped to the piece (the generator state itself is exact either way).
-// READ_ALL: read all eight LDS pieces of a flush before the first store (else
-// each piece goes straight to memory).  AUX: cache policy of the whole-line
-// stores.
+// NP: pieces each member stages per flush (1 or 2, dividing L / (128 / ES));
+// with 2, every store instruction covers runs of two adjacent lines of one
+// member instead of single lines 1 KiB apart (in a chunk where rows end the
+// flush stays at one piece).  `lds` then holds 64 * (NP * 128 + 16) bytes.
+// READ_ALL: read all LDS pieces of a flush before the first store (else each
+// piece goes straight to memory).  AUX: cache policy of the whole-line stores.
 // ---------------------------------------------------------------------------
-template <int DT, int L, class G, bool READ_ALL = true, int GL = 64, int AUX = 0>
+template <int DT, int L, class G, bool READ_ALL = true, int GL = 64, int AUX = 0, int NP = 1>
 __device__ __forceinline__ void wave_fill(uint32_t *w, const uint32_t *m, unsigned char *lds,
                                           int lane, unsigned char *srow, uint64_t row_stride,
                                           int nsv, uint64_t v0, uint64_t v1,
@@ -287,11 +290,12 @@ __device__ __forceinline__ void wave_fill(uint32_t *w, const uint32_t *m, unsign
     constexpr int ES = Elem<DT>::size;
     constexpr int TV = 128 / ES;   // values per 128-byte piece
     constexpr int NH = L / TV;     // pieces per lane per chunk
-    constexpr int RS = 128 + 16;   // LDS row pitch (bytes)
+    constexpr int RS = NP * 128 + 16;  // LDS row pitch (bytes)
     constexpr int SPW = 64 / GL;   // streams per wave
-    constexpr int JPS = GL / 8;    // flush instructions per stream
+    constexpr int JPS = GL / 8;    // flush instructions per stream and piece
     constexpr int ROUNDS = (TV + GL - 1) / GL;  // head rounds (heads are < TV values)
     static_assert(NH >= 1 && L % TV == 0, "chunk must be whole pieces");
+    static_assert((NP == 1 || NP == 2) && NH % NP == 0, "one or two pieces per flush");
     static_assert(GL == 64 || GL == 32 || GL == 16 || GL == 8, "8, 16, 32 or 64 lanes per stream");
     static_assert(ROUNDS * GL <= 64, "head table has 64 entries");
     const uint64_t chunk_vals = (uint64_t)GL * L;
@@ -372,50 +376,68 @@ __device__ __forceinline__ void wave_fill(uint32_t *w, const uint32_t *m, unsign
         }
         G g;
         g.load(st);
-        for (int h = 0; h < h_end; ++h) {
-            if constexpr (G::kCheckedDraws) {
-                uint32_t neg = 0;
+        const int npf = cut ? 1 : NP;  // pieces per lane in this chunk's flushes
+        for (int h = 0; h < h_end; h += npf) {
 #pragma unroll
-                for (int q = 0; q < 8; ++q) *(uint4 *)(my_lds + q * 16) = gen16<DT>(g, neg);
-                if (__any((int32_t)neg < 0)) {
-                    // this member's piece h starts gl*Lc + h*TV values into the chunk
-                    uint32_t ps[6] = {w[0], w[1], w[2], w[3], w[4], w[5]};
-                    jump_global(table, (uint64_t)gl * Lc + (uint64_t)h * TV, 0, 0, 0, 16, ps);
-                    G ge;
-                    ge.load(ps);
+            for (int p = 0; p < NP; ++p) {
+                if (p >= npf) break;
+                unsigned char *pl = my_lds + p * 128;
+                if constexpr (G::kCheckedDraws) {
+                    uint32_t neg = 0;
+#pragma unroll
+                    for (int q = 0; q < 8; ++q) *(uint4 *)(pl + q * 16) = gen16<DT>(g, neg);
+                    if (__any((int32_t)neg < 0)) {
+                        // this member's piece h + p starts gl*Lc + (h+p)*TV values
+                        // into the chunk
+                        uint32_t ps[6] = {w[0], w[1], w[2], w[3], w[4], w[5]};
+                        jump_global(table, (uint64_t)gl * Lc + (uint64_t)(h + p) * TV, 0, 0, 0, 16,
+                                    ps);
+                        G ge;
+                        ge.load(ps);
 #pragma unroll 1
-                    for (int q = 0; q < 8; ++q) *(uint4 *)(my_lds + q * 16) = gen16<DT>(ge);
-                }
-            } else {
+                        for (int q = 0; q < 8; ++q) *(uint4 *)(pl + q * 16) = gen16<DT>(ge);
+                    }
+                } else {
 #pragma unroll
-                for (int q = 0; q < 8; ++q) *(uint4 *)(my_lds + q * 16) = gen16<DT>(g);
+                    for (int q = 0; q < 8; ++q) *(uint4 *)(pl + q * 16) = gen16<DT>(g);
+                }
             }
             __syncthreads();
-            // piece row prow + 8j is stream j / JPS, member prow + 8 (j % JPS);
-            // each piece is one aligned 128-byte line of the row
+            // store instruction j takes the NP-piece runs of the 8 / NP lanes
+            // (members) 8j / NP ...: lane group prow writes piece P = 8j + prow,
+            // i.e. piece h + P % NP of lane P / NP, an aligned 128-byte line of
+            // that member's row; all lanes of one instruction serve one stream
             if (!cut) {
+                constexpr int NJ = 8 * NP;
                 if constexpr (READ_ALL) {
-                    uint4 v[8];
+                    uint4 v[NJ];
 #pragma unroll
-                    for (int j = 0; j < 8; ++j)
-                        v[j] = *(const uint4 *)(lds + (prow + 8 * j) * RS + pcol);
+                    for (int j = 0; j < NJ; ++j) {
+                        const int P = 8 * j + prow;
+                        v[j] = *(const uint4 *)(lds + (P / NP) * RS + (P % NP) * 128 + pcol);
+                    }
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        const int t = j / JPS;
+                    for (int j = 0; j < NJ; ++j) {
+                        const int t = j / (JPS * NP);
                         const uint64_t ct = v0 + hvt[t] + c * chunk_vals;
                         if ((SPW > 1 && t >= nsv) || ct + chunk_vals > v1) continue;
-                        const uint32_t loff = (uint32_t)((prow + 8 * (j % JPS)) * L * ES + pcol);
+                        const int P = 8 * j + prow;
+                        const uint32_t loff =
+                            (uint32_t)(((P / NP) % GL) * L * ES + (P % NP) * 128 + pcol);
                         store16_uniform<AUX>(srow + t * row_stride + (ct + (uint64_t)h * TV) * ES,
                                              loff, (uint32_t)(GL * L * ES), v[j]);
                     }
                 } else {
 #pragma unroll
-                    for (int j = 0; j < 8; ++j) {
-                        const int t = j / JPS;
+                    for (int j = 0; j < NJ; ++j) {
+                        const int t = j / (JPS * NP);
                         const uint64_t ct = v0 + hvt[t] + c * chunk_vals;
                         if ((SPW > 1 && t >= nsv) || ct + chunk_vals > v1) continue;
-                        const uint4 v = *(const uint4 *)(lds + (prow + 8 * j) * RS + pcol);
-                        const uint32_t loff = (uint32_t)((prow + 8 * (j % JPS)) * L * ES + pcol);
+                        const int P = 8 * j + prow;
+                        const uint4 v =
+                            *(const uint4 *)(lds + (P / NP) * RS + (P % NP) * 128 + pcol);
+                        const uint32_t loff =
+                            (uint32_t)(((P / NP) % GL) * L * ES + (P % NP) * 128 + pcol);
                         store16_uniform<AUX>(srow + t * row_stride + (ct + (uint64_t)h * TV) * ES,
                                              loff, (uint32_t)(GL * L * ES), v);
                     }

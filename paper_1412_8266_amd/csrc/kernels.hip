@@ -185,10 +185,16 @@ fill_il_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t fi
 // wave_fill, so that every flush writes whole 128-byte lines and the streams
 // in flight stay adjacent.  Lanes of a group past the last stream run on a
 // dummy state and write nothing.  Groups go to XCDs by xcd_chunk (or
-// xcd_range), gen_device.hpp.  Four waves per SIMD is what the LDS allows
-// (9 KiB per wave); the bound keeps the register count inside that.
+// xcd_range), gen_device.hpp.  Members stage two pieces per flush when their
+// chunk segment holds an even number of them (runs of two lines per member
+// per store instruction: 4 % faster on 2^20 x 4096 uint32 than one piece, at
+// 17 KiB of LDS per wave, two waves per SIMD); else one (9 KiB, four waves
+// per SIMD).  The bound keeps the register count inside that occupancy.
+template <int DT, int L>
+constexpr int coop_pieces() { return (L / (128 / Elem<DT>::size)) % 2 == 0 ? 2 : 1; }
+
 template <int DT, int L, int GL, class G>
-__global__ void __launch_bounds__(64, 4)
+__global__ void __launch_bounds__(64, (coop_pieces<DT, L>() == 2 ? 2 : 4))
 fill_coop_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t first,
                  uint64_t count, uint64_t n, unsigned char *__restrict__ out,
                  const uint32_t *__restrict__ lane_tab, const uint32_t *__restrict__ tabs,
@@ -196,7 +202,8 @@ fill_coop_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t 
 {
     constexpr int ES = Elem<DT>::size;
     constexpr int SPW = 64 / GL;
-    __shared__ __attribute__((aligned(16))) unsigned char lds[64 * 144];
+    constexpr int NP = coop_pieces<DT, L>();
+    __shared__ __attribute__((aligned(16))) unsigned char lds[64 * (NP * 128 + 16)];
     const int lane = threadIdx.x;
     const int t = lane / GL;  // this lane's stream within the group
 
@@ -213,8 +220,8 @@ fill_coop_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t 
         uint32_t m[18];
 #pragma unroll
         for (int i = 0; i < 18; ++i) m[i] = lane_tab[(lane % GL) * 18 + i];
-        wave_fill<DT, L, G, true, GL>(w, m, lds, lane, out + s0 * n * ES, n * ES, nsv, 0, n, table,
-                                      tabs, true);
+        wave_fill<DT, L, G, true, GL, 0, NP>(w, m, lds, lane, out + s0 * n * ES, n * ES, nsv, 0, n,
+                                             table, tabs, true);
         if (lane % GL == 0 && t < nsv) store_state(planes, plane_stride, idx, w);
     }
 }
