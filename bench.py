@@ -192,9 +192,9 @@ def batched(mg, wl, torch, stream, reps):
     # stream length above which a stream gets a whole wave instead of a lane
     cands = [mg.batch_config(segment_bytes=sb, waves_per_cu=w, schedule=sc, wave_min_bytes=wm)
              for sb, w, sc, wm in [(256 << 10, 16, 1, 16 << 10), (1 << 20, 16, 1, 16 << 10),
-                                   (256 << 10, 8, 1, 16 << 10), (64 << 10, 16, 1, 16 << 10),
-                                   (256 << 10, 16, 2, 16 << 10), (1 << 20, 16, 1, 4 << 10),
-                                   (1 << 20, 16, 1, 64 << 10)]]
+                                   (256 << 10, 8, 1, 16 << 10), (1 << 20, 8, 1, 16 << 10),
+                                   (64 << 10, 16, 1, 16 << 10), (256 << 10, 8, 2, 16 << 10),
+                                   (1 << 20, 16, 1, 4 << 10), (1 << 20, 16, 1, 64 << 10)]]
     t0 = time.perf_counter()
     best, cand_ms = b.autotune(cands, reps=1)
     tune_s = time.perf_counter() - t0

@@ -109,6 +109,24 @@ struct GenF {
         asm("v_or_b32 %0, %0, %1" : "+v"(neg) : "v"(__builtin_bit_cast(uint2, r2).y));
         return combinef_nn(r1, r2);
     }
+    // Two checked draws (combined values za then zb) whose sign checks take
+    // one v_or3_b32 between them, again kept as written.
+    __device__ __forceinline__ void step2_nn(double &za, double &zb, uint32_t &neg)
+    {
+        const double r1a = next1f(a0, a1);
+        const double r2a = next2f(b0, b2);
+        a0 = a1; a1 = a2; a2 = r1a;
+        b0 = b1; b1 = b2; b2 = r2a;
+        const double r1b = next1f(a0, a1);
+        const double r2b = next2f(b0, b2);
+        a0 = a1; a1 = a2; a2 = r1b;
+        b0 = b1; b1 = b2; b2 = r2b;
+        asm("v_or3_b32 %0, %0, %1, %2"
+            : "+v"(neg)
+            : "v"(__builtin_bit_cast(uint2, r2a).y), "v"(__builtin_bit_cast(uint2, r2b).y));
+        za = combinef_nn(r1a, r2a);
+        zb = combinef_nn(r1b, r2b);
+    }
     __device__ __forceinline__ uint32_t next_u32(uint32_t &neg) { return (uint32_t)step_nn(neg); }
     __device__ __forceinline__ float next_f32(uint32_t &neg) { return to_f32f(step_nn(neg)); }
     __device__ __forceinline__ double next_f64(uint32_t &neg) { return to_f64f(step_nn(neg)); }

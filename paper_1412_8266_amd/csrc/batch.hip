@@ -81,8 +81,8 @@ __device__ __forceinline__ void wave_item(const BatchReq &R, uint64_t local, uns
         // exponent v0 + sub * 2^76 (v0 < 2^64: no carry between the words)
         jump_global(A.table, v0, sub << 12, sub >> 52, 0, kTableWindows, w);
         const bool end = (R.flags & kReqWriteBack) && v1 == R.n;
-        wave_fill<DT, L, G, false>(w, m, lds, lane, R.out + j * R.n * ES, 0, 1, v0, v1, A.table,
-                                   A.lane_tab, end);
+        wave_fill<DT, L, G, false, 64, 0, 2>(w, m, lds, lane, R.out + j * R.n * ES, 0, 1, v0, v1,
+                                             A.table, A.lane_tab, end);
         if (end) {
             if (lane == 0) {
                 if (R.segs == 1) store_state(A.planes, A.plane_stride, R.stream0 + j, w);
@@ -119,11 +119,13 @@ __device__ __forceinline__ void row_item(const BatchReq &R, uint64_t local, unsi
 // register use at that of the plain fill kernels.  The writers move each LDS
 // piece straight to memory (READ_ALL = false): staging all eight pieces in an
 // array first, as the plain fill kernels do, sends that array to scratch
-// memory inside this loop.
+// memory inside this loop.  Wave items stage two pieces per member per flush
+// (runs of two lines per store instruction, 17 KiB of LDS per wave), row
+// items one 128-byte tile per row (9 KiB).
 template <int DT, int KIND, class G>
 __global__ void __launch_bounds__(64) batch_kernel(BatchArgs A)
 {
-    __shared__ __attribute__((aligned(16))) unsigned char lds[64 * 144];
+    __shared__ __attribute__((aligned(16))) unsigned char lds[64 * (KIND == kKindWave ? 272 : 144)];
     const int lane = threadIdx.x;
     uint32_t m[18];  // wave items: the lane's A^(lane * L), L = 256 bytes of values
     if constexpr (KIND == kKindWave) {

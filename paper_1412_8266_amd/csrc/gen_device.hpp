@@ -43,24 +43,31 @@ __device__ __forceinline__ uint4 gen16(G &g)
     return v;
 }
 
-// The same 16 bytes from checked draws (G::kCheckedDraws): exact unless the
-// sign bit of `neg` comes out set (see GenF).
+// The same 16 bytes from checked draws (G::kCheckedDraws), taken in pairs
+// (one sign check instruction per pair): exact unless the sign bit of `neg`
+// comes out set (see GenF).
 template <int DT, class G>
 __device__ __forceinline__ uint4 gen16(G &g, uint32_t &neg)
 {
     uint4 v;
-    if constexpr (DT == 0) {
-        v.x = g.next_u32(neg); v.y = g.next_u32(neg); v.z = g.next_u32(neg); v.w = g.next_u32(neg);
-    } else if constexpr (DT == 1) {
-        v.x = __float_as_uint(g.next_f32(neg));
-        v.y = __float_as_uint(g.next_f32(neg));
-        v.z = __float_as_uint(g.next_f32(neg));
-        v.w = __float_as_uint(g.next_f32(neg));
-    } else {
-        const uint64_t u0 = (uint64_t)__double_as_longlong(g.next_f64(neg));
-        const uint64_t u1 = (uint64_t)__double_as_longlong(g.next_f64(neg));
+    double z0, z1;
+    g.step2_nn(z0, z1, neg);
+    if constexpr (DT == 2) {
+        const uint64_t u0 = (uint64_t)__double_as_longlong(to_f64f(z0));
+        const uint64_t u1 = (uint64_t)__double_as_longlong(to_f64f(z1));
         v.x = (uint32_t)u0; v.y = (uint32_t)(u0 >> 32);
         v.z = (uint32_t)u1; v.w = (uint32_t)(u1 >> 32);
+    } else {
+        double z2, z3;
+        g.step2_nn(z2, z3, neg);
+        if constexpr (DT == 0) {
+            v.x = (uint32_t)z0; v.y = (uint32_t)z1; v.z = (uint32_t)z2; v.w = (uint32_t)z3;
+        } else {
+            v.x = __float_as_uint(to_f32f(z0));
+            v.y = __float_as_uint(to_f32f(z1));
+            v.z = __float_as_uint(to_f32f(z2));
+            v.w = __float_as_uint(to_f32f(z3));
+        }
     }
     return v;
 }
@@ -79,16 +86,30 @@ __device__ __forceinline__ void put1(unsigned char *p, G &g)
 // instruction on its 64-bit address.  Offsets at or past span are dropped.
 // AUX is the instruction's cache-policy field (0: the default write-back).
 typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
-template <int AUX = 0>
-__device__ __forceinline__ void store16_uniform(const unsigned char *base, uint32_t off,
-                                                uint32_t span, uint4 v)
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t uniform_rsrc(const unsigned char *base,
+                                                              uint32_t span)
 {
     const uint64_t b = (uint64_t)base;
     const uint64_t bu = (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)b) |
                         (uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(b >> 32)) << 32;
-    const __amdgpu_buffer_rsrc_t r =
-        __builtin_amdgcn_make_buffer_rsrc((void *)bu, 0, (int)span, 0x00020000);
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, v), r, off, 0, AUX);
+    return __builtin_amdgcn_make_buffer_rsrc((void *)bu, 0, (int)span, 0x00020000);
+}
+
+template <int AUX = 0>
+__device__ __forceinline__ void store16_uniform(const unsigned char *base, uint32_t off,
+                                                uint32_t span, uint4 v)
+{
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, v), uniform_rsrc(base, span),
+                                           off, 0, AUX);
+}
+
+// 16-byte store at soff + voff bytes past the base of descriptor r (soff
+// wave-uniform, voff per lane).
+template <int AUX = 0>
+__device__ __forceinline__ void store16_rsrc(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff,
+                                             uint4 v)
+{
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4_t, v), r, voff, soff, AUX);
 }
 
 template <int ES>
@@ -246,6 +267,33 @@ __device__ __forceinline__ void rows_fill_short(G &g, unsigned char *lds, int la
     __syncthreads();
 }
 
+// One 128-byte piece (128 / ES values) of a member's segment from g into
+// LDS at pl.  With checked draws (GenF) the piece is drawn with the cheaper
+// combination; when some lane's check fails the whole wave draws it again
+// exactly, each lane from the state `at` values past w0 (the piece's first
+// value: w0 is the chunk's first state).  g moves on by the piece either way.
+template <int DT, class G>
+__device__ __forceinline__ void draw_piece(G &g, unsigned char *pl, const uint32_t *w0, uint64_t at,
+                                           const uint32_t *__restrict__ table)
+{
+    if constexpr (G::kCheckedDraws) {
+        uint32_t neg = 0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) *(uint4 *)(pl + q * 16) = gen16<DT>(g, neg);
+        if (__any((int32_t)neg < 0)) {
+            uint32_t ps[6] = {w0[0], w0[1], w0[2], w0[3], w0[4], w0[5]};
+            jump_global(table, at, 0, 0, 0, 16, ps);
+            G ge;
+            ge.load(ps);
+#pragma unroll 1
+            for (int q = 0; q < 8; ++q) *(uint4 *)(pl + q * 16) = gen16<DT>(ge);
+        }
+    } else {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) *(uint4 *)(pl + q * 16) = gen16<DT>(g);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // wave_fill: values [v0, v1) of 64/GL streams at once, GL lanes per stream
 // (lane l serves stream l / GL as its member g = l % GL).  Stream t of the
@@ -376,39 +424,34 @@ __device__ __forceinline__ void wave_fill(uint32_t *w, const uint32_t *m, unsign
         }
         G g;
         g.load(st);
-        const int npf = cut ? 1 : NP;  // pieces per lane in this chunk's flushes
-        for (int h = 0; h < h_end; h += npf) {
+        // piece h + p of this member (gl*Lc + (h+p)*TV values into the
+        // chunk) into its LDS row at p * 128
+        auto draw = [&](int h, int p) {
+            draw_piece<DT>(g, my_lds + p * 128, w, (uint64_t)gl * Lc + (uint64_t)(h + p) * TV,
+                           table);
+        };
+        if (!cut) {
+            // whole chunks: NP pieces per member per flush; store instruction
+            // j takes the NP-piece runs of the 8 / NP lanes (members) 8j / NP
+            // ...: lane group prow writes piece P = 8j + prow, i.e. piece
+            // h + P % NP of lane P / NP, an aligned 128-byte line of that
+            // member's row; all lanes of one instruction serve one stream
+            constexpr int NJ = 8 * NP;
+            // per stream of the wave: written in this chunk or not, and a
+            // descriptor based at its chunk (the pieces then differ only by
+            // the per-lane offset and the flush's uniform offset)
+            __amdgpu_buffer_rsrc_t rs[SPW];
+            uint32_t live = 0;
 #pragma unroll
-            for (int p = 0; p < NP; ++p) {
-                if (p >= npf) break;
-                unsigned char *pl = my_lds + p * 128;
-                if constexpr (G::kCheckedDraws) {
-                    uint32_t neg = 0;
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) *(uint4 *)(pl + q * 16) = gen16<DT>(g, neg);
-                    if (__any((int32_t)neg < 0)) {
-                        // this member's piece h + p starts gl*Lc + (h+p)*TV values
-                        // into the chunk
-                        uint32_t ps[6] = {w[0], w[1], w[2], w[3], w[4], w[5]};
-                        jump_global(table, (uint64_t)gl * Lc + (uint64_t)(h + p) * TV, 0, 0, 0, 16,
-                                    ps);
-                        G ge;
-                        ge.load(ps);
-#pragma unroll 1
-                        for (int q = 0; q < 8; ++q) *(uint4 *)(pl + q * 16) = gen16<DT>(ge);
-                    }
-                } else {
-#pragma unroll
-                    for (int q = 0; q < 8; ++q) *(uint4 *)(pl + q * 16) = gen16<DT>(g);
-                }
+            for (int t = 0; t < SPW; ++t) {
+                const uint64_t ct = v0 + hvt[t] + c * chunk_vals;
+                if (!((SPW > 1 && t >= nsv) || ct + chunk_vals > v1)) live |= 1u << t;
+                rs[t] = uniform_rsrc(srow + t * row_stride + ct * ES, (uint32_t)(GL * L * ES));
             }
-            __syncthreads();
-            // store instruction j takes the NP-piece runs of the 8 / NP lanes
-            // (members) 8j / NP ...: lane group prow writes piece P = 8j + prow,
-            // i.e. piece h + P % NP of lane P / NP, an aligned 128-byte line of
-            // that member's row; all lanes of one instruction serve one stream
-            if (!cut) {
-                constexpr int NJ = 8 * NP;
+            for (int h = 0; h < NH; h += NP) {
+#pragma unroll
+                for (int p = 0; p < NP; ++p) draw(h, p);
+                __syncthreads();
                 if constexpr (READ_ALL) {
                     uint4 v[NJ];
 #pragma unroll
@@ -419,32 +462,34 @@ __device__ __forceinline__ void wave_fill(uint32_t *w, const uint32_t *m, unsign
 #pragma unroll
                     for (int j = 0; j < NJ; ++j) {
                         const int t = j / (JPS * NP);
-                        const uint64_t ct = v0 + hvt[t] + c * chunk_vals;
-                        if ((SPW > 1 && t >= nsv) || ct + chunk_vals > v1) continue;
+                        if (!((live >> t) & 1u)) continue;
                         const int P = 8 * j + prow;
                         const uint32_t loff =
                             (uint32_t)(((P / NP) % GL) * L * ES + (P % NP) * 128 + pcol);
-                        store16_uniform<AUX>(srow + t * row_stride + (ct + (uint64_t)h * TV) * ES,
-                                             loff, (uint32_t)(GL * L * ES), v[j]);
+                        store16_rsrc<AUX>(rs[t], loff, (uint32_t)(h * TV * ES), v[j]);
                     }
                 } else {
 #pragma unroll
                     for (int j = 0; j < NJ; ++j) {
                         const int t = j / (JPS * NP);
-                        const uint64_t ct = v0 + hvt[t] + c * chunk_vals;
-                        if ((SPW > 1 && t >= nsv) || ct + chunk_vals > v1) continue;
+                        if (!((live >> t) & 1u)) continue;
                         const int P = 8 * j + prow;
                         const uint4 v =
                             *(const uint4 *)(lds + (P / NP) * RS + (P % NP) * 128 + pcol);
                         const uint32_t loff =
                             (uint32_t)(((P / NP) % GL) * L * ES + (P % NP) * 128 + pcol);
-                        store16_uniform<AUX>(srow + t * row_stride + (ct + (uint64_t)h * TV) * ES,
-                                             loff, (uint32_t)(GL * L * ES), v);
+                        store16_rsrc<AUX>(rs[t], loff, (uint32_t)(h * TV * ES), v);
                     }
                 }
-            } else {
-                // some row ends here: the same pieces, 16-byte stores below
-                // the end and dword stores for the group that straddles it
+                __syncthreads();
+            }
+        } else {
+            // some row ends here: one piece per flush, 16-byte stores below
+            // the end and dword stores for the group that straddles it
+            for (int h = 0; h < h_end; ++h) {
+                draw(h, 0);
+                __syncthreads();
+                // piece row prow + 8j is stream j / JPS, member prow + 8 (j % JPS)
 #pragma unroll 1
                 for (int j = 0; j < 8; ++j) {
                     const int t = j / JPS;
@@ -466,8 +511,8 @@ __device__ __forceinline__ void wave_fill(uint32_t *w, const uint32_t *m, unsign
                         if (o + 8 < rem) *(uint32_t *)(p + 8) = v.z;
                     }
                 }
+                __syncthreads();
             }
-            __syncthreads();
         }
         if (full) {  // member GL-1 ends at the next chunk's first state
             uint32_t e[6];
@@ -480,6 +525,70 @@ __device__ __forceinline__ void wave_fill(uint32_t *w, const uint32_t *m, unsign
     }
     // w is the last chunk's first state: move it over the partial chunk
     if (!whole && want_end) jump_global(table, (v1 - start) % chunk_vals, 0, 0, 0, 16, w);
+}
+
+// ---------------------------------------------------------------------------
+// wave_fill_whole: wave_fill(w, ..., 0, n, ..., want_end) for the bulk case
+// where every chunk is whole and every row starts on a line: 64/GL full
+// streams of n values, n a multiple of the chunk GL*L, srow 128-byte aligned,
+// row pitch n*ES a multiple of 128, and the group's 64/GL rows addressable
+// from srow with 32-bit offsets (64/GL * n * ES < 2^32).  One descriptor for
+// the group; a store's lane offset is fixed by its piece slot and the flush
+// adds a wave-uniform offset.  Same outputs and end states as wave_fill.
+// ---------------------------------------------------------------------------
+template <int DT, int L, class G, int GL, int NP, int AUX = 0>
+__device__ __forceinline__ void wave_fill_whole(uint32_t *w, const uint32_t *m, unsigned char *lds,
+                                                int lane, unsigned char *srow, uint64_t n,
+                                                const uint32_t *__restrict__ table)
+{
+    constexpr int ES = Elem<DT>::size;
+    constexpr int TV = 128 / ES;       // values per 128-byte piece
+    constexpr int NH = L / TV;         // pieces per lane per chunk
+    constexpr int RS = NP * 128 + 16;  // LDS row pitch (bytes)
+    constexpr int SPW = 64 / GL;
+    constexpr int NJ = 8 * NP;         // store instructions per flush
+    static_assert((NP == 1 || NP == 2) && NH % NP == 0, "one or two pieces per flush");
+    const int tl = lane / GL, gl = lane % GL;
+    const int prow = lane >> 3, pcol = (lane & 7) * 16;
+    unsigned char *my_lds = lds + lane * RS;
+    const uint32_t row_bytes = (uint32_t)(n * ES);
+    const __amdgpu_buffer_rsrc_t rsrc = uniform_rsrc(srow, SPW * row_bytes);
+    const uint64_t nchunks = n / ((uint64_t)GL * L);
+    for (uint64_t c = 0; c < nchunks; ++c) {
+        uint32_t st[6] = {w[0], w[1], w[2], w[3], w[4], w[5]};
+        matvec3<C1>(m, st[0], st[1], st[2]);
+        matvec3<C2>(m + 9, st[3], st[4], st[5]);
+        G g;
+        g.load(st);
+        for (int h = 0; h < NH; h += NP) {
+#pragma unroll
+            for (int p = 0; p < NP; ++p)
+                draw_piece<DT>(g, my_lds + p * 128, w, (uint64_t)gl * L + (uint64_t)(h + p) * TV,
+                               table);
+            __syncthreads();
+            // store j: piece P = 8j + prow is piece h + P % NP of lane P / NP
+            uint4 v[NJ];
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const int P = 8 * j + prow;
+                v[j] = *(const uint4 *)(lds + (P / NP) * RS + (P % NP) * 128 + pcol);
+            }
+            const uint32_t soff = (uint32_t)((c * GL * L + (uint64_t)h * TV) * ES);
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) {
+                const int P = 8 * j + prow, owner = P / NP;
+                const uint32_t voff = (uint32_t)(owner / GL) * row_bytes +
+                                      (uint32_t)((owner % GL) * L * ES + (P % NP) * 128 + pcol);
+                store16_rsrc<AUX>(rsrc, voff, soff, v[j]);
+            }
+            __syncthreads();
+        }
+        // member GL-1 ends at the next chunk's first state
+        uint32_t e[6];
+        g.store(e);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) w[k] = __shfl(e[k], tl * GL + GL - 1);
+    }
 }
 
 // Workgroups are dispatched to the 8 XCDs in turn (workgroup b on XCD b % 8).

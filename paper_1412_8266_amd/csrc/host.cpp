@@ -617,6 +617,10 @@ mrg_status mrg_fill(mrg_streamset ss, uint64_t first, uint64_t count, uint64_t n
                                                       : ((uint64_t)1 << 31) - 1;
             fl.grid = (unsigned)(groups < cap ? groups : cap);
             fl.order = tune.coop_order;
+            // the bulk case: rows on lines, whole chunks, a group's rows
+            // addressable with 32-bit offsets
+            fl.whole = rows_aligned && n_per_stream % ((uint64_t)GL * L) == 0 &&
+                       (uint64_t)(64 / GL) * n_per_stream * es < ((uint64_t)1 << 32);
         }
     }
     hipError_t e = mrg::launch_fill(ss->d_planes, ss->n, first, count, n_per_stream, (int)dtype,

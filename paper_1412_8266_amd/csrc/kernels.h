@@ -51,6 +51,7 @@ struct FillLaunch {
     const uint32_t *table = nullptr;    // windowed jump tables (end state of a partial chunk)
     unsigned grid = 0;                  // workgroups (wave per stream)
     int order = 0;                      // group order (FillTuning::coop_order)
+    int whole = 0;                      // rows on 128-byte lines, whole chunks only (fast writer)
 };
 
 hipError_t launch_fill(uint32_t *planes, uint64_t plane_stride, uint64_t first, uint64_t count,

@@ -198,7 +198,7 @@ __global__ void __launch_bounds__(64, (coop_pieces<DT, L>() == 2 ? 2 : 4))
 fill_coop_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t first,
                  uint64_t count, uint64_t n, unsigned char *__restrict__ out,
                  const uint32_t *__restrict__ lane_tab, const uint32_t *__restrict__ tabs,
-                 const uint32_t *__restrict__ table, int order)
+                 const uint32_t *__restrict__ table, int order, int whole)
 {
     constexpr int ES = Elem<DT>::size;
     constexpr int SPW = 64 / GL;
@@ -220,8 +220,11 @@ fill_coop_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t 
         uint32_t m[18];
 #pragma unroll
         for (int i = 0; i < 18; ++i) m[i] = lane_tab[(lane % GL) * 18 + i];
-        wave_fill<DT, L, G, true, GL, 0, NP>(w, m, lds, lane, out + s0 * n * ES, n * ES, nsv, 0, n,
-                                             table, tabs, true);
+        if (whole && nsv == SPW)  // every chunk whole, rows on lines (checked on the host)
+            wave_fill_whole<DT, L, G, GL, NP>(w, m, lds, lane, out + s0 * n * ES, n, table);
+        else
+            wave_fill<DT, L, G, true, GL, 0, NP>(w, m, lds, lane, out + s0 * n * ES, n * ES, nsv, 0,
+                                                 n, table, tabs, true);
         if (lane % GL == 0 && t < nsv) store_state(planes, plane_stride, idx, w);
     }
 }
@@ -391,7 +394,7 @@ static hipError_t launch_fill_g(uint32_t *planes, uint64_t plane_stride, uint64_
 #define MRG_COOP(GL, NH)                                                                        \
     hipLaunchKernelGGL((fill_coop_kernel<DT, (NH) * TV, GL, G>), grid, block, 0, st, planes,     \
                        plane_stride, first, count, n, o, fl.lane_tab, fl.tabs, fl.table,   \
-                       fl.order)
+                       fl.order, fl.whole)
         if (fl.L % TV) return hipErrorInvalidValue;
         else if (fl.lanes == 64 && nh == 1) MRG_COOP(64, 1);
         else if (fl.lanes == 64 && nh == 2) MRG_COOP(64, 2);

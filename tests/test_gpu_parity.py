@@ -451,6 +451,52 @@ def test_random_fill_sweep(mg):
             mg.mrg_config_set(k, v)
 
 
+# (count, n, dtype, lanes per stream): rows on 128-byte lines and whole
+# chunks only, so every full group takes the whole-chunk writer; counts that
+# leave a partial last group (general writer), one and several chunks per row
+WHOLE_SHAPES = [(1001, 4096, 0, 16), (7, 12288, 0, 16), (66, 8192, 1, 32), (130, 4096, 2, 16),
+                (9, 16384, 0, 8), (3, 65536, 0, 64), (64, 2048, 1, 16), (255, 6144, 0, 32)]
+
+
+@pytest.mark.parametrize("engine_id", [1, 0], ids=["f64", "int"])
+def test_whole_chunk_writer(mg, engine_id):
+    """The wave-per-stream fill's whole-chunk writer (rows starting on lines,
+    row lengths a multiple of the chunk) against the oracle, with stream
+    ranges that start inside the set and end in a partial group, twice in a
+    row, every output and end state, inside guard words."""
+    import torch
+    keys = ("engine", "strategy", "coop_lanes")
+    old = [mg.mrg_config_get(k) for k in keys]
+    base = oracle.seed_from_master(4096)
+    try:
+        for count, n, dt, lanes in WHOLE_SHAPES:
+            for k, v in zip(keys, (engine_id, 2, lanes)):
+                mg.mrg_config_set(k, v)
+            say("whole-chunk writer", engine_id, count, n, dt, lanes)
+            first = 3
+            ss = mg.StreamSet(first + count + 2, seed=[int(x) for x in base])
+            st = oracle.streams(base, first, count)
+            guard = 1024  # a line-aligned view inside the buffer
+            buf = torch.zeros(count * n + 2 * guard, dtype=mg.torch_dtype(dt), device="cuda")
+            assert buf.data_ptr() % 128 == 0
+            for rep in range(2):
+                buf.zero_()
+                view = buf[guard:guard + count * n]
+                ss.fill_ptr(n, dt, 0, view.data_ptr(), first=first, count=count)
+                h = host(buf)
+                want, st = oracle_threaded(st, n, dt)
+                got = h[guard:guard + count * n]
+                assert np.array_equal(got.view(np.uint8), want.reshape(-1).view(np.uint8)), \
+                    (count, n, dt, lanes, rep)
+                assert not h[:guard].view(np.uint8).any(), (count, n, dt, lanes, "before")
+                assert not h[guard + count * n:].view(np.uint8).any(), (count, n, dt, lanes, "after")
+            assert np.array_equal(ss.get_states(first, count), st), (count, n, dt, lanes)
+            ss.close()
+    finally:
+        for k, v in zip(keys, old):
+            mg.mrg_config_set(k, v)
+
+
 @pytest.mark.parametrize("gen", ["mrg32k3a", "philox"])
 def test_degenerate_calls_change_nothing(mg, gen):
     """Empty ranges, zero-length fills, zero jumps and empty deals write
