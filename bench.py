@@ -40,10 +40,10 @@ METRIC = "uint32 Gsamples/s (% HBM write roofline), batched vs plain; p50/p99 la
 # (SQ_INSTS_VALU).  They are reported only while the sources still hash the
 # same; after any change to the kernel they read null until profiled again.
 COUNTERS = {
-    "traffic": None,
-    "valu_insts": None,
-    "source": None,
-    "kernel_sources_sha256": None,
+    "traffic": 17230900255,
+    "valu_insts": 1079772000,
+    "source": "profiles/fill_coop_u32_16lanes_2p20x4096.md",
+    "kernel_sources_sha256": "1f47c8ee9407961036259dd34ff3d450e069ebfc4e91befebc002362ff17b17b",
 }
 KERNEL_SOURCES = ["include/mrg_arith.hpp", "include/mrg32k3a_device.h",
                   "paper_1412_8266_amd/csrc/gen_device.hpp", "paper_1412_8266_amd/csrc/kernels.hip",
@@ -435,7 +435,8 @@ def main():
             "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": COUNTERS["traffic"] if counters_current() else None,
-            "traffic_source": COUNTERS["source"] if counters_current() else
+            "traffic_source": "%s (kernel sources sha256 %s)" % (
+                COUNTERS["source"], COUNTERS["kernel_sources_sha256"][:16]) if counters_current() else
             "none: the kernel sources changed since the last counter profile",
             "kernel": ("fill_coop_kernel<u32, %d lanes per stream>" % coop_lanes_used(mg, n * 4))
                       if n >= 2048 and mg.mrg_config_get("strategy") != 1
@@ -470,7 +471,8 @@ def main():
                                     "ms": round(msi, 4)}
         # store-only probes over the same 16 GiB: what the stores alone attain
         probe = {}
-        for name, pat in (("streaming_16B", 0), ("fill_lines", 1), ("fill_runs_of_8_lines", 2)):
+        for name, pat in (("streaming_16B", 0), ("fill_lines", 1), ("fill_runs_of_8_lines", 2),
+                          ("single_lines", 3)):
             per_p, _ = timed(lambda: mg.write_probe(out, pat, stream), args.steps, 1, stream)
             msp = sum(per_p) / len(per_p)
             probe[name + "_GBs"] = round(out.numel() * 4 / msp / 1e6, 1)

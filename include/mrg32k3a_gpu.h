@@ -560,10 +560,14 @@ mrg_status mrg_config_get(const char *key, int64_t *value);
  *   pattern 0: streaming 16-byte stores, one pass in address order (bytes a
  *              multiple of 16, d_out 16-byte aligned);
  *   pattern 1: the wave-per-stream fill's geometry at 16 lanes per stream and
- *              1 KiB per lane: four 16 KiB rows per wave, 128-byte lines staged
- *              in LDS (bytes a multiple of 65536, d_out 128-byte aligned);
+ *              1 KiB per lane: four 16 KiB rows per wave, two 128-byte lines
+ *              per lane staged in LDS per flush, each store instruction four
+ *              runs of two adjacent lines (bytes a multiple of 65536, d_out
+ *              128-byte aligned);
  *   pattern 2: the same 64 KiB per wave as runs of 8 lines (1 KiB) per store
- *              instruction (sizes and alignment as pattern 1).
+ *              instruction (sizes and alignment as pattern 1);
+ *   pattern 3: as pattern 1 with one line per lane per flush (8 single lines
+ *              1 KiB apart per store instruction).
  * Other patterns or sizes, or d_out not device memory of the current device:
  * MRG_EINVAL.  Asynchronous. */
 mrg_status mrg_write_probe(void *d_out, uint64_t bytes, int32_t pattern, void *stream);

@@ -255,8 +255,9 @@ def tinymt_test_candidates(master_seed: int, c0: int, n: int, with_phi: bool = F
 def write_probe(out, pattern: int = 0, stream=None) -> None:
     """Store-only bandwidth probe over the whole of `out` (a CUDA tensor):
     pattern 0 streaming 16-byte stores in one pass, 1 the wave-per-stream
-    fill's 128-byte line geometry, 2 the same with runs of 8 lines per store
-    instruction (mrg_write_probe in the C ABI)."""
+    fill's geometry (runs of two 128-byte lines per member), 2 the same with
+    runs of 8 lines per store instruction, 3 single lines per member
+    (mrg_write_probe in the C ABI)."""
     _abi.mrg_write_probe(out.data_ptr(), out.numel() * out.element_size(), pattern,
                          _stream_handle(stream))
 

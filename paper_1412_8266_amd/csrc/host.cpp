@@ -832,7 +832,7 @@ const char *mrg_last_error(void) { return g_last_error.c_str(); }
 
 mrg_status mrg_write_probe(void *d_out, uint64_t bytes, int32_t pattern, void *stream)
 {
-    if (pattern < 0 || pattern > 2) return set_error(MRG_EINVAL, "unknown probe pattern %d", pattern);
+    if (pattern < 0 || pattern > 3) return set_error(MRG_EINVAL, "unknown probe pattern %d", pattern);
     if (!d_out) return set_error(MRG_EINVAL, "null output");
     const uint64_t unit = pattern == 0 ? 16 : 65536, align = pattern == 0 ? 16 : 128;
     if (bytes % unit) return set_error(MRG_EINVAL, "probe size must be a multiple of %llu bytes",

@@ -266,12 +266,13 @@ def test_negative_component2_words(mg, engine, dtype):
     too big and the word comes out negative: the wave-per-stream writer's
     checked draws must draw that piece again.  Positions fall in row heads,
     first and last pieces, chunk and member boundaries and row tails, for
-    aligned and unaligned rows, inside guard words."""
+    aligned and unaligned rows (aligned rows of whole chunks go through the
+    whole-chunk writer), inside guard words."""
     import torch
     from tests import crafted
     rng = np.random.default_rng(77)
     es = 8 if dtype == 2 else 4
-    for n, off in [(4096, 0), (5000, 3), (2048, 0), (9000, 1), (300, 1)]:
+    for n, off in [(4096, 0), (4096, 5), (5000, 3), (2048, 0), (9000, 1), (300, 1), (8192, 0)]:
         pos = {0, 1, 2, 31, 32, 33, 63, 64, 127, 128, 255, 256, 257, 511, 512, 1023, 1024,
                n - 33, n - 32, n - 2, n - 1} | set(int(x) for x in rng.integers(0, n, 12))
         positions = sorted(k for k in pos if 0 <= k < n)
@@ -280,7 +281,7 @@ def test_negative_component2_words(mg, engine, dtype):
         say("negative words", engine, dtype, n, off, S)
         ss = mg.StreamSet(S, master_seed=1)
         ss.set_states(starts)
-        guard = 16
+        guard = 32  # 128 or 256 bytes: off = 0 leaves the rows on lines
         buf = torch.zeros(S * n + off + 2 * guard, dtype=mg.torch_dtype(dtype), device="cuda")
         ss.fill_ptr(n, dtype, mg.STREAM_MAJOR, buf.data_ptr() + (guard + off) * es)
         h = host(buf)

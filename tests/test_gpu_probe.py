@@ -27,14 +27,15 @@ def test_stream_probe_covers_every_word(mg):
     assert not h[4000:].any()
 
 
-def test_pieces_probe_geometry(mg):
+@pytest.mark.parametrize("pattern", [1, 3], ids=["two-lines", "single-lines"])
+def test_pieces_probe_geometry(mg, pattern):
     import torch
     groups = 3
     buf = torch.zeros(groups * 65536 // 4 + 32, dtype=torch.int32, device="cuda")
-    mg.write_probe(buf[:groups * 65536 // 4], 1)
+    mg.write_probe(buf[:groups * 65536 // 4], pattern)
     torch.cuda.synchronize()
     h = buf.cpu().numpy().view(np.uint32)
-    # word offset of (group, row t, member g, flush h, 16-byte column q)
+    # word offset of (group, row t, member g, piece h, 16-byte column q)
     v = h[:groups * 65536 // 4].reshape(groups, 4, 16, 8, 8, 4)
     gr, t, g, fl, q = np.meshgrid(np.arange(groups), np.arange(4), np.arange(16), np.arange(8),
                                   np.arange(8), indexing="ij")
