@@ -89,6 +89,8 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the replayed arrival trace (the whole trace is 60 s)")
     ap.add_argument("--quick", action="store_true", help="headline only (for profiling)")
+    ap.add_argument("--rows-only", action="store_true",
+                    help="only the lane-per-stream fills of short rows")
     ap.add_argument("--partitions-only", action="store_true",
                     help="only the leapfrog, random-spacing and Philox lines (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -275,6 +277,30 @@ def serving(mg, wl, seconds, speed=1.0):
     }
 
 
+def short_rows(mg, torch, stream):
+    """Stream-major fills of short rows (the lane-per-stream writer), about
+    4 GiB per launch: rows of 1000 and 1001 uint32 (off their 128-byte lines,
+    each line shared by two rows written once), 1024 and 2000 uint32, 1000
+    float64."""
+    out = {}
+    for i, (dt, n) in enumerate(((0, 1000), (0, 1001), (0, 1024), (0, 2000), (2, 1000))):
+        es = 8 if dt == 2 else 4
+        S = (1 << 30) // n if es == 4 else (1 << 29) // n
+        ss = mg.StreamSet(S, master_seed=5)
+        buf = torch.empty(S * n * es // 4, dtype=torch.int32, device="cuda")
+        # the first shape also takes the clocks out of their idle state (a
+        # burst from idle runs fast for two launches, then dips for several)
+        per, _ = timed(lambda: ss.fill_ptr(n, dt, mg.STREAM_MAJOR, buf.data_ptr()), 10,
+                       30 if i == 0 else 3, stream)
+        ms = sum(per) / len(per)
+        out["%s_rows_of_%d" % ("u32" if dt == 0 else "f64", n)] = {
+            "streams": S, "ms": round(ms, 4), "TB_s": round(S * n * es / ms / 1e9, 3)}
+        ss.close()
+        del buf
+    torch.cuda.synchronize()
+    return out
+
+
 def partitions(mg, wl, torch, stream):
     """The other partitions of sec. 2.3 and the other generators over 2^32
     uint32 (16 GiB): one stream dealt to 2^16 players x 2^16 cards (in order,
@@ -367,6 +393,11 @@ def main():
     engine = mg.mrg_config_get("engine")
     tile = mg.mrg_config_get("tile_bytes")
     stream = torch.cuda.current_stream()
+
+    if args.rows_only:
+        print("[bench] short rows", file=sys.stderr, flush=True)
+        print(json.dumps({"short_rows": short_rows(mg, torch, stream)}), flush=True)
+        return
 
     if args.partitions_only:
         print("[bench] partitions and Philox", file=sys.stderr, flush=True)
@@ -506,6 +537,7 @@ def main():
         del out3
         ss3.close()
         extra.update(partitions(mg, wl, torch, stream))
+        extra["short_rows"] = short_rows(mg, torch, stream)
     ss.close()
     torch.cuda.synchronize()
     if not args.quick and not args.no_batch:

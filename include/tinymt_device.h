@@ -41,6 +41,8 @@ struct TinyMTStream {
     uint32_t q;                // global index of the parameter set
     uint32_t mat1, mat2, tmat; // the set's parameters
     const uint32_t *rec;       // the set's record
+    // draws are exact as they come (no cheaper checked form)
+    static constexpr bool kCheckedDraws = false;
 
     // Stream i of a set whose six state planes of n_streams words start at
     // planes; records of the sets q0, q0 + 1, ...

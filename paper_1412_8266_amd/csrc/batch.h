@@ -15,6 +15,11 @@ namespace mrg {
 constexpr uint32_t kReqSubstreams = 1u;  // streams are substreams of one stream; no write-back
 constexpr uint32_t kReqWriteBack = 2u;   // store each stream's end state
 
+// Bytes each lane of a wave item generates per chunk (64 lanes per chunk):
+// the lane's start state costs one matrix-vector product per chunk, so longer
+// lane segments spend fewer instructions per sample on it.
+constexpr int kBatchLaneBytes = 1024;
+
 constexpr int kKindWave = 0;  // one wave per stream segment
 constexpr int kKindRow = 1;   // one lane per stream, 64 streams per item
 

@@ -60,7 +60,7 @@ __device__ __forceinline__ void wave_item(const BatchReq &R, uint64_t local, uns
                                           int lane, const uint32_t *m, const BatchArgs &A)
 {
     constexpr int ES = Elem<DT>::size;
-    constexpr int L = ES == 4 ? 64 : 32;  // 256 bytes per lane per chunk
+    constexpr int L = kBatchLaneBytes / ES;  // values per lane per chunk
     const bool subs = R.flags & kReqSubstreams;
     uint64_t j0, j1, q;  // streams [j0, j1), segment q of each
     if (R.spi > 1) {
@@ -111,7 +111,12 @@ __device__ __forceinline__ void row_item(const BatchReq &R, uint64_t local, unsi
         s.g.load(dummy);
     }
     if (subs) s.substream(A.table, active ? R.sub0 + j : 0);
-    rows_fill<DT, 128, G, false>(s.g, lds, lane, nrows, R.out + r0 * R.n * ES, R.n * ES, R.n);
+    unsigned char *out0 = R.out + r0 * R.n * ES;
+    if (R.n * ES >= 128 && ((uintptr_t)out0 % 128 || (R.n * ES) % 128))
+        // rows off their lines: one write per line shared by two rows
+        rows_fill_carry<DT, 128, G>(s.g, lds, lane, nrows, out0, R.n);
+    else
+        rows_fill<DT, 128, G, false>(s.g, lds, lane, nrows, out0, R.n * ES, R.n);
     if ((R.flags & kReqWriteBack) && active) s.store(A.planes, A.plane_stride, R.stream0 + j);
 }
 
@@ -120,16 +125,16 @@ __device__ __forceinline__ void row_item(const BatchReq &R, uint64_t local, unsi
 // piece straight to memory (READ_ALL = false): staging all eight pieces in an
 // array first, as the plain fill kernels do, sends that array to scratch
 // memory inside this loop.  Wave items stage two pieces per member per flush
-// (runs of two lines per store instruction, 17 KiB of LDS per wave), row
-// items one 128-byte tile per row (9 KiB).
+// (runs of two lines per store instruction), row items one 128-byte window
+// per row and its spill (rows_fill_carry): 17 KiB of LDS per wave either way.
 template <int DT, int KIND, class G>
 __global__ void __launch_bounds__(64) batch_kernel(BatchArgs A)
 {
-    __shared__ __attribute__((aligned(16))) unsigned char lds[64 * (KIND == kKindWave ? 272 : 144)];
+    __shared__ __attribute__((aligned(16))) unsigned char lds[64 * 272];
     const int lane = threadIdx.x;
-    uint32_t m[18];  // wave items: the lane's A^(lane * L), L = 256 bytes of values
+    uint32_t m[18];  // wave items: the lane's A^(lane * L), L = kBatchLaneBytes of values
     if constexpr (KIND == kKindWave) {
-        constexpr int k = lane_table(256 / Elem<DT>::size);  // L = 64 or 32 values
+        constexpr int k = lane_table(kBatchLaneBytes / Elem<DT>::size);
 #pragma unroll
         for (int i = 0; i < 18; ++i) m[i] = A.lane_tab[(k * 64 + lane) * 18 + i];
     }

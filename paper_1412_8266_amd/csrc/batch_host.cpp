@@ -77,7 +77,7 @@ void plan_batch(const mrg_request *reqs, uint64_t n, const mrg_batch_config &cfg
         const mrg_request &q = reqs[i];
         if (!q.count || !q.n_per_stream) continue;
         const uint64_t es = q.dtype == MRG_F64 ? 8 : 4;
-        const uint64_t chunk = 64 * (256 / es);  // values per wave_fill chunk
+        const uint64_t chunk = 64 * (kBatchLaneBytes / es);  // values per wave_fill chunk
         BatchReq R = {};
         R.out = (unsigned char *)q.d_out;
         R.stream0 = q.first;

@@ -250,6 +250,177 @@ __device__ __forceinline__ void rows_fill(G &g, unsigned char *lds, int lane, ui
     }
 }
 
+// rows_fill_carry: as rows_fill (one stream per lane, row r < nrows of n
+// values at out0 + r * n * ES: contiguous rows, ES-aligned, at least one line
+// long), for rows off their lines.  Every lane draws the same number of
+// values in every step whatever its row's alignment, and each line shared by
+// two rows of the wave is written once, whole.  Row r is written through
+// windows of TB bytes aligned to 128-byte lines: window k covers the row's
+// bytes [k*TB - o, k*TB - o + TB), o = the row's offset past its first line.
+// Step k draws the row's values [k*TV, k*TV + TV) into the lane's LDS row at
+// byte o (filling window k from o on and spilling o bytes into window k+1);
+// the wave then writes the lines of window k that lie wholly in their row,
+// and the spilled bytes move to the front of the LDS row for the next
+// window.  A row's first line (when o > 0) and last line (when the row ends
+// off a line) are kept in registers instead; at the end each first line is
+// written whole from the two rows that share it (the wave's first and last
+// lines only in part: their other bytes belong to the neighbouring waves).
+// With checked draws (GenF) a step whose sign check fails in some lane is
+// drawn again exactly from the state saved before it.  `lds` holds
+// 64 * (TB + 144) bytes.
+template <int DT, int TB, class G>
+__device__ __forceinline__ void rows_fill_carry(G &g, unsigned char *lds, int lane, uint64_t nrows,
+                                                unsigned char *out0, uint64_t n)
+{
+    constexpr int ES = Elem<DT>::size;
+    constexpr int TV = TB / ES;      // values per step
+    constexpr int RS = TB + 144;     // LDS row: window + spill (< 128 bytes) + pad
+    constexpr int LPR = TB / 16;     // lanes per row when writing a window
+    constexpr int RPI = 64 / LPR;    // rows per store instruction
+    constexpr int NJ = 64 / RPI;     // store instructions per window
+    static_assert(TB % 128 == 0 && TB <= 256, "windows of whole lines");
+
+    const uint64_t nb = n * ES;      // bytes per row
+    unsigned char *my_lds = lds + lane * RS;
+    // this lane's own row: offset past its first line, its last line (in
+    // line units from the first) and the row's end within that line
+    const uint32_t o_me = (uint32_t)((uintptr_t)(out0 + (uint64_t)lane * nb) & 127u);
+    const uint64_t last_me = (o_me + nb - 1) / 128;
+    const uint32_t e_me = (uint32_t)((o_me + nb) & 127u);
+    // the rows this lane writes in store instruction j of a window
+    const int chunk = lane % LPR;
+    uint64_t rbase[NJ], rlast[NJ];
+    uint32_t rflag[NJ];  // bit 0: row exists, 1: first line shared, 2: last line shared
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+        const uint64_t r = (uint64_t)(lane / LPR + RPI * j);
+        const uintptr_t row = (uintptr_t)(out0 + r * nb);
+        const uint32_t o = (uint32_t)(row & 127u);
+        rbase[j] = (uint64_t)(row - o);
+        rlast[j] = (o + nb - 1) / 128;
+        rflag[j] = (r < nrows ? 1u : 0u) | (o ? 2u : 0u) | (((o + nb) & 127u) ? 4u : 0u);
+    }
+    // this row's first and last line, kept in registers
+    uint4 f0, f1, f2, f3, f4, f5, f6, f7, l0, l1, l2, l3, l4, l5, l6, l7;
+#define MRG_LOAD_LINE(x, p)                                                                  \
+    do {                                                                                     \
+        const unsigned char *p_ = (p);                                                      \
+        x##0 = *(const uint4 *)(p_); x##1 = *(const uint4 *)(p_ + 16);                       \
+        x##2 = *(const uint4 *)(p_ + 32); x##3 = *(const uint4 *)(p_ + 48);                  \
+        x##4 = *(const uint4 *)(p_ + 64); x##5 = *(const uint4 *)(p_ + 80);                  \
+        x##6 = *(const uint4 *)(p_ + 96); x##7 = *(const uint4 *)(p_ + 112);                 \
+    } while (0)
+#define MRG_STORE_LINE(x, p)                                                                 \
+    do {                                                                                     \
+        unsigned char *p_ = (p);                                                            \
+        *(uint4 *)(p_) = x##0; *(uint4 *)(p_ + 16) = x##1;                                   \
+        *(uint4 *)(p_ + 32) = x##2; *(uint4 *)(p_ + 48) = x##3;                              \
+        *(uint4 *)(p_ + 64) = x##4; *(uint4 *)(p_ + 80) = x##5;                              \
+        *(uint4 *)(p_ + 96) = x##6; *(uint4 *)(p_ + 112) = x##7;                             \
+    } while (0)
+    const uint64_t nsteps = (n + TV - 1) / TV;
+    const uint64_t nwin = (nb + 127 + TB - 1) / TB;  // covers o + nb for any o < 128
+    for (uint64_t k = 0; k < nwin; ++k) {
+        if (k < nsteps) {
+            const uint64_t cnt = n - k * TV < (uint64_t)TV ? n - k * TV : (uint64_t)TV;
+            unsigned char *dst = my_lds + o_me;
+            if (cnt == (uint64_t)TV) {
+                if constexpr (G::kCheckedDraws) {
+                    const G saved = g;
+                    uint32_t neg = 0;
+#pragma unroll
+                    for (int q = 0; q < TB / 16; ++q) {
+                        const uint4 v = gen16<DT>(g, neg);
+                        *(uint32_t *)(dst + q * 16) = v.x;
+                        *(uint32_t *)(dst + q * 16 + 4) = v.y;
+                        *(uint32_t *)(dst + q * 16 + 8) = v.z;
+                        *(uint32_t *)(dst + q * 16 + 12) = v.w;
+                    }
+                    if (__any((int32_t)neg < 0)) {
+                        g = saved;
+#pragma unroll 1
+                        for (int q = 0; q < TB / 16; ++q) {
+                            const uint4 v = gen16<DT>(g);
+                            *(uint32_t *)(dst + q * 16) = v.x;
+                            *(uint32_t *)(dst + q * 16 + 4) = v.y;
+                            *(uint32_t *)(dst + q * 16 + 8) = v.z;
+                            *(uint32_t *)(dst + q * 16 + 12) = v.w;
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int q = 0; q < TB / 16; ++q) {
+                        const uint4 v = gen16<DT>(g);
+                        *(uint32_t *)(dst + q * 16) = v.x;
+                        *(uint32_t *)(dst + q * 16 + 4) = v.y;
+                        *(uint32_t *)(dst + q * 16 + 8) = v.z;
+                        *(uint32_t *)(dst + q * 16 + 12) = v.w;
+                    }
+                }
+            } else {
+                // the rows' last, shorter step (the same count in every lane)
+                for (uint64_t c = 0; c < cnt; ++c) put1<DT>(dst + c * ES, g);
+            }
+        }
+        __syncthreads();
+        // keep this row's first line (window 0) and last line (its window)
+        if (k == 0) MRG_LOAD_LINE(f, my_lds);
+        if (last_me * 128 / TB == k) MRG_LOAD_LINE(l, my_lds + (last_me * 128 - k * TB));
+        // the lines of window k that lie wholly in their row
+        const uint64_t wof = k * TB + (uint64_t)chunk * 16;
+        const uint64_t line = wof / 128;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+            const uint4 v = *(const uint4 *)(lds + (lane / LPR + RPI * j) * RS + chunk * 16);
+            const bool whole = (rflag[j] & 1u) && line <= rlast[j] &&
+                               !(line == 0 && (rflag[j] & 2u)) &&
+                               !(line == rlast[j] && (rflag[j] & 4u));
+            if (whole) *(uint4 *)(rbase[j] + wof) = v;
+        }
+        __syncthreads();
+        // the spill past the window becomes the front of the next one
+#pragma unroll
+        for (int q = 0; q < 8; ++q) *(uint4 *)(my_lds + q * 16) = *(const uint4 *)(my_lds + TB + q * 16);
+    }
+    // shared lines: row r's first line holds row r-1's last bytes below o_r
+    __syncthreads();
+    MRG_STORE_LINE(f, my_lds);
+    MRG_STORE_LINE(l, my_lds + 128);
+#undef MRG_LOAD_LINE
+#undef MRG_STORE_LINE
+    __syncthreads();
+    const int c16 = (lane & 7) * 16;
+#pragma unroll 1
+    for (int j = 0; j < 8; ++j) {
+        const uint64_t r = (uint64_t)(8 * j + (lane >> 3));
+        if (r >= nrows) break;
+        const uintptr_t row = (uintptr_t)(out0 + r * nb);
+        const uint32_t o = (uint32_t)(row & 127u);
+        if (!o) continue;  // the first line is the row's own, written whole
+        unsigned char *p = (unsigned char *)(row - o) + c16;
+        // dword d of this lane's 16 bytes: row r's own byte b >= o, else row r-1's
+        auto word = [&](uint32_t b) {
+            return b >= o ? *(const uint32_t *)(lds + r * RS + b)
+                          : *(const uint32_t *)(lds + (r - 1) * RS + 128 + b);
+        };
+        const uint32_t b0 = (uint32_t)c16;
+        if (r > 0 || b0 >= o) {
+            *(uint4 *)p = make_uint4(word(b0), word(b0 + 4), word(b0 + 8), word(b0 + 12));
+        } else {
+            // the wave's first row: bytes below o belong to the previous wave
+            for (uint32_t b = b0; b < b0 + 16; b += 4)
+                if (b >= o) *(uint32_t *)(p + (b - b0)) = word(b);
+        }
+    }
+    // the wave's last row ends in a line shared with the next wave's first
+    if ((uint64_t)lane == nrows - 1 && e_me) {
+        unsigned char *p = (unsigned char *)((uintptr_t)(out0 + (uint64_t)lane * nb) - o_me) +
+                           last_me * 128;
+        for (uint32_t b = 0; b < e_me; b += 4)
+            *(uint32_t *)(p + b) = *(const uint32_t *)(my_lds + 128 + b);
+    }
+}
+
 // rows_fill_short: adjacent rows shorter than a line (n * ES < 128, row r at
 // out0 + r * n * ES) are one block of nrows * n values.  Each lane stages its
 // row in LDS (row r at r * n * ES, `lds` holding 64 * 128 bytes) and the wave

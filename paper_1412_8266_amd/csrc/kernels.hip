@@ -128,7 +128,8 @@ fill_sm_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t fi
                uint64_t count, uint64_t n, unsigned char *__restrict__ out)
 {
     constexpr int ES = Elem<DT>::size;
-    __shared__ __attribute__((aligned(16))) unsigned char lds[64 * (TB + 16)];
+    // TB = 0: rows off their lines, written by rows_fill_carry in 128-byte windows
+    __shared__ __attribute__((aligned(16))) unsigned char lds[64 * (TB ? TB + 16 : 128 + 144)];
     const int lane = threadIdx.x;
     const uint64_t s0 = (uint64_t)blockIdx.x * 64;
     const uint64_t nrows = count - s0 < 64 ? count - s0 : 64;
@@ -139,10 +140,14 @@ fill_sm_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t fi
     if (active) load_state(planes, plane_stride, idx, w);
     G g;
     g.load(w);
-    if (n * ES < 128)  // the wave's rows are one block shorter than 64 lines
+    if (n * ES < 128) {  // the wave's rows are one block shorter than 64 lines
         rows_fill_short<DT, G>(g, lds, lane, nrows, out + s0 * n * ES, n);
-    else
-        rows_fill<DT, TB, G>(g, lds, lane, nrows, out + s0 * n * ES, n * ES, n);
+    } else {
+        if constexpr (TB == 0)
+            rows_fill_carry<DT, 128, G>(g, lds, lane, nrows, out + s0 * n * ES, n);
+        else
+            rows_fill<DT, TB, G>(g, lds, lane, nrows, out + s0 * n * ES, n * ES, n);
+    }
     if (active) {
         g.store(w);
         store_state(planes, plane_stride, idx, w);
@@ -406,6 +411,10 @@ static hipError_t launch_fill_g(uint32_t *planes, uint64_t plane_stride, uint64_
         else if (fl.lanes == 8 && nh == 16) MRG_COOP(8, 16);
         else return hipErrorInvalidValue;
 #undef MRG_COOP
+    } else if (tile_bytes == 0 && ((uintptr_t)out % 128 || (n * Elem<DT>::size) % 128)) {
+        // rows off their lines: one write per shared line (rows_fill_carry)
+        hipLaunchKernelGGL((fill_sm_kernel<DT, 0, G>), dim3(grid_of(count, 64)), dim3(64), 0, st,
+                           planes, plane_stride, first, count, n, o);
     } else if (tile_bytes == 256 || (tile_bytes == 0 && n * Elem<DT>::size >= 1024)) {
         hipLaunchKernelGGL((fill_sm_kernel<DT, 256, G>), dim3(grid_of(count, 64)), dim3(64), 0, st,
                            planes, plane_stride, first, count, n, o);

@@ -155,7 +155,7 @@ mrg::BatchReq to_batch_req(mrg_server s, const Req &r)
     R.dtype = (uint32_t)r.dtype;
     R.flags = mrg::kReqSubstreams;
     if (r.n * es >= 16 * 1024) {
-        const uint64_t chunk = 64 * (256 / es);
+        const uint64_t chunk = 64 * (mrg::kBatchLaneBytes / es);
         uint64_t seg = (256 * 1024) / es / chunk * chunk;
         R.seg = seg;
         R.segs = (r.n + seg - 1) / seg;

@@ -20,7 +20,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "gen_device.hpp"   // rows_fill, rows_fill_short, put1
+#include "gen_device.hpp"   // rows_fill, rows_fill_carry, rows_fill_short, put1
 #include "kernels.h"
 #include "tinymt_device.h"
 
@@ -111,7 +111,8 @@ tmt_sm_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t fir
               const uint32_t *__restrict__ records, uint64_t q0)
 {
     constexpr int ES = Elem<DT>::size;
-    __shared__ __attribute__((aligned(16))) unsigned char lds[64 * (TB + 16)];
+    // TB = 0: rows off their lines, written by rows_fill_carry in 128-byte windows
+    __shared__ __attribute__((aligned(16))) unsigned char lds[64 * (TB ? TB + 16 : 128 + 144)];
     const int lane = threadIdx.x;
     const uint64_t s0 = (uint64_t)blockIdx.x * 64;
     const uint64_t nrows = count - s0 < 64 ? count - s0 : 64;
@@ -125,10 +126,14 @@ tmt_sm_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t fir
         g.mat1 = g.mat2 = g.tmat = 0u;
         g.rec = records;
     }
-    if (n * ES < 128)  // the wave's rows are one block shorter than 64 lines
+    if (n * ES < 128) {  // the wave's rows are one block shorter than 64 lines
         rows_fill_short<DT, TinyMTStream>(g, lds, lane, nrows, out + s0 * n * ES, n);
-    else
-        rows_fill<DT, TB, TinyMTStream>(g, lds, lane, nrows, out + s0 * n * ES, n * ES, n);
+    } else {
+        if constexpr (TB == 0)
+            rows_fill_carry<DT, 128, TinyMTStream>(g, lds, lane, nrows, out + s0 * n * ES, n);
+        else
+            rows_fill<DT, TB, TinyMTStream>(g, lds, lane, nrows, out + s0 * n * ES, n * ES, n);
+    }
     if (active) g.store(planes, plane_stride, first + s0 + lane);
 }
 
@@ -175,7 +180,11 @@ hipError_t launch_tmt_fill_t(uint32_t *planes, uint64_t plane_stride, uint64_t f
     } else {
         constexpr int ES = Elem<DT>::size;
         const int tb = tile_bytes ? tile_bytes : (n * ES < 1024 ? 128 : 256);
-        if (tb == 128)
+        if (!tile_bytes && ((uintptr_t)out % 128 || (n * ES) % 128))
+            // rows off their lines: one write per shared line (rows_fill_carry)
+            hipLaunchKernelGGL((tmt_sm_kernel<DT, 0>), dim3(blocks_of(count, 64)), dim3(64), 0,
+                               st, planes, plane_stride, first, count, n, o, records, q0);
+        else if (tb == 128)
             hipLaunchKernelGGL((tmt_sm_kernel<DT, 128>), dim3(blocks_of(count, 64)), dim3(64), 0,
                                st, planes, plane_stride, first, count, n, o, records, q0);
         else

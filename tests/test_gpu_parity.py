@@ -498,6 +498,52 @@ def test_whole_chunk_writer(mg, engine_id):
             mg.mrg_config_set(k, v)
 
 
+def test_lane_writer_rows_off_lines(mg):
+    """The lane-per-stream writer for rows off their 128-byte lines (each
+    line shared by two rows written once, from both rows' lanes): row lengths
+    from one line up, offsets across a line, waves of 1 to 64 rows and
+    partial last waves, every dtype, both engines, twice in a row, inside
+    guard words (the bytes around the output belong to nobody)."""
+    import torch
+    keys = ("engine", "strategy")
+    old = [mg.mrg_config_get(k) for k in keys]
+    base = oracle.seed_from_master(128)
+    rng = np.random.default_rng(128)
+    try:
+        for engine_id in (1, 0):
+            for dt in (0, 1, 2):
+                es = 8 if dt == 2 else 4
+                lens = [128 // es, 128 // es + 1, 256 // es - 1, 256 // es, 256 // es + 1,
+                        1000, 1001, 333]
+                for n in lens:
+                    count = int(rng.choice([1, 2, 63, 64, 65, 130]))
+                    off = int(rng.integers(0, 128 // es))
+                    for k, v in zip(keys, (engine_id, 1)):
+                        mg.mrg_config_set(k, v)
+                    say("rows off lines", engine_id, dt, n, count, off)
+                    ss = mg.StreamSet(count, seed=[int(x) for x in base])
+                    st = oracle.streams(base, 0, count)
+                    guard = 64
+                    buf = torch.zeros(count * n + off + 2 * guard, dtype=mg.torch_dtype(dt),
+                                      device="cuda")
+                    for rep in range(2):
+                        buf.zero_()
+                        view = buf[guard + off:guard + off + count * n]
+                        ss.fill_ptr(n, dt, 0, view.data_ptr())
+                        h = host(buf)
+                        want, st = oracle.fill(st, n, dt)
+                        got = h[guard + off:guard + off + count * n]
+                        assert np.array_equal(got.view(np.uint8), want.reshape(-1).view(np.uint8)), \
+                            (engine_id, dt, n, count, off, rep)
+                        assert not h[:guard + off].view(np.uint8).any()
+                        assert not h[guard + off + count * n:].view(np.uint8).any()
+                    assert np.array_equal(ss.get_states(), st)
+                    ss.close()
+    finally:
+        for k, v in zip(keys, old):
+            mg.mrg_config_set(k, v)
+
+
 @pytest.mark.parametrize("gen", ["mrg32k3a", "philox"])
 def test_degenerate_calls_change_nothing(mg, gen):
     """Empty ranges, zero-length fills, zero jumps and empty deals write

@@ -46,7 +46,7 @@ def requests(rng, n_plain, max_k, max_n, sub_stream):
             break
         specs.append((first, k, n, 0, int(rng.integers(0, 3)), 0))
         first += k
-    specs.append((first, 5, 12000, 0, 0, 0))  # streams of several 16 KiB segments
+    specs.append((first, 5, 40000, 0, 0, 0))  # streams of several 64 KiB segments
     specs.append((first + 5, 0, 5, 0, 0, 0))  # empty requests are skipped
     for sub0, k, n, dt in ((7, 40, 700, 1), (1 << 40, 3, 9000, 2)):
         specs.append((sub_stream, k, n, sub0, dt, 1))
@@ -130,16 +130,16 @@ def test_noalloc_refuses_batches_beyond_the_array(mg):
     import torch
     abi = mg._abi
     stream = torch.cuda.current_stream().cuda_stream
-    # 700,000 streams of two 16 KiB segments each: 16.8 MB of staged end
-    # states, beyond the 16 MiB array
-    k, n = 700_000, 4097
+    # 210,000 one-value requests: 16.8 MB of request descriptors, beyond the
+    # 16 MiB array
+    k = 210_000
     ss = mg.StreamSet(k, master_seed=wl.MASTER_SEED)
     before = ss.get_states(0, 1000)
-    out = torch.empty((k, n), dtype=torch.uint32, device="cuda")
-    arr = abi.make_requests([(0, k, n, 0, out.data_ptr(), 0, 0)])
+    out = torch.empty(k, dtype=torch.uint32, device="cuda")
+    base = out.data_ptr()
+    arr = abi.make_requests([(i, 1, 1, 0, base + 4 * i, 0, 0) for i in range(k)])
     with pytest.raises(abi.MRGError) as e:
-        abi.mrg_batch_run_noalloc(ss.handle, arr, 1, mg.batch_config(segment_bytes=16 * 1024),
-                                  stream)
+        abi.mrg_batch_run_noalloc(ss.handle, arr, k, None, stream)
     assert e.value.status == -4  # MRG_ERANGE
     assert "scratch" in str(e.value)
     torch.cuda.synchronize()
