@@ -201,8 +201,15 @@ MRG_HD uint32_t canonf(double r, double m)
 
 MRG_HD double to_f64f(double z) { return z * NORM; }
 
-// FP32 output from an exact binary64 z in [1, m1]: through its uint32 value.
-MRG_HD float to_f32f(double z) { return to_f32((uint32_t)z); }
+// FP32 output from an exact binary64 z in [1, m1]: k = (z - 1) >> 9 taken as
+// the truncated conversion of (z - 1) * 2^-9 (exact: at most 32 significant
+// bits), then as to_f32.  The same value as to_f32((uint32_t)z), one
+// instruction fewer.
+MRG_HD float to_f32f(double z)
+{
+    const uint32_t k = (uint32_t)__builtin_fma(z, 0x1p-9, -0x1p-9);
+    return __builtin_bit_cast(float, 0x3F800000u | k) - 0x1.fffffep-1f;
+}
 
 // ---------------------------------------------------------------------------
 // SplitMix64 (Steele, Lea & Flood, OOPSLA 2014): the state advances by a fixed

@@ -1,5 +1,5 @@
 // Descriptors of the persistent batch kernels and the grouping of requests
-// into per-(dtype, kind) launches (shared by batch.hip, the planner in
+// into launch groups (shared by batch.hip, the planner in
 // batch_host.cpp and the server in serve.cpp).
 #pragma once
 #include <hip/hip_runtime.h>
@@ -20,8 +20,14 @@ constexpr uint32_t kReqWriteBack = 2u;   // store each stream's end state
 // lane segments spend fewer instructions per sample on it.
 constexpr int kBatchLaneBytes = 1024;
 
-constexpr int kKindWave = 0;  // one wave per stream segment
-constexpr int kKindRow = 1;   // one lane per stream, 64 streams per item
+// Launch kinds.  kKindWave: wave items of one dtype.  kKindRows: the row
+// items of every dtype (one lane per stream, up to 64 streams per item),
+// largest first, then the wave items of one dtype, in one persistent launch:
+// row items are too few and too uneven to fill the chip on their own (a
+// stream of up to 16 KiB per lane), and the wave items that follow them fill
+// the slots their tail leaves idle.
+constexpr int kKindWave = 0;
+constexpr int kKindRows = 1;
 
 // One request as the kernel sees it.  seg > 0: wave items, one per segment of
 // seg values of one stream (segs per stream), or, when a stream fits one
@@ -61,27 +67,27 @@ struct BatchArgs {
     uint32_t n_cb;
     uint32_t pad;
     uint64_t cb_slots;
-    // completion stamps (all NULL: none): per request of the group, items
-    // finished and the wall clock when its last item ended; the earliest
-    // workgroup start of the run
-    unsigned long long *req_cnt;
+    // completion stamps (both NULL: none): per request of the group, the
+    // latest wall clock at which one of its items ended (a max over items);
+    // the earliest workgroup start of the run
     unsigned long long *req_done;
     unsigned long long *t_start;
 };
 
-inline int kind_of(const BatchReq &R) { return R.seg ? kKindWave : kKindRow; }
+__host__ __device__ inline bool is_row(const BatchReq &R) { return R.seg == 0; }
 inline uint64_t items_of(const BatchReq &R)
 {
     if (!R.seg) return (R.k + 63) / 64;
     return R.spi > 1 ? (R.k + R.spi - 1) / R.spi : R.k * R.segs;
 }
 
-// Requests reordered into (dtype, kind) groups, each with its own item
-// prefix; built on the host, uploaded as one request array and one prefix
-// array.
+// Requests reordered into launch groups, each with its own item prefix:
+// one per dtype with wave items, the first launched (least output) led by the
+// row items of every dtype (kKindRows; alone when no request has wave items);
+// built on the host, uploaded as one request array and one prefix array.
 struct Grouped {
     struct Group {
-        int dtype, kind;
+        int dtype, kind;  // kKindRows: dtype is the wave items' (rows carry their own)
         uint32_t req_off, nreq;  // slice of `reqs`
         uint32_t prefix_off;     // slice of `prefix` (nreq + 1 entries)
         uint64_t items;
@@ -125,8 +131,8 @@ hipError_t launch_grouped(const Grouped &g, const BatchReq *d_reqs, const uint64
 hipError_t launch_batch_group(const BatchArgs &A, int dtype, int kind, unsigned grid, int engine,
                               hipStream_t st);
 hipError_t launch_copyback(const BatchArgs &A, hipStream_t st);
-// Zero n request counters and set the start stamp to its maximum (before a run).
-hipError_t launch_stamp_reset(unsigned long long *req_cnt, uint64_t n, unsigned long long *t_start,
+// Zero n completion stamps and set the start stamp to its maximum (before a run).
+hipError_t launch_stamp_reset(unsigned long long *req_done, uint64_t n, unsigned long long *t_start,
                               hipStream_t st);
 
 }  // namespace mrg

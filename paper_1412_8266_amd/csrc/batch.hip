@@ -7,7 +7,9 @@
 //     state is the stream's state jumped by v0 with the windowed tables
 //     (sequence splitting inside a stream, sec. 2.3);
 //   - a row item is up to 64 streams of a short-stream request, one per lane,
-//     written with rows_fill.
+//     written with rows_fill or rows_fill_carry.
+// One launch per group (batch.h): wave items of one dtype, or the row items
+// of every dtype, largest first, followed by the wave items of one dtype.
 // Persistent workgroups (one wave each) claim items from a global counter or
 // take them round robin; item i belongs to the request r with
 // prefix[r] <= i < prefix[r+1].  A request in substream mode draws its streams
@@ -112,7 +114,10 @@ __device__ __forceinline__ void row_item(const BatchReq &R, uint64_t local, unsi
     }
     if (subs) s.substream(A.table, active ? R.sub0 + j : 0);
     unsigned char *out0 = R.out + r0 * R.n * ES;
-    if (R.n * ES >= 128 && ((uintptr_t)out0 % 128 || (R.n * ES) % 128))
+    if (R.n * ES < 128)
+        // the item's rows are one block shorter than 64 lines
+        rows_fill_short<DT, G>(s.g, lds, lane, nrows, out0, R.n);
+    else if ((uintptr_t)out0 % 128 || (R.n * ES) % 128)
         // rows off their lines: one write per line shared by two rows
         rows_fill_carry<DT, 128, G>(s.g, lds, lane, nrows, out0, R.n);
     else
@@ -120,32 +125,39 @@ __device__ __forceinline__ void row_item(const BatchReq &R, uint64_t local, unsi
     if ((R.flags & kReqWriteBack) && active) s.store(A.planes, A.plane_stride, R.stream0 + j);
 }
 
-// One persistent kernel per (dtype, kind) group keeps each instantiation's
-// register use at that of the plain fill kernels.  The writers move each LDS
+// One persistent kernel per group: wave items of dtype DT, led in the first
+// group (KIND = kKindRows) by the row items of every dtype.  The writers move each LDS
 // piece straight to memory (READ_ALL = false): staging all eight pieces in an
 // array first, as the plain fill kernels do, sends that array to scratch
 // memory inside this loop.  Wave items stage two pieces per member per flush
 // (runs of two lines per store instruction), row items one 128-byte window
 // per row and its spill (rows_fill_carry): 17 KiB of LDS per wave either way.
 template <int DT, int KIND, class G>
-__global__ void __launch_bounds__(64) batch_kernel(BatchArgs A)
+__global__ void __launch_bounds__(64, 2) batch_kernel(BatchArgs A)
 {
     __shared__ __attribute__((aligned(16))) unsigned char lds[64 * 272];
     const int lane = threadIdx.x;
-    uint32_t m[18];  // wave items: the lane's A^(lane * L), L = kBatchLaneBytes of values
+    // wave items: the lane's A^(lane * L), L = kBatchLaneBytes of values, held
+    // for the whole launch when every item is a wave item, else loaded per
+    // wave item (a row item's writer needs those registers)
+    constexpr int kt = lane_table(kBatchLaneBytes / Elem<DT>::size);
+    const uint32_t *mt = A.lane_tab + (kt * 64 + lane) * 18;
+    uint32_t m[18];
     if constexpr (KIND == kKindWave) {
-        constexpr int k = lane_table(kBatchLaneBytes / Elem<DT>::size);
 #pragma unroll
-        for (int i = 0; i < 18; ++i) m[i] = A.lane_tab[(k * 64 + lane) * 18 + i];
+        for (int i = 0; i < 18; ++i) m[i] = mt[i];
     }
     if (A.t_start && lane == 0) atomicMin(A.t_start, (unsigned long long)wall_clock64());
     uint64_t next = blockIdx.x;  // static schedule: blockIdx.x + t * gridDim.x
+    // dynamic schedule: a wave claims its next item as it starts the current
+    // one, so that the claim's round trip overlaps the item's own loads
+    uint64_t claim = 0;
+    if (A.dynamic && lane == 0) claim = atomicAdd(A.counter, 1ull);
     for (;;) {
         uint64_t item;
         if (A.dynamic) {
-            uint64_t mine = 0;
-            if (lane == 0) mine = atomicAdd(A.counter, 1ull);
-            item = lane0_uniform(mine);
+            item = lane0_uniform(claim);
+            if (item < A.total_items && lane == 0) claim = atomicAdd(A.counter, 1ull);
         } else {
             item = next;
             next += gridDim.x;
@@ -154,22 +166,27 @@ __global__ void __launch_bounds__(64) batch_kernel(BatchArgs A)
         const uint32_t r = find_req(A.prefix, A.nreq, item, lane);
         const BatchReq R = A.reqs[r];
         const uint64_t local = item - A.prefix[r];
-        if constexpr (KIND == kKindWave) wave_item<DT, G>(R, local, lds, lane, m, A);
-        else row_item<DT, G>(R, local, lds, lane, A);
-        if (A.req_cnt && lane == 0) {
-            const unsigned long long done = atomicAdd(&A.req_cnt[r], 1ull) + 1ull;
-            if (done == A.prefix[r + 1] - A.prefix[r])
-                A.req_done[r] = (unsigned long long)wall_clock64();
-        }
+        if constexpr (KIND == kKindWave) {
+            wave_item<DT, G>(R, local, lds, lane, m, A);
+        } else if (!is_row(R)) {
+            uint32_t mi[18];
+#pragma unroll
+            for (int i = 0; i < 18; ++i) mi[i] = mt[i];
+            wave_item<DT, G>(R, local, lds, lane, mi, A);
+        } else if (R.dtype == 0) row_item<0, G>(R, local, lds, lane, A);
+        else if (R.dtype == 1) row_item<1, G>(R, local, lds, lane, A);
+        else row_item<2, G>(R, local, lds, lane, A);
+        // no value returned: the item's end costs no round trip
+        if (A.req_done && lane == 0) atomicMax(&A.req_done[r], (unsigned long long)wall_clock64());
     }
 }
 
-__global__ void __launch_bounds__(256) batch_stamp_reset_kernel(unsigned long long *req_cnt,
+__global__ void __launch_bounds__(256) batch_stamp_reset_kernel(unsigned long long *req_done,
                                                                 uint64_t n,
                                                                 unsigned long long *t_start)
 {
     const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) req_cnt[i] = 0ull;
+    if (i < n) req_done[i] = 0ull;
     if (i == 0) *t_start = ~0ull;
 }
 
@@ -210,9 +227,9 @@ static void launch_group_g(const BatchArgs &A, int dtype, int kind, unsigned gri
         else if (dtype == 1) hipLaunchKernelGGL((batch_kernel<1, kKindWave, G>), g, b, 0, st, A);
         else hipLaunchKernelGGL((batch_kernel<2, kKindWave, G>), g, b, 0, st, A);
     } else {
-        if (dtype == 0) hipLaunchKernelGGL((batch_kernel<0, kKindRow, G>), g, b, 0, st, A);
-        else if (dtype == 1) hipLaunchKernelGGL((batch_kernel<1, kKindRow, G>), g, b, 0, st, A);
-        else hipLaunchKernelGGL((batch_kernel<2, kKindRow, G>), g, b, 0, st, A);
+        if (dtype == 0) hipLaunchKernelGGL((batch_kernel<0, kKindRows, G>), g, b, 0, st, A);
+        else if (dtype == 1) hipLaunchKernelGGL((batch_kernel<1, kKindRows, G>), g, b, 0, st, A);
+        else hipLaunchKernelGGL((batch_kernel<2, kKindRows, G>), g, b, 0, st, A);
     }
 }
 
@@ -225,12 +242,12 @@ hipError_t launch_batch_group(const BatchArgs &A, int dtype, int kind, unsigned 
     return hipGetLastError();
 }
 
-hipError_t launch_stamp_reset(unsigned long long *req_cnt, uint64_t n, unsigned long long *t_start,
+hipError_t launch_stamp_reset(unsigned long long *req_done, uint64_t n, unsigned long long *t_start,
                               hipStream_t st)
 {
     const uint64_t blocks = (n + 255) / 256;
     hipLaunchKernelGGL(batch_stamp_reset_kernel, dim3((unsigned)(blocks ? blocks : 1)), dim3(256), 0,
-                       st, req_cnt, n, t_start);
+                       st, req_done, n, t_start);
     return hipGetLastError();
 }
 

@@ -24,44 +24,52 @@ void group_requests(const std::vector<BatchReq> &in, Grouped *out)
     out->groups.clear();
     out->pos.assign(in.size(), 0);
     out->total_items = 0;
-    for (int dtype = 0; dtype < 3; ++dtype)
-        for (int kind = 0; kind < 2; ++kind) {
-            Grouped::Group g = {dtype, kind, (uint32_t)out->reqs.size(), 0,
-                                (uint32_t)out->prefix.size(), 0};
-            out->prefix.push_back(0);
-            for (size_t i = 0; i < in.size(); ++i) {
-                if ((int)in[i].dtype != dtype || kind_of(in[i]) != kind) continue;
-                out->pos[i] = (uint32_t)out->reqs.size();
-                out->reqs.push_back(in[i]);
-                g.items += items_of(in[i]);
-                out->prefix.push_back(g.items);
-                ++g.nreq;
-            }
-            if (g.nreq) {
-                out->groups.push_back(g);
-                out->total_items += g.items;
-            } else {
-                out->prefix.pop_back();
-            }
-        }
-    // launch the groups with the least output first (shortest-job-first
-    // keeps the completion times of most requests low; the run's end does
-    // not move)
-    std::vector<uint64_t> bytes(out->groups.size(), 0);
-    for (size_t i = 0; i < out->groups.size(); ++i) {
-        const Grouped::Group &G = out->groups[i];
-        for (uint32_t r = G.req_off; r < G.req_off + G.nreq; ++r) {
-            const BatchReq &R = out->reqs[r];
-            bytes[i] += R.k * R.n * (R.dtype == 2 ? 8 : 4);
+    // wave requests by dtype, in input order, and their output bytes
+    std::vector<size_t> wave[3], rows;
+    uint64_t bytes[3] = {0, 0, 0};
+    for (size_t i = 0; i < in.size(); ++i) {
+        const BatchReq &R = in[i];
+        if (is_row(R)) {
+            rows.push_back(i);
+        } else {
+            wave[R.dtype].push_back(i);
+            bytes[R.dtype] += R.k * R.n * (R.dtype == 2 ? 8 : 4);
         }
     }
-    std::vector<size_t> order(out->groups.size());
-    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](size_t a, size_t b) { return bytes[a] < bytes[b]; });
-    std::vector<Grouped::Group> sorted;
-    for (size_t i : order) sorted.push_back(out->groups[i]);
-    out->groups.swap(sorted);
+    // row items largest first: a row item is up to 64 whole streams on one
+    // wave (up to 64 x 16 KiB), claimed in this order; big ones left for the
+    // end would run the launch's tail alone
+    std::stable_sort(rows.begin(), rows.end(), [&](size_t a, size_t b) {
+        return std::min<uint64_t>(in[a].k, 64) * in[a].n * (in[a].dtype == 2 ? 8 : 4) >
+               std::min<uint64_t>(in[b].k, 64) * in[b].n * (in[b].dtype == 2 ? 8 : 4);
+    });
+    // wave groups with the least output first (shortest-job-first keeps the
+    // completion times of most requests low; the run's end does not move)
+    std::vector<int> order;
+    for (int d = 0; d < 3; ++d)
+        if (!wave[d].empty()) order.push_back(d);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return bytes[a] < bytes[b]; });
+    if (order.empty() && !rows.empty()) order.push_back(-1);  // rows alone
+    for (size_t gi = 0; gi < order.size(); ++gi) {
+        const int d = order[gi];
+        const bool lead = gi == 0 && !rows.empty();
+        Grouped::Group g = {d < 0 ? 0 : d, lead ? kKindRows : kKindWave,
+                            (uint32_t)out->reqs.size(), 0, (uint32_t)out->prefix.size(), 0};
+        out->prefix.push_back(0);
+        auto add = [&](size_t i) {
+            out->pos[i] = (uint32_t)out->reqs.size();
+            out->reqs.push_back(in[i]);
+            g.items += items_of(in[i]);
+            out->prefix.push_back(g.items);
+            ++g.nreq;
+        };
+        if (lead)
+            for (size_t i : rows) add(i);
+        if (d >= 0)
+            for (size_t i : wave[d]) add(i);
+        out->groups.push_back(g);
+        out->total_items += g.items;
+    }
 }
 
 void plan_batch(const mrg_request *reqs, uint64_t n, const mrg_batch_config &cfg, HostPlan *out)
@@ -126,8 +134,7 @@ hipError_t launch_grouped(const Grouped &g, const BatchReq *d_reqs, const uint64
         A.nreq = G.nreq;
         A.total_items = G.items;
         A.counter = d_counters + i;
-        if (base.req_cnt) {
-            A.req_cnt = base.req_cnt + G.req_off;
+        if (base.req_done) {
             A.req_done = base.req_done + G.req_off;
         }
         const unsigned grid = (unsigned)std::max<uint64_t>(1, std::min(grid_cap, G.items));
@@ -157,7 +164,7 @@ struct mrg_batch_s {
     uint64_t *d_solo = nullptr;      // [nreq][2]: {0, items of request r}
     uint64_t *d_cb = nullptr;        // cb_prefix | cb_stream0 | cb_scratch0
     unsigned long long *d_counter = nullptr;  // one per group
-    unsigned long long *d_stamps = nullptr;   // [nreq] counts | [nreq] done stamps | start
+    unsigned long long *d_stamps = nullptr;   // [nreq] done stamps | start
     uint32_t *d_scratch = nullptr;
     uint64_t grid_cap = 0;
 
@@ -237,7 +244,7 @@ mrg_status build_plan(mrg_batch b)
     if ((st = upload(&b->d_cb, cb, "batch copy-back"))) return st;
     hipError_t e = hipMalloc((void **)&b->d_counter, 6 * sizeof(unsigned long long));
     if (e != hipSuccess) return set_error(MRG_ENOMEM, "hipMalloc(counters)");
-    e = hipMalloc((void **)&b->d_stamps, (2 * b->plan.reqs.size() + 1) * sizeof(unsigned long long));
+    e = hipMalloc((void **)&b->d_stamps, (b->plan.reqs.size() + 1) * sizeof(unsigned long long));
     if (e != hipSuccess) return set_error(MRG_ENOMEM, "hipMalloc(completion stamps)");
     if (b->scratch_slots) {
         e = hipMalloc((void **)&b->d_scratch, 6 * b->scratch_slots * sizeof(uint32_t));
@@ -266,16 +273,15 @@ mrg::BatchArgs base_args(mrg_batch b)
     A.n_cb = ncb;
     A.cb_slots = b->cb_prefix.back();
     const uint64_t nr = b->plan.reqs.size();
-    A.req_cnt = b->d_stamps;
-    A.req_done = b->d_stamps + nr;
-    A.t_start = b->d_stamps + 2 * nr;
+    A.req_done = b->d_stamps;
+    A.t_start = b->d_stamps + nr;
     return A;
 }
 
 hipError_t launch_all(mrg_batch b, hipStream_t st)
 {
     const mrg::BatchArgs A = base_args(b);
-    hipError_t e = mrg::launch_stamp_reset(A.req_cnt, b->plan.reqs.size(), A.t_start, st);
+    hipError_t e = mrg::launch_stamp_reset(A.req_done, b->plan.reqs.size(), A.t_start, st);
     if (e != hipSuccess) return e;
     e = mrg::launch_grouped(b->plan, b->d_reqs, b->d_prefix, b->d_counter, A,
                                        b->grid_cap, b->engine, st);
@@ -449,11 +455,12 @@ mrg_status mrg_batch_run_per_request(mrg_batch b, void *stream)
             A.nreq = 1;
             A.total_items = mrg::items_of(R);
             A.counter = b->d_counter;
-            A.req_cnt = A.req_done = A.t_start = nullptr;  // stamps belong to batch runs
+            A.req_done = A.t_start = nullptr;  // stamps belong to batch runs
             const unsigned grid =
                 (unsigned)std::max<uint64_t>(1, std::min(b->grid_cap, A.total_items));
-            hipError_t e = mrg::launch_batch_group(A, (int)R.dtype, mrg::kind_of(R), grid,
-                                                   b->engine, (hipStream_t)stream);
+            hipError_t e = mrg::launch_batch_group(
+                A, (int)R.dtype, mrg::is_row(R) ? mrg::kKindRows : mrg::kKindWave, grid, b->engine,
+                (hipStream_t)stream);
             st = e == hipSuccess ? MRG_OK : hip_error(e, "batch kernel launch");
         } else {
             st = mrg_fill(b->ss, q.first, q.count, q.n_per_stream, (mrg_dtype)q.dtype,
@@ -468,7 +475,7 @@ mrg_status mrg_batch_request_times(mrg_batch b, void *stream, double *h_ms)
 {
     if (!b || !h_ms) return set_error(MRG_EINVAL, "null argument");
     const size_t nr = b->plan.reqs.size();
-    std::vector<unsigned long long> st(2 * nr + 1);
+    std::vector<unsigned long long> st(nr + 1);
     hipError_t e = hipStreamSynchronize((hipStream_t)stream);
     if (e == hipSuccess)
         e = hipMemcpy(st.data(), b->d_stamps, st.size() * sizeof(unsigned long long),
@@ -478,9 +485,9 @@ mrg_status mrg_batch_request_times(mrg_batch b, void *stream, double *h_ms)
     if (e != hipSuccess) return hip_error(e, "reading completion stamps");
     if (khz <= 0) return set_error(MRG_EHIP, "no wall clock rate");
     for (size_t i = 0; i < b->reqs.size(); ++i) h_ms[i] = 0.0;
-    const unsigned long long t0 = st[2 * nr];
+    const unsigned long long t0 = st[nr];
     for (size_t r = 0; r < b->req_of.size(); ++r) {
-        const unsigned long long t = st[nr + b->plan.pos[r]];
+        const unsigned long long t = st[b->plan.pos[r]];
         h_ms[b->req_of[r]] = t >= t0 ? (double)(t - t0) / (double)khz : 0.0;
     }
     return MRG_OK;

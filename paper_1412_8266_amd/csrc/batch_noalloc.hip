@@ -128,7 +128,7 @@ mrg_status mrg_batch_run_noalloc(mrg_streamset ss, const mrg_request *reqs, uint
     A.cb_scratch0 = A.cb_prefix + (2 * ncb + 1);
     A.n_cb = (uint32_t)ncb;
     A.cb_slots = P.cb_prefix.back();
-    A.req_cnt = A.req_done = A.t_start = nullptr;  // no completion stamps
+    A.req_done = A.t_start = nullptr;  // no completion stamps
     const uint64_t grid_cap = (uint64_t)tabs.cus * c.waves_per_cu;
     e = mrg::launch_grouped(P.plan, (const mrg::BatchReq *)d, (const uint64_t *)(d + o_prefix),
                             (unsigned long long *)(d + o_cnt), A, grid_cap,

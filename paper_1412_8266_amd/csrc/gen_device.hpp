@@ -208,8 +208,22 @@ __device__ __forceinline__ void rows_fill(G &g, unsigned char *lds, int lane, ui
     const uint64_t ntiles = n / TV;
     for (uint64_t t = 0; t < ntiles; ++t) {
         if (t < nfull) {
+            if constexpr (G::kCheckedDraws) {
+                // checked draws; the whole tile again, exactly, when a lane's
+                // check fails (rare: the same rule as in wave_fill)
+                const G saved = g;
+                uint32_t neg = 0;
 #pragma unroll
-            for (int c = 0; c < TB / 16; ++c) *(uint4 *)(my_lds + c * 16) = gen16<DT>(g);
+                for (int c = 0; c < TB / 16; ++c) *(uint4 *)(my_lds + c * 16) = gen16<DT>(g, neg);
+                if (__any((int32_t)neg < 0)) {
+                    g = saved;
+#pragma unroll 1
+                    for (int c = 0; c < TB / 16; ++c) *(uint4 *)(my_lds + c * 16) = gen16<DT>(g);
+                }
+            } else {
+#pragma unroll
+                for (int c = 0; c < TB / 16; ++c) *(uint4 *)(my_lds + c * 16) = gen16<DT>(g);
+            }
         }
         __syncthreads();
         const uint64_t off = t * TB;
@@ -282,11 +296,10 @@ __device__ __forceinline__ void rows_fill_carry(G &g, unsigned char *lds, int la
 
     const uint64_t nb = n * ES;      // bytes per row
     unsigned char *my_lds = lds + lane * RS;
-    // this lane's own row: offset past its first line, its last line (in
-    // line units from the first) and the row's end within that line
+    // this lane's own row: offset past its first line and its last line (in
+    // line units from the first)
     const uint32_t o_me = (uint32_t)((uintptr_t)(out0 + (uint64_t)lane * nb) & 127u);
     const uint64_t last_me = (o_me + nb - 1) / 128;
-    const uint32_t e_me = (uint32_t)((o_me + nb) & 127u);
     // the rows this lane writes in store instruction j of a window
     const int chunk = lane % LPR;
     uint64_t rbase[NJ], rlast[NJ];
@@ -389,35 +402,54 @@ __device__ __forceinline__ void rows_fill_carry(G &g, unsigned char *lds, int la
 #undef MRG_LOAD_LINE
 #undef MRG_STORE_LINE
     __syncthreads();
+    // 16 bytes per lane of each shared first line, 8 lanes per line, 8 rows
+    // per step, four steps at a time: their LDS reads first, then the stores
     const int c16 = (lane & 7) * 16;
 #pragma unroll 1
-    for (int j = 0; j < 8; ++j) {
-        const uint64_t r = (uint64_t)(8 * j + (lane >> 3));
-        if (r >= nrows) break;
-        const uintptr_t row = (uintptr_t)(out0 + r * nb);
-        const uint32_t o = (uint32_t)(row & 127u);
-        if (!o) continue;  // the first line is the row's own, written whole
-        unsigned char *p = (unsigned char *)(row - o) + c16;
-        // dword d of this lane's 16 bytes: row r's own byte b >= o, else row r-1's
-        auto word = [&](uint32_t b) {
-            return b >= o ? *(const uint32_t *)(lds + r * RS + b)
-                          : *(const uint32_t *)(lds + (r - 1) * RS + 128 + b);
-        };
-        const uint32_t b0 = (uint32_t)c16;
-        if (r > 0 || b0 >= o) {
-            *(uint4 *)p = make_uint4(word(b0), word(b0 + 4), word(b0 + 8), word(b0 + 12));
-        } else {
-            // the wave's first row: bytes below o belong to the previous wave
-            for (uint32_t b = b0; b < b0 + 16; b += 4)
-                if (b >= o) *(uint32_t *)(p + (b - b0)) = word(b);
+    for (int h = 0; h < 8; h += 4) {
+        uint4 sv[4];
+        uint32_t so[4];  // the row's o (0: nothing to write: first line whole, or no row)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint64_t r = (uint64_t)(8 * (h + j) + (lane >> 3));
+            so[j] = r < nrows ? (uint32_t)((uintptr_t)(out0 + r * nb) & 127u) : 0u;
+            // dword d: row r's own byte b >= o, else row r-1's last line (row
+            // 0 reads its own window there and never writes those bytes)
+            const uint32_t own = (uint32_t)r * RS, prev = r ? own - RS + 128 : own;
+            uint32_t w[4];
+#pragma unroll
+            for (int d = 0; d < 4; ++d) {
+                const uint32_t b = (uint32_t)c16 + 4 * d;
+                w[d] = *(const uint32_t *)(lds + (b >= so[j] ? own : prev) + b);
+            }
+            sv[j] = make_uint4(w[0], w[1], w[2], w[3]);
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            if (!so[j]) continue;
+            const uint64_t r = (uint64_t)(8 * (h + j) + (lane >> 3));
+            unsigned char *p = (unsigned char *)((uintptr_t)(out0 + r * nb) - so[j]) + c16;
+            if (r > 0 || (uint32_t)c16 >= so[j]) {
+                *(uint4 *)p = sv[j];
+            } else {
+                // the wave's first row: bytes below o belong to the previous wave
+                const uint32_t w[4] = {sv[j].x, sv[j].y, sv[j].z, sv[j].w};
+#pragma unroll
+                for (int d = 0; d < 4; ++d)
+                    if ((uint32_t)c16 + 4 * d >= so[j]) *(uint32_t *)(p + 4 * d) = w[d];
+            }
         }
     }
-    // the wave's last row ends in a line shared with the next wave's first
-    if ((uint64_t)lane == nrows - 1 && e_me) {
-        unsigned char *p = (unsigned char *)((uintptr_t)(out0 + (uint64_t)lane * nb) - o_me) +
-                           last_me * 128;
-        for (uint32_t b = 0; b < e_me; b += 4)
-            *(uint32_t *)(p + b) = *(const uint32_t *)(my_lds + 128 + b);
+    // the wave's last row ends in a line shared with the next wave's first:
+    // its bytes there as dwords, one per lane
+    {
+        const uint64_t rl = nrows - 1;
+        const uintptr_t row = (uintptr_t)(out0 + rl * nb);
+        const uint32_t ol = (uint32_t)(row & 127u), el = (uint32_t)((ol + nb) & 127u);
+        if ((uint32_t)lane * 4 < el) {
+            unsigned char *p = (unsigned char *)(row - ol) + (ol + nb - 1) / 128 * 128;
+            *(uint32_t *)(p + 4 * lane) = *(const uint32_t *)(lds + (uint32_t)rl * RS + 128 + 4 * lane);
+        }
     }
 }
 

@@ -9,7 +9,7 @@
 // in arrival order within two size classes (large requests queue apart and
 // run on their own quarter of the HIP streams) while the output arena has room
 // (first fit), launches each
-// admitted group ("tick": one persistent batch kernel per dtype and item kind)
+// admitted group ("tick": one persistent batch kernel per launch group, batch.h)
 // on the next of several HIP streams -- ticks overlap on the device -- and
 // retires ticks by polling their completion events.  Latency is measured from submission to the
 // moment the scheduler observes the tick's event complete.
@@ -104,7 +104,7 @@ struct Slot {  // one tick in flight
     hipEvent_t done = nullptr;
     mrg::BatchReq *d_reqs = nullptr;
     uint64_t *d_prefix = nullptr;
-    unsigned long long *d_counter = nullptr;  // one per (dtype, kind) group
+    unsigned long long *d_counter = nullptr;  // one per launch group (at most 3)
     mrg::BatchReq *h_reqs = nullptr;  // pinned staging
     uint64_t *h_prefix = nullptr;
     std::vector<Req> reqs;
@@ -169,7 +169,7 @@ mrg::BatchReq to_batch_req(mrg_server s, const Req &r)
 }
 
 // Launch the admitted requests of `slot` (scheduler thread): one persistent
-// kernel per (dtype, kind) group, all on the slot's stream.
+// kernel per launch group, all on the slot's stream.
 mrg_status launch_tick(mrg_server s, Slot &slot)
 {
     std::vector<mrg::BatchReq> in(slot.reqs.size());
