@@ -40,10 +40,10 @@ METRIC = "uint32 Gsamples/s (% HBM write roofline), batched vs plain; p50/p99 la
 # (SQ_INSTS_VALU).  They are reported only while the sources still hash the
 # same; after any change to the kernel they read null until profiled again.
 COUNTERS = {
-    "traffic": 17230900255,
-    "valu_insts": 1079772000,
+    "traffic": 17230995168,
+    "valu_insts": 1079772685,
     "source": "profiles/fill_coop_u32_16lanes_2p20x4096.md",
-    "kernel_sources_sha256": "1f47c8ee9407961036259dd34ff3d450e069ebfc4e91befebc002362ff17b17b",
+    "kernel_sources_sha256": "a3441d3951b741250b1eb38c2cc693bb7c7dd1bf240597f6ce0876ec484bd00c",
 }
 KERNEL_SOURCES = ["include/mrg_arith.hpp", "include/mrg32k3a_device.h",
                   "paper_1412_8266_amd/csrc/gen_device.hpp", "paper_1412_8266_amd/csrc/kernels.hip",
@@ -203,9 +203,27 @@ def batched(mg, wl, torch, stream, reps):
     info = b.info()
     per_b, _ = timed(lambda: b.run(), reps, 1, stream)
     import numpy as np
-    done = b.request_times()  # of the last graph run
-    done = np.sort(done[req.samples() > 0])
+    done_all = b.request_times()  # of the last graph run
+    done = np.sort(done_all[req.samples() > 0])
+    # the row items (streams shorter than wave_min_bytes, one lane each) lead
+    # the first launch; when the last of them ended, from the run's start
+    row = (nbytes // np.maximum(req.n_streams, 1) < info["wave_min_bytes"]) & (req.samples() > 0)
+    row_bytes = int(nbytes[row].sum())
+    row_done = float(done_all[row].max()) if row.any() else 0.0
     per_r, _ = timed(lambda: b.run_per_request(), reps, 1, stream)
+    # the same row requests as a batch of their own (one launch of row items
+    # only), under the chosen plan
+    alone = None
+    if row.any():
+        cfg = mg.batch_config(segment_bytes=info["segment_bytes"],
+                              wave_min_bytes=info["wave_min_bytes"],
+                              waves_per_cu=info["waves_per_cu"], schedule=info["schedule"])
+        br = mg.Batch(ss, [rows[i] for i in np.nonzero(row)[0]], cfg)
+        per_a, _ = timed(lambda: br.run(), 5, 2, stream)
+        ms_a = sum(per_a) / len(per_a)
+        alone = {"ms": round(ms_a, 4), "items": br.info()["items"],
+                 "TB_s": round(row_bytes / ms_a / 1e9, 3)}
+        br.close()
     ms_b = sum(per_b) / len(per_b)
     ms_r = sum(per_r) / len(per_r)
     samples = info["samples"]
@@ -226,6 +244,12 @@ def batched(mg, wl, torch, stream, reps):
                                   "p99": round(float(done[int(0.99 * len(done))]), 3),
                                   "max": round(float(done[-1]), 3)},
         "batched_hbm_frac": round(info["bytes"] / ms_b / 1e6 / HBM_PEAK_GBS, 4),
+        # bytes of the row items over the time their last one ended: a lower
+        # bound on their rate (wave items run beside them at the end)
+        "row_items": {"requests": int(row.sum()), "bytes": row_bytes,
+                      "done_ms": round(row_done, 3),
+                      "TB_s_lower_bound": round(row_bytes / row_done / 1e9, 3) if row_done else None,
+                      "alone": alone},
         "autotune": {"chosen": {"segment_bytes": info["segment_bytes"],
                                 "wave_min_bytes": info["wave_min_bytes"],
                                 "waves_per_cu": info["waves_per_cu"],
