@@ -31,8 +31,8 @@ constexpr int kKindRows = 1;
 
 // One request as the kernel sees it.  seg > 0: wave items, one per segment of
 // seg values of one stream (segs per stream), or, when a stream fits one
-// segment, one per spi consecutive whole streams; seg == 0: row items of up
-// to 64 streams.
+// segment, one per spi consecutive whole streams; seg == 0: row items of spi
+// consecutive blocks of up to 64 streams each.
 struct BatchReq {
     unsigned char *out;  // [k, n] stream-major output of dtype elements
     uint64_t stream0;    // plane index of stream 0 (substream mode: of the one stream)
@@ -44,7 +44,8 @@ struct BatchReq {
     uint64_t scratch0;   // first scratch slot (multi-segment write-back)
     uint32_t dtype;      // 0 u32, 1 f32, 2 f64
     uint32_t flags;      // kReqSubstreams | kReqWriteBack
-    uint32_t spi;        // wave items: whole streams per item (segs == 1), else 1
+    uint32_t spi;        // wave items: whole streams per item (segs == 1), else 1;
+                         // row items: 64-stream blocks per item
     uint32_t pad;
 };
 
@@ -75,9 +76,21 @@ struct BatchArgs {
 };
 
 __host__ __device__ inline bool is_row(const BatchReq &R) { return R.seg == 0; }
+
+// Row items carry blocks of 64 streams until they hold about kRowItemBytes of
+// output (at most 16 blocks): an item pays its claim, request lookup and
+// descriptor load once, which for rows of a few hundred bytes cost as much as
+// writing them.
+constexpr uint64_t kRowItemBytes = 128 * 1024;
+inline uint32_t row_blocks_per_item(uint64_t n, uint64_t es)
+{
+    const uint64_t b = kRowItemBytes / (64 * n * es);
+    return (uint32_t)(b < 1 ? 1 : b > 16 ? 16 : b);
+}
+
 inline uint64_t items_of(const BatchReq &R)
 {
-    if (!R.seg) return (R.k + 63) / 64;
+    if (!R.seg) return ((R.k + 63) / 64 + R.spi - 1) / R.spi;
     return R.spi > 1 ? (R.k + R.spi - 1) / R.spi : R.k * R.segs;
 }
 

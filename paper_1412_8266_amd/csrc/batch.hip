@@ -95,11 +95,10 @@ __device__ __forceinline__ void wave_item(const BatchReq &R, uint64_t local, uns
 }
 
 template <int DT, class G>
-__device__ __forceinline__ void row_item(const BatchReq &R, uint64_t local, unsigned char *lds, int lane,
-                         const BatchArgs &A)
+__device__ __forceinline__ void row_block(const BatchReq &R, uint64_t r0, unsigned char *lds, int lane,
+                                          const BatchArgs &A)
 {
     constexpr int ES = Elem<DT>::size;
-    const uint64_t r0 = local * 64;
     const uint64_t nrows = R.k - r0 < 64 ? R.k - r0 : 64;
     const bool active = (uint64_t)lane < nrows;
     const uint64_t j = r0 + lane;
@@ -153,30 +152,48 @@ __global__ void __launch_bounds__(64, 2) batch_kernel(BatchArgs A)
     // one, so that the claim's round trip overlaps the item's own loads
     uint64_t claim = 0;
     if (A.dynamic && lane == 0) claim = atomicAdd(A.counter, 1ull);
+    // a row item's 64-stream blocks [blk, blk_end) still to write: one block
+    // per turn of the loop, a new item claimed when none is left
+    uint32_t r = 0;
+    uint64_t local = 0, blk = 0, blk_end = 0;
     for (;;) {
-        uint64_t item;
-        if (A.dynamic) {
-            item = lane0_uniform(claim);
-            if (item < A.total_items && lane == 0) claim = atomicAdd(A.counter, 1ull);
-        } else {
-            item = next;
-            next += gridDim.x;
+        if (blk == blk_end) {
+            uint64_t item;
+            if (A.dynamic) {
+                item = lane0_uniform(claim);
+                if (item < A.total_items && lane == 0) claim = atomicAdd(A.counter, 1ull);
+            } else {
+                item = next;
+                next += gridDim.x;
+            }
+            if (item >= A.total_items) break;
+            r = find_req(A.prefix, A.nreq, item, lane);
+            local = item - A.prefix[r];
+            blk = blk_end = 0;
+            if constexpr (KIND == kKindRows) {
+                const BatchReq &Q = A.reqs[r];
+                if (is_row(Q)) {
+                    const uint64_t nb = (Q.k + 63) / 64;
+                    blk = local * Q.spi;
+                    blk_end = blk + Q.spi < nb ? blk + Q.spi : nb;
+                }
+            }
         }
-        if (item >= A.total_items) break;
-        const uint32_t r = find_req(A.prefix, A.nreq, item, lane);
         const BatchReq R = A.reqs[r];
-        const uint64_t local = item - A.prefix[r];
-        if constexpr (KIND == kKindWave) {
+        if (blk < blk_end) {
+            if (R.dtype == 0) row_block<0, G>(R, blk * 64, lds, lane, A);
+            else if (R.dtype == 1) row_block<1, G>(R, blk * 64, lds, lane, A);
+            else row_block<2, G>(R, blk * 64, lds, lane, A);
+            if (++blk < blk_end) continue;
+        } else if constexpr (KIND == kKindWave) {
             wave_item<DT, G>(R, local, lds, lane, m, A);
-        } else if (!is_row(R)) {
+        } else {
             uint32_t mi[18];
 #pragma unroll
             for (int i = 0; i < 18; ++i) mi[i] = mt[i];
             wave_item<DT, G>(R, local, lds, lane, mi, A);
-        } else if (R.dtype == 0) row_item<0, G>(R, local, lds, lane, A);
-        else if (R.dtype == 1) row_item<1, G>(R, local, lds, lane, A);
-        else row_item<2, G>(R, local, lds, lane, A);
-        // no value returned: the item's end costs no round trip
+        }
+        // the item's end (no value returned: no round trip)
         if (A.req_done && lane == 0) atomicMax(&A.req_done[r], (unsigned long long)wall_clock64());
     }
 }

@@ -36,13 +36,15 @@ void group_requests(const std::vector<BatchReq> &in, Grouped *out)
             bytes[R.dtype] += R.k * R.n * (R.dtype == 2 ? 8 : 4);
         }
     }
-    // row items largest first: a row item is up to 64 whole streams on one
-    // wave (up to 64 x 16 KiB), claimed in this order; big ones left for the
-    // end would run the launch's tail alone
-    std::stable_sort(rows.begin(), rows.end(), [&](size_t a, size_t b) {
-        return std::min<uint64_t>(in[a].k, 64) * in[a].n * (in[a].dtype == 2 ? 8 : 4) >
-               std::min<uint64_t>(in[b].k, 64) * in[b].n * (in[b].dtype == 2 ? 8 : 4);
-    });
+    // row items largest first: a row item is whole streams on one wave, one
+    // per lane (up to 64 rows of wave_min_bytes), claimed in this order; big
+    // ones left for the end would run the launch's tail alone
+    auto item_bytes = [&](size_t i) {
+        const BatchReq &R = in[i];
+        return std::min<uint64_t>(R.k, 64 * (uint64_t)R.spi) * R.n * (R.dtype == 2 ? 8 : 4);
+    };
+    std::stable_sort(rows.begin(), rows.end(),
+                     [&](size_t a, size_t b) { return item_bytes(a) > item_bytes(b); });
     // wave groups with the least output first (shortest-job-first keeps the
     // completion times of most requests low; the run's end does not move)
     std::vector<int> order;
@@ -112,7 +114,7 @@ void plan_batch(const mrg_request *reqs, uint64_t n, const mrg_batch_config &cfg
         } else {
             R.seg = 0;
             R.segs = 1;
-            R.spi = 1;
+            R.spi = row_blocks_per_item(R.n, es);
         }
         P.in.push_back(R);
         P.req_of.push_back((uint32_t)i);

@@ -163,7 +163,7 @@ mrg::BatchReq to_batch_req(mrg_server s, const Req &r)
     } else {
         R.seg = 0;
         R.segs = 1;
-        R.spi = 1;
+        R.spi = mrg::row_blocks_per_item(r.n, es);
     }
     return R;
 }
