@@ -196,7 +196,8 @@ def batched(mg, wl, torch, stream, reps):
              for sb, w, sc, wm in [(256 << 10, 16, 1, 16 << 10), (1 << 20, 16, 1, 16 << 10),
                                    (256 << 10, 8, 1, 16 << 10), (1 << 20, 8, 1, 16 << 10),
                                    (64 << 10, 16, 1, 16 << 10), (256 << 10, 8, 2, 16 << 10),
-                                   (1 << 20, 16, 1, 4 << 10), (1 << 20, 16, 1, 64 << 10)]]
+                                   (1 << 20, 16, 1, 4 << 10), (1 << 20, 16, 1, 32 << 10),
+                                   (1 << 20, 16, 1, 64 << 10)]]
     t0 = time.perf_counter()
     best, cand_ms = b.autotune(cands, reps=1)
     tune_s = time.perf_counter() - t0

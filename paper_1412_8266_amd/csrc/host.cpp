@@ -581,7 +581,8 @@ mrg_status mrg_fill(mrg_streamset ss, uint64_t first, uint64_t count, uint64_t n
     mrg::FillLaunch fl;
     if (layout == MRG_STREAM_MAJOR) {
         // wave per stream when a stream fills at least one chunk of 64 lanes x
-        // 128 bytes (or when forced); lane per stream for short streams
+        // 128 bytes (or when forced; see below for rows under 16 KiB); lane per
+        // stream for short streams
         const uint64_t min_chunk = 64 * (128 / es);
         const bool coop = tune.strategy == 2 || (tune.strategy == 0 && n_per_stream >= min_chunk);
         if (coop) {
@@ -621,6 +622,14 @@ mrg_status mrg_fill(mrg_streamset ss, uint64_t first, uint64_t count, uint64_t n
             // addressable with 32-bit offsets
             fl.whole = rows_aligned && n_per_stream % ((uint64_t)GL * L) == 0 &&
                        (uint64_t)(64 / GL) * n_per_stream * es < ((uint64_t)1 << 32);
+            // automatic choice: a row under 16 KiB that is not whole chunks on
+            // lines is one cut chunk for this writer (values drawn past the
+            // row's end, one piece per flush), and the lane-per-stream writer
+            // is the faster one there (uint32 rows of 3000: 4.0-4.5 against
+            // 3.4 TB/s; of 4000: 4.2-4.4 against 3.6-3.7); from 4500 values
+            // this writer leads (4.7-4.8 against 4.0-4.5)
+            if (tune.strategy == 0 && !fl.whole && n_per_stream * es < 16 * 1024)
+                fl = mrg::FillLaunch();
         }
     }
     hipError_t e = mrg::launch_fill(ss->d_planes, ss->n, first, count, n_per_stream, (int)dtype,
