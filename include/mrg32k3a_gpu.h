@@ -536,9 +536,10 @@ mrg_status mrg_state_check(const uint32_t state6[6]);
  *                stream-major fill, 128 or 256, or 0 (default: 128 for rows
  *                shorter than 1 KiB, else 256);
  *   "strategy"   stream-major fill: 0 = automatic (default: one wave per
- *                stream when a stream has at least 16 KiB of output, or at
- *                least 64 x 128 bytes in whole chunks on 128-byte lines,
- *                else one lane per stream), 1 = always lane per stream,
+ *                stream when a stream has at least 64 x 128 bytes of output,
+ *                except rows under 16 KiB that are not whole chunks on
+ *                128-byte lines when at least 2^17 streams are filled; else
+ *                one lane per stream), 1 = always lane per stream,
  *                2 = always wave per stream;
  *   "coop_wgs_per_cu" wave-per-stream fill: one-wave workgroups per compute
  *                unit, each looping over stream groups (0 = one workgroup

@@ -624,11 +624,14 @@ mrg_status mrg_fill(mrg_streamset ss, uint64_t first, uint64_t count, uint64_t n
                        (uint64_t)(64 / GL) * n_per_stream * es < ((uint64_t)1 << 32);
             // automatic choice: a row under 16 KiB that is not whole chunks on
             // lines is one cut chunk for this writer (values drawn past the
-            // row's end, one piece per flush), and the lane-per-stream writer
-            // is the faster one there (uint32 rows of 3000: 4.0-4.5 against
-            // 3.4 TB/s; of 4000: 4.2-4.4 against 3.6-3.7); from 4500 values
-            // this writer leads (4.7-4.8 against 4.0-4.5)
-            if (tune.strategy == 0 && !fl.whole && n_per_stream * es < 16 * 1024)
+            // row's end, one piece per flush), and with enough streams to fill
+            // the chip one lane each (2048 waves of 64) the lane-per-stream
+            // writer is the faster one (uint32 rows of 3000: 4.0-4.5 against
+            // 3.4 TB/s; of 4000: 4.2-4.4 against 3.6-3.7; from 4500 values
+            // this writer leads, 4.7-4.8 against 4.0-4.5).  With fewer streams
+            // this writer's 16 lanes per stream keep the launch short.
+            if (tune.strategy == 0 && !fl.whole && n_per_stream * es < 16 * 1024 &&
+                count >= ((uint64_t)64 << 11))
                 fl = mrg::FillLaunch();
         }
     }
