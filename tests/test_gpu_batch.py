@@ -113,6 +113,49 @@ def test_plain_batch_matches_oracle(mg, name, engine):
         mg.mrg_config_set("engine", old)
 
 
+# (streams, values per stream, dtype): row requests whose items carry several
+# 64-stream blocks (short rows: up to 16 blocks, about 128 KiB of output per
+# item) with a partial last item and a partial last block, next to requests of
+# one block or less and rows long enough for one block per item.
+ROW_BLOCK_SHAPES = [(1100, 20, 0), (1100, 33, 1), (1025, 7, 2), (1, 20, 0), (63, 33, 0),
+                    (64, 100, 1), (65, 100, 0), (700, 1000, 0), (130, 700, 2), (2500, 3, 1)]
+
+
+@pytest.mark.parametrize("engine", [0, 1], ids=["int", "f64"])
+def test_row_items_in_blocks(mg, engine):
+    import torch
+    say("row blocks", engine)
+    old = mg.mrg_config_get("engine")
+    mg.mrg_config_set("engine", engine)
+    try:
+        rows, outs, specs, first = [], [], [], 0
+        for k, n, dt in ROW_BLOCK_SHAPES:
+            t = torch.empty((k, n), dtype=mg.torch_dtype(dt), device="cuda")
+            rows.append((first, k, n, 0, t.data_ptr(), dt, 0))
+            outs.append(t)
+            specs.append((first, k, n, dt))
+            first += k
+        base = oracle.seed_from_master(SEED + 7)
+        ss = mg.StreamSet(first, seed=[int(x) for x in base])
+        st0 = oracle.streams(base, 0, first)
+        # every request a row request; a few resident waves, so that waves
+        # take several items each
+        b = mg.Batch(ss, rows, mg.batch_config(wave_min_bytes=1 << 40, waves_per_cu=1))
+        b.run()
+        check_plain(base, specs, outs, st0)
+        st1 = st0.copy()
+        for f, k, n, dt in specs:
+            st1[f:f + k] = oracle.jump_many(st0[f:f + k], n)
+        assert np.array_equal(ss.get_states(), st1)
+        # the per-request launches agree
+        b.run_per_request()
+        check_plain(base, specs, outs, st1)
+        b.close()
+        ss.close()
+    finally:
+        mg.mrg_config_set("engine", old)
+
+
 def test_substream_requests(mg):
     import torch
     say("substreams")
