@@ -294,7 +294,7 @@ mrg_status mrg_set_states(mrg_streamset ss, uint64_t first, uint64_t count,
                           const uint32_t *h_in, void *stream);
 
 /* ---------------------------------------------------------------------- */
-/* Batched generation: many fill requests in one persistent launch         */
+/* Batched generation: many fill requests in one graph of persistent launches */
 /* ---------------------------------------------------------------------- */
 
 /* Request flag: the request's streams are substreams (sec. 4.1) of ONE
@@ -349,7 +349,11 @@ typedef struct mrg_batch_s *mrg_batch;
 /* Plan a batch over stream set ss: validate the requests (plain requests
  * must cover disjoint stream ranges and no substream request may name a
  * stream that a plain request advances, else MRG_EINVAL), cut them into
- * one-wave work items, group them by (dtype, item kind) and capture one
+ * one-wave work items (a segment of one stream, whole streams packed about a
+ * segment per item, or up to 16 blocks of 64 streams shorter than
+ * wave_min_bytes, one per lane), group them into at most one launch per
+ * dtype of the long streams' items, the first (least output) led by the
+ * short streams' items of every dtype, largest first, and capture one
  * hipGraph (per group a counter reset and a persistent kernel, then the
  * copy-back of end states).  Every non-empty request's d_out must be device
  * memory of the set's device holding its output inside one allocation (else
