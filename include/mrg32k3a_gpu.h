@@ -377,6 +377,28 @@ mrg_status mrg_batch_run_per_request(mrg_batch b, void *stream);
 
 mrg_status mrg_batch_info(mrg_batch b, mrg_batch_info_t *info);
 
+/* One launch group of a batch plan (mrg_batch_plan_groups). */
+typedef struct {
+    int32_t dtype;         /* dtype of the group's wave items */
+    int32_t rows;          /* 1: the group is led by the row items of every dtype */
+    uint64_t requests;     /* requests in the group */
+    uint64_t items;        /* work items */
+    uint64_t row_items;    /* of which row items (they come first) */
+    uint64_t bytes;        /* output bytes of the group's requests */
+} mrg_plan_group;
+
+/* The launch groups that mrg_batch_create would capture for these requests
+ * under cfg (NULL: defaults), computed on the host alone: no stream set,
+ * device or output memory is touched, d_out is not read, and the requests
+ * are not validated against a stream set (dtype and flags are checked).
+ * groups receives up to 3 groups in launch order (*n_groups of them); when
+ * pos is not NULL, pos[i] is input request i's index in the grouped order
+ * (items are claimed in that order; UINT64_MAX for empty requests), and
+ * when items is not NULL, items[i] its work items.  For tests and tools. */
+mrg_status mrg_batch_plan_groups(const mrg_request *reqs, uint64_t n_reqs,
+                                 const mrg_batch_config *cfg, mrg_plan_group *groups,
+                                 uint32_t *n_groups, uint64_t *pos, uint64_t *items);
+
 /* Completion time of every request in the last mrg_batch_run or
  * mrg_batch_run_direct: h_ms[i] (n_reqs doubles, host memory, input order)
  * receives the milliseconds from the earliest workgroup start of that run to

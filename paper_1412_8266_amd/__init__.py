@@ -275,9 +275,17 @@ def batch_config(segment_bytes=0, wave_min_bytes=0, waves_per_cu=0, schedule=0):
     return _abi.make_config(segment_bytes, wave_min_bytes, waves_per_cu, schedule)
 
 
+def batch_plan_groups(requests, config=None):
+    """The launch groups a Batch of these request rows would run, planned on
+    the host alone (no device, d_out not read): (groups in launch order,
+    each request's index in the grouped order, each request's work items)."""
+    rows = list(requests)
+    return _abi.mrg_batch_plan_groups(_abi.make_requests(rows), len(rows), config)
+
+
 class Batch:
-    """Many fill requests over one StreamSet run by one persistent,
-    hipGraph-captured launch.
+    """Many fill requests over one StreamSet run as one hipGraph of
+    persistent launches (batch_plan_groups shows the grouping).
 
     ``requests`` rows are (first, count, n_per_stream, substream0, d_out,
     dtype, flags); d_out is a device pointer (int) to a [count, n] array.
@@ -330,4 +338,5 @@ class Batch:
         self.close()
 
 
-__all__ += ["Batch", "batch_config", "REQ_SUBSTREAMS", "SCHEDULE_DYNAMIC", "SCHEDULE_STATIC"]
+__all__ += ["Batch", "batch_config", "batch_plan_groups", "REQ_SUBSTREAMS", "SCHEDULE_DYNAMIC",
+            "SCHEDULE_STATIC"]

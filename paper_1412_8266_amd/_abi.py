@@ -98,7 +98,16 @@ class mrg_batch_info_t(ctypes.Structure):
                 ("pad", ctypes.c_uint32), ("config", mrg_batch_config)]
 
 
+class mrg_plan_group(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("rows", ctypes.c_int32), ("requests", ctypes.c_uint64),
+                ("items", ctypes.c_uint64), ("row_items", ctypes.c_uint64),
+                ("bytes", ctypes.c_uint64)]
+
+
 _SIGS.update({
+    "mrg_batch_plan_groups": [ctypes.POINTER(mrg_request), _U64, ctypes.POINTER(mrg_batch_config),
+                              ctypes.POINTER(mrg_plan_group), ctypes.POINTER(ctypes.c_uint32),
+                              ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_uint64)],
     "mrg_batch_create": [ctypes.POINTER(_P), _P, ctypes.POINTER(mrg_request), _U64,
                          ctypes.POINTER(mrg_batch_config)],
     "mrg_batch_run": [_P, _P],
@@ -403,6 +412,19 @@ def mrg_batch_info(b: int) -> dict:
             "bytes": info.bytes, "scratch_states": info.scratch_states, "grid": info.grid,
             "segment_bytes": c.segment_bytes, "wave_min_bytes": c.wave_min_bytes,
             "waves_per_cu": c.waves_per_cu, "schedule": c.schedule}
+
+
+def mrg_batch_plan_groups(reqs, n_reqs: int, cfg=None):
+    """Host-only plan: (groups in launch order as dicts, pos, items) per input request."""
+    groups = (mrg_plan_group * 3)()
+    ng = ctypes.c_uint32()
+    pos = (ctypes.c_uint64 * max(n_reqs, 1))()
+    items = (ctypes.c_uint64 * max(n_reqs, 1))()
+    _call("mrg_batch_plan_groups", reqs, n_reqs, ctypes.byref(cfg) if cfg is not None else None,
+          groups, ctypes.byref(ng), pos, items)
+    out = [{"dtype": g.dtype, "rows": bool(g.rows), "requests": g.requests, "items": g.items,
+            "row_items": g.row_items, "bytes": g.bytes} for g in groups[:ng.value]]
+    return out, [pos[i] for i in range(n_reqs)], [items[i] for i in range(n_reqs)]
 
 
 def mrg_batch_request_times(b: int, n_reqs: int, stream: int = 0):

@@ -508,6 +508,50 @@ mrg_status mrg_batch_info(mrg_batch b, mrg_batch_info_t *info)
     return MRG_OK;
 }
 
+mrg_status mrg_batch_plan_groups(const mrg_request *reqs, uint64_t n_reqs,
+                                 const mrg_batch_config *cfg, mrg_plan_group *groups,
+                                 uint32_t *n_groups, uint64_t *pos, uint64_t *items)
+{
+    if ((!reqs && n_reqs) || !groups || !n_groups) return set_error(MRG_EINVAL, "null argument");
+    for (uint64_t i = 0; i < n_reqs; ++i) {
+        const mrg_request &q = reqs[i];
+        if (q.dtype != MRG_U32 && q.dtype != MRG_F32 && q.dtype != MRG_F64)
+            return set_error(MRG_EINVAL, "request %llu: unknown dtype %d", (unsigned long long)i,
+                             (int)q.dtype);
+        if (q.flags & ~(uint32_t)MRG_REQ_SUBSTREAMS)
+            return set_error(MRG_EINVAL, "request %llu: unknown flags", (unsigned long long)i);
+    }
+    mrg::HostPlan P;
+    mrg::plan_batch(reqs, n_reqs, mrg::batch_config(cfg), &P);
+    const mrg::Grouped &g = P.plan;
+    *n_groups = (uint32_t)g.groups.size();
+    for (size_t k = 0; k < g.groups.size(); ++k) {
+        const mrg::Grouped::Group &G = g.groups[k];
+        mrg_plan_group &o = groups[k];
+        o.dtype = G.dtype;
+        o.rows = G.kind == mrg::kKindRows ? 1 : 0;
+        o.requests = G.nreq;
+        o.items = G.items;
+        o.row_items = 0;
+        o.bytes = 0;
+        for (uint32_t r = G.req_off; r < G.req_off + G.nreq; ++r) {
+            const mrg::BatchReq &R = g.reqs[r];
+            if (mrg::is_row(R)) o.row_items += mrg::items_of(R);
+            o.bytes += R.k * R.n * (R.dtype == 2 ? 8 : 4);
+        }
+    }
+    if (pos)
+        for (uint64_t i = 0; i < n_reqs; ++i) pos[i] = UINT64_MAX;
+    if (items)
+        for (uint64_t i = 0; i < n_reqs; ++i) items[i] = 0;
+    for (size_t r = 0; r < P.req_of.size(); ++r) {
+        const uint64_t i = P.req_of[r];
+        if (pos) pos[i] = g.pos[r];
+        if (items) items[i] = mrg::items_of(P.in[r]);
+    }
+    return MRG_OK;
+}
+
 mrg_status mrg_batch_autotune(mrg_batch b, const mrg_batch_config *cands, uint32_t n_cands,
                               uint32_t reps, void *stream, uint32_t *best_out, float *ms_out)
 {
