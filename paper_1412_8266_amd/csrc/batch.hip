@@ -118,7 +118,9 @@ __device__ __forceinline__ void row_block(const BatchReq &R, uint64_t r0, unsign
         rows_fill_short<DT, G>(s.g, lds, lane, nrows, out0, R.n);
     else if ((uintptr_t)out0 % 128 || (R.n * ES) % 128)
         // rows off their lines: one write per line shared by two rows
-        rows_fill_carry<DT, 128, G>(s.g, lds, lane, nrows, out0, R.n);
+        // (dword staging only: the 16-byte variant's registers on top of the
+        // other paths of this kernel would spill)
+        rows_fill_carry_w<DT, 128, G, false>(s.g, lds, lane, nrows, out0, R.n);
     else
         rows_fill<DT, 128, G, false>(s.g, lds, lane, nrows, out0, R.n * ES, R.n);
     if ((R.flags & kReqWriteBack) && active) s.store(A.planes, A.plane_stride, R.stream0 + j);
@@ -130,11 +132,11 @@ __device__ __forceinline__ void row_block(const BatchReq &R, uint64_t r0, unsign
 // array first, as the plain fill kernels do, sends that array to scratch
 // memory inside this loop.  Wave items stage two pieces per member per flush
 // (runs of two lines per store instruction), row items one 128-byte window
-// per row and its spill (rows_fill_carry): 17 KiB of LDS per wave either way.
+// per row and its spill (rows_fill_carry): 17-18 KiB of LDS per wave.
 template <int DT, int KIND, class G>
 __global__ void __launch_bounds__(64, 2) batch_kernel(BatchArgs A)
 {
-    __shared__ __attribute__((aligned(16))) unsigned char lds[64 * 272];
+    __shared__ __attribute__((aligned(16))) unsigned char lds[64 * 288];
     const int lane = threadIdx.x;
     // wave items: the lane's A^(lane * L), L = kBatchLaneBytes of values, held
     // for the whole launch when every item is a wave item, else loaded per

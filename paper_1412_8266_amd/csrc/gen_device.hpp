@@ -281,21 +281,44 @@ __device__ __forceinline__ void rows_fill(G &g, unsigned char *lds, int lane, ui
 // lines only in part: their other bytes belong to the neighbouring waves).
 // With checked draws (GenF) a step whose sign check fails in some lane is
 // drawn again exactly from the state saved before it.  `lds` holds
-// 64 * (TB + 144) bytes.
-template <int DT, int TB, class G>
-__device__ __forceinline__ void rows_fill_carry(G &g, unsigned char *lds, int lane, uint64_t nrows,
-                                                unsigned char *out0, uint64_t n)
+// 64 * (TB + 160) bytes.
+//
+// LDS banks: lane r stages its row at byte r * RS + o_r, o_r = r * nb mod 128
+// (plus a constant), so one write step puts lane r on dword bank
+// r * (RS + nb) / 4 mod 32: with a pitch of TB + 144 bytes and rows of
+// nb / 4 = 4 mod 8 dwords that stride is a multiple of 8 dwords and up to all
+// 32 lanes hit one bank (rows of 1500 or 5500 uint32 ran at 1.8-2.0 TB/s);
+// such rows take a pitch of TB + 160.  Rows a multiple of 16 bytes long on a
+// 16-byte aligned base are staged with 16-byte writes, one per four values,
+// which with the pitch chosen so go to distinct banks; other rows with dword
+// writes (their stride is then odd or twice odd: at most two-way).
+template <int DT, int TB, class G, bool WIDE>
+__device__ __forceinline__ void rows_fill_carry_w(G &g, unsigned char *lds, int lane, uint64_t nrows,
+                                                  unsigned char *out0, uint64_t n)
 {
     constexpr int ES = Elem<DT>::size;
     constexpr int TV = TB / ES;      // values per step
-    constexpr int RS = TB + 144;     // LDS row: window + spill (< 128 bytes) + pad
     constexpr int LPR = TB / 16;     // lanes per row when writing a window
     constexpr int RPI = 64 / LPR;    // rows per store instruction
     constexpr int NJ = 64 / RPI;     // store instructions per window
     static_assert(TB % 128 == 0 && TB <= 256, "windows of whole lines");
 
     const uint64_t nb = n * ES;      // bytes per row
+    // LDS row: window + spill (< 128 bytes) + pad, its pitch by the row length
+    const uint32_t RS = (nb / 4) % 8 == 4 ? TB + 160 : TB + 144;
     unsigned char *my_lds = lds + lane * RS;
+    // 16 bytes of this lane's row into LDS at p (16-byte aligned when WIDE:
+    // every lane's staging offset o_me is then a multiple of 16 bytes)
+    auto stage16 = [](unsigned char *p, const uint4 &v) {
+        if constexpr (WIDE) {
+            *(uint4 *)p = v;
+        } else {
+            *(uint32_t *)(p) = v.x;
+            *(uint32_t *)(p + 4) = v.y;
+            *(uint32_t *)(p + 8) = v.z;
+            *(uint32_t *)(p + 12) = v.w;
+        }
+    };
     // this lane's own row: offset past its first line and its last line (in
     // line units from the first)
     const uint32_t o_me = (uint32_t)((uintptr_t)(out0 + (uint64_t)lane * nb) & 127u);
@@ -342,33 +365,17 @@ __device__ __forceinline__ void rows_fill_carry(G &g, unsigned char *lds, int la
                     const G saved = g;
                     uint32_t neg = 0;
 #pragma unroll
-                    for (int q = 0; q < TB / 16; ++q) {
-                        const uint4 v = gen16<DT>(g, neg);
-                        *(uint32_t *)(dst + q * 16) = v.x;
-                        *(uint32_t *)(dst + q * 16 + 4) = v.y;
-                        *(uint32_t *)(dst + q * 16 + 8) = v.z;
-                        *(uint32_t *)(dst + q * 16 + 12) = v.w;
-                    }
+                    for (int q = 0; q < TB / 16; ++q) stage16(dst + q * 16, gen16<DT>(g, neg));
                     if (__any((int32_t)neg < 0)) {
                         g = saved;
 #pragma unroll 1
                         for (int q = 0; q < TB / 16; ++q) {
-                            const uint4 v = gen16<DT>(g);
-                            *(uint32_t *)(dst + q * 16) = v.x;
-                            *(uint32_t *)(dst + q * 16 + 4) = v.y;
-                            *(uint32_t *)(dst + q * 16 + 8) = v.z;
-                            *(uint32_t *)(dst + q * 16 + 12) = v.w;
+                            stage16(dst + q * 16, gen16<DT>(g));
                         }
                     }
                 } else {
 #pragma unroll
-                    for (int q = 0; q < TB / 16; ++q) {
-                        const uint4 v = gen16<DT>(g);
-                        *(uint32_t *)(dst + q * 16) = v.x;
-                        *(uint32_t *)(dst + q * 16 + 4) = v.y;
-                        *(uint32_t *)(dst + q * 16 + 8) = v.z;
-                        *(uint32_t *)(dst + q * 16 + 12) = v.w;
-                    }
+                    for (int q = 0; q < TB / 16; ++q) stage16(dst + q * 16, gen16<DT>(g));
                 }
             } else {
                 // the rows' last, shorter step (the same count in every lane)
@@ -451,6 +458,18 @@ __device__ __forceinline__ void rows_fill_carry(G &g, unsigned char *lds, int la
             *(uint32_t *)(p + 4 * lane) = *(const uint32_t *)(lds + (uint32_t)rl * RS + 128 + 4 * lane);
         }
     }
+}
+
+// rows_fill_carry: rows_fill_carry_w with 16-byte staging when every row
+// starts 16-byte aligned (the base and the row length), else dword staging.
+template <int DT, int TB, class G>
+__device__ __forceinline__ void rows_fill_carry(G &g, unsigned char *lds, int lane, uint64_t nrows,
+                                                unsigned char *out0, uint64_t n)
+{
+    if ((uintptr_t)out0 % 16 == 0 && (n * Elem<DT>::size) % 16 == 0)
+        rows_fill_carry_w<DT, TB, G, true>(g, lds, lane, nrows, out0, n);
+    else
+        rows_fill_carry_w<DT, TB, G, false>(g, lds, lane, nrows, out0, n);
 }
 
 // rows_fill_short: adjacent rows shorter than a line (n * ES < 128, row r at

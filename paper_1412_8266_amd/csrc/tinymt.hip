@@ -112,7 +112,7 @@ tmt_sm_kernel(uint32_t *__restrict__ planes, uint64_t plane_stride, uint64_t fir
 {
     constexpr int ES = Elem<DT>::size;
     // TB = 0: rows off their lines, written by rows_fill_carry in 128-byte windows
-    __shared__ __attribute__((aligned(16))) unsigned char lds[64 * (TB ? TB + 16 : 128 + 144)];
+    __shared__ __attribute__((aligned(16))) unsigned char lds[64 * (TB ? TB + 16 : 128 + 160)];
     const int lane = threadIdx.x;
     const uint64_t s0 = (uint64_t)blockIdx.x * 64;
     const uint64_t nrows = count - s0 < 64 ? count - s0 : 64;
