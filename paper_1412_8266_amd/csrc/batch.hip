@@ -1,13 +1,14 @@
 // Persistent batched generation: many fill requests of uneven stream counts
-// and lengths in one launch.
+// and lengths in a few persistent launches.
 //
 // Each request is cut into work items of one wave:
 //   - a wave item is one segment [v0, v1) of one stream, written with
 //     wave_fill (lane l owns consecutive L-value pieces); the segment's first
 //     state is the stream's state jumped by v0 with the windowed tables
 //     (sequence splitting inside a stream, sec. 2.3);
-//   - a row item is up to 64 streams of a short-stream request, one per lane,
-//     written with rows_fill or rows_fill_carry.
+//   - a row item is up to 16 blocks of up to 64 streams of a short-stream
+//     request, one stream per lane, each block written with rows_fill_short,
+//     rows_fill_carry_w or rows_fill.
 // One launch per group (batch.h): wave items of one dtype, or the row items
 // of every dtype, largest first, followed by the wave items of one dtype.
 // Persistent workgroups (one wave each) claim items from a global counter or
