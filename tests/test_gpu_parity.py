@@ -503,7 +503,9 @@ def test_lane_writer_rows_off_lines(mg):
     line shared by two rows written once, from both rows' lanes): row lengths
     from one line up, offsets across a line, waves of 1 to 64 rows and
     partial last waves, every dtype, both engines, twice in a row, inside
-    guard words (the bytes around the output belong to nobody)."""
+    guard words (the bytes around the output belong to nobody).  Rows of
+    4 mod 8 dwords (the wider LDS pitch) run both on 16-byte boundaries
+    (16-byte staging) and off them."""
     import torch
     keys = ("engine", "strategy")
     old = [mg.mrg_config_get(k) for k in keys]
@@ -515,9 +517,14 @@ def test_lane_writer_rows_off_lines(mg):
                 es = 8 if dt == 2 else 4
                 lens = [128 // es, 128 // es + 1, 256 // es - 1, 256 // es, 256 // es + 1,
                         1000, 1001, 333]
-                for n in lens:
+                # (n, element offset or None for a random one): rows of 4 mod 8
+                # dwords, 16-byte aligned (offset 0) and not (offset 1)
+                cases = [(n, None) for n in lens] + [(m * 4 // es, o) for m in (44, 1500)
+                                                     for o in (0, 1)]
+                for n, off in cases:
                     count = int(rng.choice([1, 2, 63, 64, 65, 130]))
-                    off = int(rng.integers(0, 128 // es))
+                    if off is None:
+                        off = int(rng.integers(0, 128 // es))
                     for k, v in zip(keys, (engine_id, 1)):
                         mg.mrg_config_set(k, v)
                     say("rows off lines", engine_id, dt, n, count, off)
