@@ -588,10 +588,21 @@ def main():
                 break
             best = r
             k += 1
+        if best is not None and sweep and not sweep[-1]["kept_up"]:
+            # one more window halfway between the last rate kept up and the
+            # first that fell behind
+            mid = round((best["rate_per_s"] + sweep[-1]["rate_per_s"]) / 2.0 / wl.C5_RATE, 6)
+            print("[bench] serving at %g x the arrival rate" % mid, file=sys.stderr, flush=True)
+            r = serving(mg, wl, 4.0, mid)
+            sweep.insert(len(sweep) - 1, {key: r[key] for key in (
+                "rate_per_s", "offered_Gsamples_s", "served_Gsamples_s", "kept_up", "latency_ms")})
+            if r["kept_up"]:
+                best = r
         extra["serving_rate_sweep"] = sweep
+        behind = [x["rate_per_s"] for x in sweep if not x["kept_up"]]
         extra["serving_max_sustained"] = None if best is None else {
             "rate_per_s": best["rate_per_s"], "offered_Gsamples_s": best["offered_Gsamples_s"],
-            "first_rate_behind_per_s": sweep[-1]["rate_per_s"] if not sweep[-1]["kept_up"] else None}
+            "first_rate_behind_per_s": min(behind) if behind else None}
     res["extra"] = extra
 
     if not args.no_cpu and not args.quick:
